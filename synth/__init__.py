@@ -1,0 +1,118 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only draws random numbers and lays out meshes; it contains none of
+the preconditioner's arithmetic (no 1D tables, no element blocks, no SVD, no
+solves).  Both the CPU oracle and the GPU path read the arrays it returns.
+
+Element record (float64[12]), one per element:
+
+    [0] beta_x   [1] beta_y   [2] beta_z (0 in 2D)
+    [3] nu       [4] alpha    [5] phi
+    [6] tau      [7] face flag (1.0: the element's outflow-face self-terms of
+                    the upwind flux are part of its diagonal block)
+    [8..11] reserved, zero
+
+Draws (numpy PCG64 via ``default_rng``), per element in order:
+beta_x, beta_y, [beta_z], log10(nu), alpha, phi with
+beta ~ U[-1,1], log10 nu ~ U[-3,-1], alpha ~ U[0,0.5], phi ~ U[0,2pi).
+The right-hand sides are drawn after all elements: N(0,1) of shape
+(E, nrhs, n^d).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+REC_LEN = 12
+TAU = 0.1
+
+# the five workloads (element count, dim, n, rank, face terms, nrhs)
+WORKLOADS = {
+    "c1_2d_p7": dict(dim=2, n=8, mesh=16, rank=2, face=False, nrhs=1, seed=1001, rhs_seed=2001),
+    "c2_2d_p15": dict(dim=2, n=16, mesh=128, rank=2, face=False, nrhs=8, seed=1002, rhs_seed=2002),
+    "c3_3d_p7": dict(dim=3, n=8, mesh=32, rank=2, face=True, nrhs=1, seed=1003, rhs_seed=2003),
+    "c4_3d_p15": dict(dim=3, n=16, mesh=16, rank=2, face=True, nrhs=1, seed=1004, rhs_seed=2004),
+}
+MLP_TRAIN_SEED = 3004
+MLP_VAL_SEED = 4004
+MIXED_SEED = 1005
+MIXED_RHS_SEED = 2005
+
+
+def draw_params(num_elems: int, dim: int, seed: int, face: bool = False,
+                tau: float = TAU) -> np.ndarray:
+    """Per-element records, float64[E, 12], drawn in element order."""
+    if dim not in (2, 3):
+        raise ValueError("dim must be 2 or 3")
+    rng = np.random.default_rng(seed)
+    k = dim + 3  # betas, log10 nu, alpha, phi
+    u = rng.random((num_elems, k))  # row-major fill == per-element order
+    rec = np.zeros((num_elems, REC_LEN), dtype=np.float64)
+    rec[:, 0:dim] = 2.0 * u[:, 0:dim] - 1.0
+    rec[:, 3] = 10.0 ** (-3.0 + 2.0 * u[:, dim])
+    rec[:, 4] = 0.5 * u[:, dim + 1]
+    rec[:, 5] = 2.0 * np.pi * u[:, dim + 2]
+    rec[:, 6] = tau
+    rec[:, 7] = 1.0 if face else 0.0
+    return rec
+
+
+def draw_rhs(num_elems: int, nrhs: int, ndof: int, seed: int) -> np.ndarray:
+    """Right-hand sides, float64[E, nrhs, ndof], N(0,1)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((num_elems, nrhs, ndof))
+
+
+def periodic_neighbours(mesh: int, dim: int) -> np.ndarray:
+    """Face neighbours on a periodic mesh^dim grid, int32[E, 2*dim].
+
+    Elements are numbered e = (ex*M + ey)*M + ez (x slowest).  Column 2k is the
+    neighbour across the low face of axis k, column 2k+1 across the high face.
+    """
+    M = mesh
+    idx = np.arange(M ** dim).reshape((M,) * dim)
+    cols = []
+    for ax in range(dim):
+        cols.append(np.roll(idx, 1, axis=ax).ravel())   # low-face neighbour: index-1
+        cols.append(np.roll(idx, -1, axis=ax).ravel())  # high-face neighbour: index+1
+    return np.stack(cols, axis=1).astype(np.int32)
+
+
+def workload(name: str, num_elems: int | None = None):
+    """Records, neighbours and right-hand sides of a named workload.
+
+    ``num_elems`` truncates the element list (the first elements of the full
+    draw) for small test cases; neighbours are then only meaningful when the
+    full mesh is used.
+    """
+    cfg = WORKLOADS[name]
+    dim, n, M = cfg["dim"], cfg["n"], cfg["mesh"]
+    E_full = M ** dim
+    E = E_full if num_elems is None else int(num_elems)
+    rec = draw_params(E_full, dim, cfg["seed"], face=cfg["face"])[:E]
+    rhs = draw_rhs(E_full, cfg["nrhs"], n ** dim, cfg["rhs_seed"])[:E]
+    nbr = periodic_neighbours(M, dim) if E == E_full else None
+    return dict(cfg, num_elems=E, params=rec, rhs=rhs, nbr=nbr)
+
+
+def mixed_batch(n2d: int = 50000, n3d: int = 2000, seed: int = MIXED_SEED):
+    """Mixed-degree batch: 2D elements with p ~ U{3..30}, then 3D with p ~ U{3..15}.
+
+    p is drawn before each element's parameters.  Returns (dims, ns, params).
+    """
+    rng = np.random.default_rng(seed)
+    dims, ns, recs = [], [], []
+    for dim, count, pmax in ((2, n2d, 30), (3, n3d, 15)):
+        for _ in range(count):
+            p = int(rng.integers(3, pmax + 1))
+            u = rng.random(dim + 3)
+            rec = np.zeros(REC_LEN)
+            rec[0:dim] = 2.0 * u[0:dim] - 1.0
+            rec[3] = 10.0 ** (-3.0 + 2.0 * u[dim])
+            rec[4] = 0.5 * u[dim + 1]
+            rec[5] = 2.0 * np.pi * u[dim + 2]
+            rec[6] = TAU
+            dims.append(dim)
+            ns.append(p + 1)
+            recs.append(rec)
+    return (np.asarray(dims, np.int8), np.asarray(ns, np.int16),
+            np.asarray(recs, np.float64))
