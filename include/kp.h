@@ -1,0 +1,175 @@
+/*
+ * kp.h -- C ABI of the KSVD tensor-product block-Jacobi preconditioner for
+ * very high order DG (Pazner & Persson, arXiv 1704.04549) on AMD MI355X.
+ *
+ * The preconditioner approximates each element's n^d x n^d diagonal block A_k
+ * of M - tau*J (Sec. 3.3) by a short Kronecker sum of n x n factors
+ * (eqs. 2d-kron-sum, 3d-simple-precond), found with the Van Loan rearrangement
+ * and a top-r SVD computed by Lanczos (Sec. 4.1, Alg. 2), and inverts that sum
+ * with sum-factorised n x n contractions plus a quasi-triangular Sylvester
+ * solve (Sec. 4.2-4.4, Algs. 5-8).  n = p + 1 nodes per direction.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array arguments are DEVICE pointers unless the name ends in _h.
+ * - The caller owns every buffer it passes; the library owns only the
+ *   workspace held by a kp_ctx (allocated on first need, grown on demand,
+ *   freed by kp_destroy).
+ * - Work is enqueued on the context's HIP stream; only kp_fgmres and
+ *   kp_blockjacobi_exact synchronise (kp_fgmres once per Arnoldi step to read
+ *   the Givens residual, kp_blockjacobi_exact never except on error).
+ * - Nodal vectors are C-ordered with x slowest: u[(i*n + j)*n + k].  The
+ *   first Kronecker factor acts on x.
+ * - Argument errors (null pointers, n outside [2,32], dim not 2 or 3, rank
+ *   not supported) return KP_ERR_ARG and write nothing.  HIP runtime errors
+ *   return KP_ERR_HIP.  Per-element numerical trouble is reported in
+ *   elem_status (bit flags KP_ELEM_*) and is not an error of the call.
+ *   No C++ exception crosses this interface.
+ */
+#ifndef KP_H
+#define KP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kp_ctx_s* kp_ctx;
+
+typedef enum {
+    KP_OK = 0,
+    KP_ERR_ARG = 1,
+    KP_ERR_ALLOC = 2,
+    KP_ERR_HIP = 3,
+    KP_ERR_NUMERIC = 4,
+    KP_ERR_NOCONV = 5,
+    KP_ERR_UNSUPPORTED = 6
+} kp_status;
+
+/* Arithmetic of the apply.  KP_BF16: bf16 operands, FP32 accumulation.
+ * KP_BF16X3: every operand split as hi + lo bf16 numbers and each product
+ * formed from the three terms hi*hi + hi*lo + lo*hi with FP32 accumulation
+ * (about 16 significant bits at the bf16 matrix-core rate). */
+typedef enum { KP_FP64 = 0, KP_FP32 = 1, KP_BF16 = 2, KP_BF16X3 = 3 } kp_prec;
+
+/* setup modes for kp_setup */
+typedef enum { KP_SETUP_SVD = 0, KP_SETUP_LEARNED = 1 } kp_setup_mode;
+
+/* preconditioner kinds for kp_fgmres */
+typedef enum { KP_PC_NONE = 0, KP_PC_KSVD = 1, KP_PC_BJ = 2 } kp_pc_kind;
+
+/* per-element status bits */
+#define KP_ELEM_OK 0
+#define KP_ELEM_LANCZOS_NOCONV 1    /* Lanczos hit its step limit; best Ritz triplets used */
+#define KP_ELEM_SINGULAR_FACTOR 2   /* a factor to invert had a zero pivot */
+#define KP_ELEM_SCHUR_NOCONV 4      /* Francis QR did not converge */
+#define KP_ELEM_NONFINITE 8         /* NaN/Inf in the element's data or results */
+#define KP_ELEM_LEARNED_REJECTED 16 /* learned factors failed the acceptance test */
+#define KP_ELEM_LEARNED_WARM 32     /* learned factors used as the Lanczos start */
+
+#define KP_REC_LEN 12
+
+/*
+ * A batch of elements of one dimension and one degree.
+ *   params : [E][12] element records (always required).  Record layout:
+ *            beta_x, beta_y, beta_z, nu, alpha, phi, tau, face, 0, 0, 0, 0.
+ *            The block of element k is (Sec. 3.3, Table 1, eq. adv-kron, with
+ *            collocated Gauss-Legendre quadrature on [0,1]^d):
+ *              diag(w (x) w [(x) w] * c) + tau * sum_axes (beta S + nu K) on
+ *              that axis (x) W on the others, c = 1 + alpha sin(pi x y [z] + phi),
+ *            plus, if face != 0, the upwind outflow self-term
+ *              tau*|beta| * l l^T on each axis (l = l(1) if beta < 0, l(0) if
+ *              beta > 0) (x) W on the others.
+ *   blocks : [E][n^d][n^d] explicit blocks, row-major, or NULL.  When NULL the
+ *            setup and the operator are matrix-free from params.
+ *   nbr    : [E][2*dim] face neighbours (low, high per axis), or NULL.  Used
+ *            only by kp_operator_apply and kp_fgmres for the upwind coupling.
+ */
+typedef struct {
+    int64_t num_elems;
+    int32_t dim;
+    int32_t n;
+    const double* params;
+    const double* blocks;
+    const int32_t* nbr;
+} kp_batch;
+
+/* Context bound to one device and one HIP stream (hipStream_t passed as void*;
+ * NULL means the default stream). */
+kp_status kp_create(kp_ctx* ctx, int device, void* stream);
+kp_status kp_destroy(kp_ctx ctx);
+kp_status kp_set_stream(kp_ctx ctx, void* stream);
+const char* kp_status_string(kp_status s);
+
+/* Bytes of the opaque preconditioner buffer for a batch and rank.
+ * rank: 2D: 1, 2 or 3; 3D: 2 (the two-stage form of Sec. 4.3.1).  Returns 0
+ * for an unsupported combination.  The buffer holds, per element, the
+ * singular values, the Kronecker factors in FP64 and the apply tables in
+ * FP64, FP32 and BF16; kp_get_factors reads the factors back. */
+size_t kp_precond_bytes(int32_t dim, int32_t n, int32_t rank, int64_t num_elems);
+
+/* S1: materialise the explicit blocks of a batch from its records
+ * (out: [E][n^d][n^d] row-major FP64). */
+kp_status kp_build_blocks(kp_ctx ctx, const kp_batch* b, double* out);
+
+/* S2-S5: form the preconditioner (Alg. 5 in 2D, Alg. 7 in 3D).
+ * Lanczos (Alg. 2, full reorthogonalisation) on the rearranged block R(A_k)
+ * through matrix-free products (explicit blocks when b->blocks != NULL,
+ * otherwise the sum-factorised products of Sec. 4.2.1 / 4.3.2 from the
+ * records), factors vec(A_j) = sqrt(sigma_j) u_j, vec(B_j) = sqrt(sigma_j) v_j,
+ * then LU inverses and real Schur forms in FP64 and the apply tables.
+ * mode KP_SETUP_LEARNED needs a model loaded with kp_mlp_load and is only
+ * valid for dim 3; it falls back to SVD per element (KP_ELEM_LEARNED_*).
+ * precond: kp_precond_bytes bytes.  elem_status: [E] int32, or NULL. */
+kp_status kp_setup(kp_ctx ctx, const kp_batch* b, int32_t rank, int32_t mode,
+                   void* precond, int32_t* elem_status);
+
+/* S5 only: build the apply tables from given Kronecker factors
+ * (factors: [E][nf][n][n] FP64, 2D rank r: A1,B1,A2,B2,...; 3D: A1,B1,C1,B2,C2). */
+kp_status kp_setup_from_factors(kp_ctx ctx, const kp_batch* b, int32_t rank,
+                                const double* factors, void* precond, int32_t* elem_status);
+
+/* Copy the factors ([E][nf][n][n]) and singular values ([E][4]: 2D sigma_1..r;
+ * 3D sigma_1 of stage 1, then sigma_1, sigma_2 of stage 2) out of a
+ * preconditioner buffer.  Either output may be NULL. */
+kp_status kp_get_factors(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* precond,
+                         double* factors, double* sigma);
+
+/* S6: z = P^{-1} r per element (Alg. 6 in 2D, Alg. 8 in 3D) for nrhs
+ * right-hand sides.  r, z: [E][nrhs][n^d] FP64.  prec selects the arithmetic
+ * of the contractions and the Sylvester solve (FP64, FP32, or BF16 operands
+ * with FP32 accumulation).  2D rank 3 is solved by an inner Krylov iteration
+ * on the three-term sum preconditioned by the rank-2 inverse. */
+kp_status kp_apply(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* precond,
+                   int32_t prec, int32_t nrhs, const double* r, double* z);
+
+/* S7: exact block Jacobi.  Factor every explicit block by LU with partial
+ * pivoting (lu: [E][N][N], piv: [E][N], N = n^d), then solve. */
+kp_status kp_blockjacobi_exact(kp_ctx ctx, const kp_batch* b, double* lu, int32_t* piv,
+                               int32_t* elem_status);
+kp_status kp_blockjacobi_solve(kp_ctx ctx, const kp_batch* b, const double* lu,
+                               const int32_t* piv, int32_t nrhs, const double* r, double* z);
+
+/* S8: y = G x for the global operator: diagonal blocks (explicit or
+ * matrix-free) plus the upwind inflow coupling through nbr. x, y: [E][n^d]. */
+kp_status kp_operator_apply(kp_ctx ctx, const kp_batch* b, const double* x, double* y);
+
+/* S9: FGMRES(restart) on G x = b from x = 0, right preconditioned by
+ * pc_kind (KSVD with pc_data = precond buffer and pc_prec, or BJ with
+ * pc_data = lu buffer, its pivots following it at offset E*N*N doubles).
+ * Stops when the residual estimate is <= rtol*||b|| and the true residual
+ * confirms it, or after maxit Arnoldi steps (then KP_ERR_NOCONV, x holds the
+ * last iterate).  iters_h, relres_h: host outputs; hist_h: host array of
+ * hist_len relative residual estimates (may be NULL). */
+kp_status kp_fgmres(kp_ctx ctx, const kp_batch* b, int32_t pc_kind, int32_t rank,
+                    const void* pc_data, int32_t pc_prec, const double* rhs, double* x,
+                    int32_t restart, double rtol, int32_t maxit, int32_t* iters_h,
+                    double* relres_h, double* hist_h, int32_t hist_len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KP_H */

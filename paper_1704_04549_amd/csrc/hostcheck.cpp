@@ -1,0 +1,106 @@
+// Host build of the per-element routines of elem_ops.h with a one-thread team.
+//
+// This library exists only so the CPU test suite can check the arithmetic the
+// GPU kernels run (same source, same operation order within each thread)
+// without a GPU.  The product library (libkp.so) neither links nor loads it.
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "elem_ops.h"
+#include "tables.h"
+
+using namespace kp;
+
+extern "C" {
+
+int kph_make_tables(int n, double* x, double* w, double* D, double* S, double* K, double* l0,
+                    double* l1) {
+    Tables1D t;
+    if (!make_tables(n, &t)) return 1;
+    memcpy(x, t.x, n * sizeof(double));
+    memcpy(w, t.w, n * sizeof(double));
+    memcpy(l0, t.l0, n * sizeof(double));
+    memcpy(l1, t.l1, n * sizeof(double));
+    memcpy(D, t.D, n * n * sizeof(double));
+    memcpy(S, t.S, n * n * sizeof(double));
+    memcpy(K, t.K, n * n * sizeof(double));
+    return 0;
+}
+
+int kph_block(int dim, int n, const double* rec, double* out) {
+    Tables1D t;
+    if (!make_tables(n, &t)) return 1;
+    HostTeam tm;
+    const long nd = dim == 2 ? n * n : n * n * n;
+    std::vector<double> mass(nd), Xax(3 * n * n);
+    record_structure(tm, rec, t, dim, mass.data(), Xax.data());
+    for (long I = 0; I < nd; ++I)
+        for (long J = 0; J < nd; ++J) out[I * nd + J] = block_entry(dim, n, I, J, mass.data(), Xax.data(), t.w);
+    return 0;
+}
+
+int kph_setup(int dim, int n, int rank, const double* rec, const double* block, const double* guess,
+              double* factors, double* sigma, int* steps) {
+    Tables1D t;
+    if (!make_tables(n, &t)) return -1;
+    HostTeam tm;
+    const bool expl = block != nullptr;
+    std::vector<double> ws(setup_work_doubles(dim, n, expl) + 64, 0.0);
+    SetupWork W = carve_setup_work(ws.data(), dim, n, expl);
+    int st = setup_element(tm, dim, n, rank, t, rec, block, guess, factors, sigma, W);
+    if (steps) *steps = W.L.ctrl[1];
+    return st;
+}
+
+int kph_form_tables(int dim, int n, int rank, const double* factors, double* tab, int8_t* kinds) {
+    HostTeam tm;
+    std::vector<double> work(10 * n * n + 64);
+    std::vector<int> piv(n + 1);
+    double sh[kMaxN + 8];
+    return form_tables(tm, dim, n, rank, factors, tab, tab + 7L * n * n, kinds, work.data(), piv.data(), sh);
+}
+
+// prec 0: FP64; 1: FP32; 2: BF16 operands with FP32 accumulation
+int kph_apply(int dim, int n, int prec, const double* tab, const int8_t* kinds, const double* r,
+              double* z) {
+    HostTeam tm;
+    const long nd = dim == 2 ? n * n : n * n * n;
+    const long ne = tab_entries(n);
+    if (prec == 0) {
+        std::vector<double> X(r, r + nd), Y(nd), H(2 * nd);
+        apply_tensor(tm, dim, n, tab, kinds, X.data(), Y.data(), H.data(), RoundNone());
+        memcpy(z, X.data(), nd * sizeof(double));
+    } else if (prec == 1) {
+        std::vector<float> tf(ne), X(nd), Y(nd), H(2 * nd);
+        for (long i = 0; i < ne; ++i) tf[i] = (float)tab[i];
+        for (long i = 0; i < nd; ++i) X[i] = (float)r[i];
+        apply_tensor(tm, dim, n, tf.data(), kinds, X.data(), Y.data(), H.data(), RoundNone());
+        for (long i = 0; i < nd; ++i) z[i] = X[i];
+    } else if (prec == 3) {
+        std::vector<float> tf(ne), X(nd), Y(nd), H(2 * nd);
+        RoundBf16x2 rx;
+        for (long i = 0; i < ne; ++i) tf[i] = rx((float)tab[i]);
+        for (long i = 0; i < nd; ++i) X[i] = (float)r[i];
+        apply_tensor(tm, dim, n, tf.data(), kinds, X.data(), Y.data(), H.data(), rx);
+        for (long i = 0; i < nd; ++i) z[i] = X[i];
+    } else {
+        std::vector<uint16_t> tb(ne);
+        std::vector<float> X(nd), Y(nd), H(2 * nd);
+        for (long i = 0; i < ne; ++i) tb[i] = f32_to_bf16((float)tab[i]);
+        for (long i = 0; i < nd; ++i) X[i] = (float)r[i];
+        apply_tensor(tm, dim, n, tb.data(), kinds, X.data(), Y.data(), H.data(), RoundBf16());
+        for (long i = 0; i < nd; ++i) z[i] = X[i];
+    }
+    return 0;
+}
+
+int kph_schur(int n, const double* C, double* T, double* Q) {
+    HostTeam tm;
+    double sh[kMaxN + 8];
+    memcpy(T, C, n * n * sizeof(double));
+    return real_schur(tm, n, T, Q, sh) ? 0 : 1;
+}
+
+}  // extern "C"

@@ -1,0 +1,33 @@
+// Launchers of the HIP kernels (kernels.hip, apply_mfma.hip, krylov.hip),
+// called by the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tables.h"
+
+namespace kp {
+
+hipError_t launch_build_blocks(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                               const double* params, double* out);
+hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int rank,
+                        const Tables1D* tab, const double* params, const double* blocks,
+                        const double* guess, double* factors, double* sigma, int32_t* status,
+                        double* ws, int64_t ws_stride);
+// LDS budget of the table kernel; above it the 10 n^2 work doubles go to
+// global memory (kFormTablesGlobalSlots slots of 10 n^2 doubles, see
+// form_tables_gwork_doubles)
+constexpr size_t kFormTablesLdsMax = 150 * 1024;
+constexpr int kFormTablesGlobalSlots = 2048;
+inline long form_tables_gwork_doubles(int n) { return (long)kFormTablesGlobalSlots * 10 * n * n; }
+hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank,
+                              const double* factors, double* tab64, int8_t* kinds,
+                              int32_t* status, double* gwork);
+hipError_t launch_cast_tables(hipStream_t s, int64_t count, const double* t64, float* t32,
+                              uint16_t* hi, uint16_t* lo, float* t2);
+hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
+                                const void* tabs, int64_t tab_stride, const int8_t* kinds,
+                                const double* r, double* z);
+
+}  // namespace kp

@@ -1,0 +1,213 @@
+// HIP kernels of the KSVD preconditioner for gfx950.
+//
+// Setup kernels run one element per workgroup with the team routines of
+// elem_ops.h; the hot apply kernels for n = 16 live in apply_mfma.hip.
+#include <hip/hip_runtime.h>
+
+#include "elem_ops.h"
+#include "kernels.h"
+
+namespace kp {
+
+// ------------------------------------------------------------ S1: blocks
+// One workgroup per element: structure in LDS, then every entry of the
+// n^d x n^d block, row by row (coalesced stores).
+__global__ void __launch_bounds__(256) k_build_blocks(int64_t E, int dim, int n, const Tables1D* tab,
+                                                      const double* params, double* out) {
+    extern __shared__ double lds[];
+    __shared__ double red[8 * kMaxReduce];
+    BlockTeam tm{red};
+    const long nd = dim == 2 ? n * n : n * n * n;
+    double* mass = lds;
+    double* Xax = lds + nd;
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        record_structure(tm, params + e * kRecLen, *tab, dim, mass, Xax);
+        double* A = out + e * nd * nd;
+        for (long t = threadIdx.x; t < nd * nd; t += blockDim.x)
+            A[t] = block_entry(dim, n, t / nd, t % nd, mass, Xax, tab->w);
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------- S2-S4: setup
+// Persistent grid: workgroup g handles elements g, g + G, ... with its own
+// workspace slot.  Team = whole workgroup (256 threads).
+__global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int rank,
+                                               const Tables1D* tab, const double* params,
+                                               const double* blocks, const double* guess,
+                                               double* factors, double* sigma, int32_t* status,
+                                               double* ws, int64_t ws_stride) {
+    __shared__ double red[4 * kMaxReduce];
+    __shared__ Tables1D T;
+    BlockTeam tm{red};
+    // copy the tables once into LDS
+    {
+        const double* src = (const double*)tab;
+        double* dst = (double*)&T;
+        for (int i = threadIdx.x; i < (int)(sizeof(Tables1D) / sizeof(double)); i += blockDim.x)
+            dst[i] = src[i];
+        __syncthreads();
+    }
+    const bool expl = blocks != nullptr;
+    SetupWork W = carve_setup_work(ws + blockIdx.x * ws_stride, dim, n, expl);
+    const long nn = (long)n * n;
+    const long nd = dim == 2 ? nn : nn * n;
+    const int nf = dim == 2 ? 2 * rank : 5;
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        const double* blk = expl ? blocks + e * nd * nd : nullptr;
+        const double* g = guess ? guess + e * nn : nullptr;
+        int st = setup_element(tm, dim, n, rank, T, params + e * kRecLen, blk, g,
+                               factors + e * nf * nn, sigma + e * 4, W);
+        if (threadIdx.x == 0) status[e] = st;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------- S5: apply tables
+// One wave per element; matrices in LDS (factors, the first seven tables and
+// the work arrays); the N_j are written straight to global memory.
+__global__ void __launch_bounds__(64) k_form_tables(int64_t E, int dim, int n, int rank,
+                                                    const double* factors, double* tab64,
+                                                    int8_t* kinds, int32_t* status, double* gwork) {
+    extern __shared__ double lds[];
+    __shared__ double red[kMaxReduce];
+    __shared__ double sh[kMaxN + 8];
+    __shared__ int ipiv[kMaxN];
+    BlockTeam tm{red};
+    const long nn = (long)n * n;
+    const int nf = dim == 2 ? 2 * rank : 5;
+    const long ne = tab_entries(n);
+    double* F = lds;                 // nf n^2
+    double* tl = F + nf * nn;        // 7 n^2 (first seven tables)
+    // 10 n^2 work doubles: in LDS when they fit, else in a global slot per workgroup
+    double* work = gwork ? gwork + blockIdx.x * 10 * nn : tl + 7 * nn;
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        for (long t = threadIdx.x; t < nf * nn; t += blockDim.x) F[t] = factors[e * nf * nn + t];
+        __syncthreads();
+        double* out = tab64 + e * ne;
+        // the seven n x n tables are formed in LDS, the N_j straight in global memory
+        int st = form_tables(tm, dim, n, rank, F, tl, out + 7 * nn, kinds + e * kMaxN, work, ipiv,
+                             sh);
+        for (long t = threadIdx.x; t < 7 * nn; t += blockDim.x) out[t] = tl[t];
+        if (threadIdx.x == 0) status[e] |= st;
+        __syncthreads();
+    }
+}
+
+// FP32 and split-BF16 copies of the FP64 tables: hi = bf16(f), lo = bf16(f - hi),
+// and their sum hi + lo as a float (the value the split operands carry)
+__global__ void k_cast_tables(int64_t count, const double* t64, float* t32, uint16_t* hi,
+                              uint16_t* lo, float* t2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = t64[i];
+        const float f = (float)v;
+        t32[i] = f;
+        const uint16_t h = f32_to_bf16(f);
+        const uint16_t l = f32_to_bf16(f - bf16_to_f32(h));
+        hi[i] = h;
+        lo[i] = l;
+        t2[i] = bf16_to_f32(h) + bf16_to_f32(l);
+    }
+}
+
+// ---------------------------------------------------- S6: generic apply
+// One workgroup per (element, rhs); tensor in LDS, tables read from global.
+template <typename T, typename TT, class Rnd>
+__global__ void __launch_bounds__(256) k_apply_generic(int64_t E, int dim, int n, int nrhs,
+                                                       const TT* tabs, int64_t tab_stride,
+                                                       const int8_t* kinds, const double* r,
+                                                       double* z, Rnd rnd) {
+    extern __shared__ double lds[];
+    __shared__ double red[4 * kMaxReduce];
+    BlockTeam tm{red};
+    const long nd = dim == 2 ? n * n : n * n * n;
+    T* X = (T*)lds;
+    T* Y = X + nd;
+    T* H = Y + nd;
+    for (int64_t w = blockIdx.x; w < E * nrhs; w += gridDim.x) {
+        const int64_t e = w / nrhs;
+        for (long t = threadIdx.x; t < nd; t += blockDim.x) X[t] = (T)r[w * nd + t];
+        __syncthreads();
+        apply_tensor(tm, dim, n, tabs + e * tab_stride, kinds + e * kMaxN, X, Y, H, rnd);
+        for (long t = threadIdx.x; t < nd; t += blockDim.x) z[w * nd + t] = (double)X[t];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------- host-side launchers
+hipError_t launch_build_blocks(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                               const double* params, double* out) {
+    const long nd = dim == 2 ? n * n : n * n * n;
+    size_t lds = (nd + 3 * n * n) * sizeof(double);
+    int grid = (int)(E < 65536 ? E : 65536);
+    hipLaunchKernelGGL(k_build_blocks, dim3(grid), dim3(256), lds, s, E, dim, n, tab, params, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int rank,
+                        const Tables1D* tab, const double* params, const double* blocks,
+                        const double* guess, double* factors, double* sigma, int32_t* status,
+                        double* ws, int64_t ws_stride) {
+    hipLaunchKernelGGL(k_setup, dim3(grid), dim3(256), 0, s, E, dim, n, rank, tab, params, blocks,
+                       guess, factors, sigma, status, ws, ws_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank,
+                              const double* factors, double* tab64, int8_t* kinds,
+                              int32_t* status, double* gwork) {
+    const long nn = (long)n * n;
+    const int nf = dim == 2 ? 2 * rank : 5;
+    int grid = (int)(E < 65536 ? E : 65536);
+    size_t lds = (nf + 17) * nn * sizeof(double);
+    if (lds > kFormTablesLdsMax) {
+        if (!gwork) return hipErrorInvalidValue;
+        lds = (nf + 7) * nn * sizeof(double);
+        if (grid > kFormTablesGlobalSlots) grid = kFormTablesGlobalSlots;
+    } else {
+        gwork = nullptr;
+    }
+    hipLaunchKernelGGL(k_form_tables, dim3(grid), dim3(64), lds, s, E, dim, n, rank, factors, tab64,
+                       kinds, status, gwork);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_tables(hipStream_t s, int64_t count, const double* t64, float* t32,
+                              uint16_t* hi, uint16_t* lo, float* t2) {
+    int grid = (int)((count + 255) / 256);
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_cast_tables, dim3(grid), dim3(256), 0, s, count, t64, t32, hi, lo, t2);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
+                                const void* tabs, int64_t tab_stride, const int8_t* kinds,
+                                const double* r, double* z) {
+    const long nd = dim == 2 ? n * n : n * n * n;
+    int64_t work = E * nrhs;
+    int grid = (int)(work < 65536 ? work : 65536);
+    if (prec == 0) {
+        size_t lds = 4 * nd * sizeof(double);
+        hipLaunchKernelGGL((k_apply_generic<double, double, RoundNone>), dim3(grid), dim3(256), lds, s,
+                           E, dim, n, nrhs, (const double*)tabs, tab_stride, kinds, r, z, RoundNone());
+    } else if (prec == 1) {
+        size_t lds = 4 * nd * sizeof(float);
+        hipLaunchKernelGGL((k_apply_generic<float, float, RoundNone>), dim3(grid), dim3(256), lds, s,
+                           E, dim, n, nrhs, (const float*)tabs, tab_stride, kinds, r, z, RoundNone());
+    } else if (prec == 2) {
+        size_t lds = 4 * nd * sizeof(float);
+        hipLaunchKernelGGL((k_apply_generic<float, uint16_t, RoundBf16>), dim3(grid), dim3(256), lds,
+                           s, E, dim, n, nrhs, (const uint16_t*)tabs, tab_stride, kinds, r, z,
+                           RoundBf16());
+    } else {
+        size_t lds = 4 * nd * sizeof(float);
+        hipLaunchKernelGGL((k_apply_generic<float, float, RoundBf16x2>), dim3(grid), dim3(256), lds,
+                           s, E, dim, n, nrhs, (const float*)tabs, tab_stride, kinds, r, z,
+                           RoundBf16x2());
+    }
+    return hipGetLastError();
+}
+
+}  // namespace kp

@@ -1,0 +1,122 @@
+// Common definitions for the KSVD preconditioner library.
+//
+// The per-element numerical routines (elem_ops.h) are written once against a
+// small "team" interface: a group of cooperating threads with a barrier and
+// deterministic sum reductions.  On the GPU a team is one workgroup; the same
+// source also builds for the host with a one-thread team, which the CPU test
+// suite uses to check the arithmetic without a GPU.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define KP_HD __host__ __device__
+#define KP_DEV __device__
+#define KP_INLINE __host__ __device__ inline
+#else
+#define KP_HD
+#define KP_DEV
+#define KP_INLINE inline
+#endif
+
+namespace kp {
+
+constexpr int kRecLen = 12;
+constexpr int kMaxN = 32;
+
+// ---------------------------------------------------------------- host team
+struct HostTeam {
+    int tid() const { return 0; }
+    int size() const { return 1; }
+    void sync() const {}
+    double sum(double v) const { return v; }
+    // reduce k partial sums in place (v[0..k)); identity on one thread
+    void sum_many(double* /*v*/, int /*k*/) const {}
+    bool leader() const { return true; }
+    // out[j] = sum_i Q[j*ldq + i] * v[i] for j < k
+    void dots(const double* Q, long ldq, int k, const double* v, int len, double* out) const {
+        for (int j = 0; j < k; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < len; ++i) s += Q[j * ldq + i] * v[i];
+            out[j] = s;
+        }
+    }
+};
+
+#if defined(__HIPCC__)
+// ----------------------------------------------------------- workgroup team
+// scratch: LDS array of at least (blockDim.x/64) * kMaxReduce doubles.
+constexpr int kMaxReduce = 72;
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+struct BlockTeam {
+    double* scratch;
+    __device__ int tid() const { return (int)threadIdx.x; }
+    __device__ int size() const { return (int)blockDim.x; }
+    __device__ void sync() const { __syncthreads(); }
+    __device__ bool leader() const { return threadIdx.x == 0; }
+    __device__ double sum(double v) const {
+        const int nw = (int)(blockDim.x >> 6);
+        v = wave_sum(v);
+        if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += scratch[w];
+        __syncthreads();
+        return s;
+    }
+    // out[j] = sum_i Q[j*ldq + i] * v[i] for j < k; one wave per dot product,
+    // fixed summation order; out is visible to the whole team on return
+    __device__ void dots(const double* Q, long ldq, int k, const double* v, int len,
+                         double* out) const {
+        const int nw = (int)(blockDim.x >> 6);
+        const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+        for (int j = w; j < k; j += nw) {
+            double s = 0.0;
+            for (int i = lane; i < len; i += 64) s += Q[j * ldq + i] * v[i];
+            s = wave_sum(s);
+            if (lane == 0) out[j] = s;
+        }
+        __syncthreads();
+    }
+    // v[0..k) hold per-thread partials on entry and the team sums on exit
+    __device__ void sum_many(double* v, int k) const {
+        const int nw = (int)(blockDim.x >> 6);
+        const int w = (int)(threadIdx.x >> 6);
+        for (int i = 0; i < k; ++i) {
+            double t = wave_sum(v[i]);
+            if ((threadIdx.x & 63) == 0) scratch[i * nw + w] = t;
+        }
+        __syncthreads();
+        for (int i = 0; i < k; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < nw; ++j) s += scratch[i * nw + j];
+            v[i] = s;
+        }
+        __syncthreads();
+    }
+};
+#endif
+
+// bf16 <-> f32 (round to nearest even), host and device
+KP_INLINE uint16_t f32_to_bf16(float f) {
+    union { float f; uint32_t u; } c;
+    c.f = f;
+    uint32_t u = c.u;
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+KP_INLINE float bf16_to_f32(uint16_t h) {
+    union { float f; uint32_t u; } c;
+    c.u = ((uint32_t)h) << 16;
+    return c.f;
+}
+
+}  // namespace kp

@@ -1,0 +1,240 @@
+"""Python binding of the libkp C ABI (include/kp.h): argument marshalling only.
+
+Every entry point keeps its C name and order of arguments; device buffers are
+passed as torch tensors on the context's device (their data pointers are
+handed to the library).  All numerical work runs in the HIP kernels of
+libkp.so; this module raises if the library is missing and has no CPU path.
+A non-OK status raises ``KpError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkp.so")
+
+KP_OK, KP_ERR_ARG, KP_ERR_ALLOC, KP_ERR_HIP, KP_ERR_NUMERIC, KP_ERR_NOCONV, KP_ERR_UNSUPPORTED = range(7)
+KP_FP64, KP_FP32, KP_BF16, KP_BF16X3 = 0, 1, 2, 3
+KP_SETUP_SVD, KP_SETUP_LEARNED = 0, 1
+KP_PC_NONE, KP_PC_KSVD, KP_PC_BJ = 0, 1, 2
+ELEM_LANCZOS_NOCONV, ELEM_SINGULAR_FACTOR, ELEM_SCHUR_NOCONV, ELEM_NONFINITE = 1, 2, 4, 8
+ELEM_LEARNED_REJECTED, ELEM_LEARNED_WARM = 16, 32
+REC_LEN = 12
+PREC = {"fp64": KP_FP64, "fp32": KP_FP32, "bf16": KP_BF16, "bf16x3": KP_BF16X3}
+
+
+class KpError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} (status {status})")
+        self.status = status
+
+
+class kp_batch(ctypes.Structure):
+    _fields_ = [("num_elems", ctypes.c_int64), ("dim", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("params", ctypes.c_void_p), ("blocks", ctypes.c_void_p), ("nbr", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libkp.so (built by paper_1704_04549_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libkp.so not built ({LIB_PATH}); run paper_1704_04549_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        bp = ctypes.POINTER(kp_batch)
+        sig = {
+            "kp_create": ([ctypes.POINTER(vp), ctypes.c_int, vp], ctypes.c_int),
+            "kp_destroy": ([vp], ctypes.c_int),
+            "kp_set_stream": ([vp, vp], ctypes.c_int),
+            "kp_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "kp_precond_bytes": ([i32, i32, i32, i64], ctypes.c_size_t),
+            "kp_build_blocks": ([vp, bp, vp], ctypes.c_int),
+            "kp_setup": ([vp, bp, i32, i32, vp, vp], ctypes.c_int),
+            "kp_setup_from_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
+            "kp_get_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
+            "kp_apply": ([vp, bp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
+            "kp_blockjacobi_exact": ([vp, bp, vp, vp, vp], ctypes.c_int),
+            "kp_blockjacobi_solve": ([vp, bp, vp, vp, i32, vp, vp], ctypes.c_int),
+            "kp_operator_apply": ([vp, bp, vp, vp], ctypes.c_int),
+            "kp_fgmres": ([vp, bp, i32, i32, vp, i32, vp, vp, i32, dbl, i32,
+                           ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, i32], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().kp_status_string(int(status)).decode()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if t.device.type != "cuda":
+            raise ValueError("device tensor expected")
+        if not t.is_contiguous():
+            raise ValueError("contiguous tensor expected")
+        return ctypes.c_void_p(t.data_ptr())
+    return t
+
+
+def _check(status, what):
+    if status != KP_OK:
+        raise KpError(status, what)
+
+
+class Batch:
+    """A uniform batch (one dim, one n); holds references to its tensors."""
+
+    def __init__(self, params: torch.Tensor, dim: int, n: int, blocks=None, nbr=None):
+        if params.dtype != torch.float64 or params.shape[-1] != REC_LEN:
+            raise ValueError("params must be float64 [E, 12]")
+        self.params, self.blocks, self.nbr = params, blocks, nbr
+        self.dim, self.n = int(dim), int(n)
+        self.num_elems = int(params.shape[0])
+        self.c = kp_batch(self.num_elems, self.dim, self.n, _ptr(params).value,
+                          _ptr(blocks).value if blocks is not None else None,
+                          _ptr(nbr).value if nbr is not None else None)
+
+    @property
+    def ndof(self) -> int:
+        return self.n ** self.dim
+
+    def nf(self, rank: int) -> int:
+        return 2 * rank if self.dim == 2 else 5
+
+
+class Ctx:
+    """kp_ctx bound to a device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().kp_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream)), "kp_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().kp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(lib().kp_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)), "kp_set_stream")
+
+    # ---- entry points (C names without the prefix) ----
+    def precond_bytes(self, dim, n, rank, num_elems):
+        return int(lib().kp_precond_bytes(dim, n, rank, num_elems))
+
+    def build_blocks(self, b: Batch, out=None):
+        N = b.ndof
+        if out is None:
+            out = torch.empty((b.num_elems, N, N), dtype=torch.float64, device=self.device)
+        _check(lib().kp_build_blocks(self.h, ctypes.byref(b.c), _ptr(out)), "kp_build_blocks")
+        return out
+
+    def setup(self, b: Batch, rank: int = 2, mode: int = KP_SETUP_SVD, precond=None, status=None):
+        if self.precond_bytes(b.dim, b.n, rank, 1) == 0:
+            raise KpError(KP_ERR_ARG, "kp_precond_bytes")
+        nbytes = max(self.precond_bytes(b.dim, b.n, rank, b.num_elems), 1)
+        if precond is None:
+            precond = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if status is None:
+            status = torch.empty(b.num_elems, dtype=torch.int32, device=self.device)
+        _check(lib().kp_setup(self.h, ctypes.byref(b.c), rank, mode, _ptr(precond), _ptr(status)),
+               "kp_setup")
+        return precond, status
+
+    def setup_from_factors(self, b: Batch, rank: int, factors: torch.Tensor, precond=None, status=None):
+        if self.precond_bytes(b.dim, b.n, rank, 1) == 0:
+            raise KpError(KP_ERR_ARG, "kp_precond_bytes")
+        nbytes = max(self.precond_bytes(b.dim, b.n, rank, b.num_elems), 1)
+        if precond is None:
+            precond = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if status is None:
+            status = torch.empty(b.num_elems, dtype=torch.int32, device=self.device)
+        _check(lib().kp_setup_from_factors(self.h, ctypes.byref(b.c), rank, _ptr(factors),
+                                           _ptr(precond), _ptr(status)), "kp_setup_from_factors")
+        return precond, status
+
+    def get_factors(self, b: Batch, rank: int, precond):
+        f = torch.empty((b.num_elems, b.nf(rank), b.n, b.n), dtype=torch.float64, device=self.device)
+        s = torch.empty((b.num_elems, 4), dtype=torch.float64, device=self.device)
+        _check(lib().kp_get_factors(self.h, ctypes.byref(b.c), rank, _ptr(precond), _ptr(f), _ptr(s)),
+               "kp_get_factors")
+        return f, s
+
+    def apply(self, b: Batch, rank: int, precond, prec, r: torch.Tensor, z=None):
+        prec = PREC.get(prec, prec)
+        if r.dtype != torch.float64:
+            raise ValueError("r must be float64")
+        nrhs = r.numel() // (b.num_elems * b.ndof) if b.num_elems else 1
+        if z is None:
+            z = torch.empty_like(r)
+        _check(lib().kp_apply(self.h, ctypes.byref(b.c), rank, _ptr(precond), int(prec), int(nrhs),
+                              _ptr(r), _ptr(z)), "kp_apply")
+        return z
+
+    def blockjacobi_exact(self, b: Batch, lu=None, piv=None, status=None):
+        N = b.ndof
+        if lu is None:
+            lu = torch.empty((b.num_elems, N, N), dtype=torch.float64, device=self.device)
+        if piv is None:
+            piv = torch.empty((b.num_elems, N), dtype=torch.int32, device=self.device)
+        if status is None:
+            status = torch.empty(b.num_elems, dtype=torch.int32, device=self.device)
+        _check(lib().kp_blockjacobi_exact(self.h, ctypes.byref(b.c), _ptr(lu), _ptr(piv), _ptr(status)),
+               "kp_blockjacobi_exact")
+        return lu, piv, status
+
+    def blockjacobi_solve(self, b: Batch, lu, piv, r, z=None):
+        nrhs = r.numel() // (b.num_elems * b.ndof) if b.num_elems else 1
+        if z is None:
+            z = torch.empty_like(r)
+        _check(lib().kp_blockjacobi_solve(self.h, ctypes.byref(b.c), _ptr(lu), _ptr(piv), int(nrhs),
+                                          _ptr(r), _ptr(z)), "kp_blockjacobi_solve")
+        return z
+
+    def operator_apply(self, b: Batch, x, y=None):
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().kp_operator_apply(self.h, ctypes.byref(b.c), _ptr(x), _ptr(y)), "kp_operator_apply")
+        return y
+
+    def fgmres(self, b: Batch, rhs, pc_kind=KP_PC_KSVD, rank=2, pc_data=None, pc_prec=KP_FP64,
+               x=None, restart=30, rtol=1e-10, maxit=3000, hist_len=0):
+        pc_prec = PREC.get(pc_prec, pc_prec)
+        if x is None:
+            x = torch.empty_like(rhs)
+        it = ctypes.c_int32(0)
+        rr = ctypes.c_double(0.0)
+        hist = (ctypes.c_double * max(hist_len, 1))()
+        st = lib().kp_fgmres(self.h, ctypes.byref(b.c), int(pc_kind), int(rank), _ptr(pc_data),
+                             int(pc_prec), _ptr(rhs), _ptr(x), int(restart), float(rtol), int(maxit),
+                             ctypes.byref(it), ctypes.byref(rr), hist if hist_len > 0 else None,
+                             int(hist_len))
+        if st not in (KP_OK, KP_ERR_NOCONV):
+            raise KpError(st, "kp_fgmres")
+        return dict(x=x, iters=it.value, relres=rr.value, converged=(st == KP_OK),
+                    hist=list(hist)[:min(hist_len, it.value)])
