@@ -146,7 +146,10 @@ kp_status kp_apply(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* prec
                    int32_t prec, int32_t nrhs, const double* r, double* z);
 
 /* S7: exact block Jacobi.  Factor every explicit block by LU with partial
- * pivoting (lu: [E][N][N], piv: [E][N], N = n^d), then solve. */
+ * pivoting: lu [E][N][N] column-major per element (entry (i,j) at j*N + i;
+ * unit lower triangle below the diagonal, U on and above), piv [E][N] (row
+ * swapped with row k at step k), N = n^d <= 4096.  A zero pivot sets
+ * KP_ELEM_SINGULAR_FACTOR in elem_status (may be NULL).  Then z = A_k^{-1} r. */
 kp_status kp_blockjacobi_exact(kp_ctx ctx, const kp_batch* b, double* lu, int32_t* piv,
                                int32_t* elem_status);
 kp_status kp_blockjacobi_solve(kp_ctx ctx, const kp_batch* b, const double* lu,
@@ -156,16 +159,20 @@ kp_status kp_blockjacobi_solve(kp_ctx ctx, const kp_batch* b, const double* lu,
  * matrix-free) plus the upwind inflow coupling through nbr. x, y: [E][n^d]. */
 kp_status kp_operator_apply(kp_ctx ctx, const kp_batch* b, const double* x, double* y);
 
-/* S9: FGMRES(restart) on G x = b from x = 0, right preconditioned by
- * pc_kind (KSVD with pc_data = precond buffer and pc_prec, or BJ with
- * pc_data = lu buffer, its pivots following it at offset E*N*N doubles).
- * Stops when the residual estimate is <= rtol*||b|| and the true residual
- * confirms it, or after maxit Arnoldi steps (then KP_ERR_NOCONV, x holds the
- * last iterate).  iters_h, relres_h: host outputs; hist_h: host array of
- * hist_len relative residual estimates (may be NULL). */
+/* S9: FGMRES(restart) on G x = rhs from x = 0 with flexible right
+ * preconditioning (Sec. 5: restarted preconditioned GMRES): pc_kind KP_PC_KSVD
+ * (pc_data = kp_setup buffer of this rank, applied in pc_prec), KP_PC_BJ
+ * (pc_data = lu, pc_aux = piv from kp_blockjacobi_exact) or KP_PC_NONE.
+ * Classical Gram-Schmidt applied twice, Givens rotations on the host.  Stops
+ * when the residual estimate is <= rtol*||rhs|| and the true residual
+ * recomputed at the restart confirms it, or after maxit Arnoldi steps (then
+ * KP_ERR_NOCONV; x holds the last iterate).  Synchronises once per Arnoldi
+ * step.  iters_h, relres_h: host scalars (final true relative residual);
+ * hist_h: host array of hist_len per-step relative residual estimates, or
+ * NULL.  Workspace: (2*restart + 3) * E * n^d doubles, owned by ctx. */
 kp_status kp_fgmres(kp_ctx ctx, const kp_batch* b, int32_t pc_kind, int32_t rank,
-                    const void* pc_data, int32_t pc_prec, const double* rhs, double* x,
-                    int32_t restart, double rtol, int32_t maxit, int32_t* iters_h,
+                    const void* pc_data, const void* pc_aux, int32_t pc_prec, const double* rhs,
+                    double* x, int32_t restart, double rtol, int32_t maxit, int32_t* iters_h,
                     double* relres_h, double* hist_h, int32_t hist_len);
 
 #ifdef __cplusplus

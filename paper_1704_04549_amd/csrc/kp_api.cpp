@@ -11,6 +11,7 @@
 
 #include "../../include/kp.h"
 #include "kernels.h"
+#include "krylov.h"
 #include "layout.h"
 #include "tables.h"
 
@@ -262,29 +263,177 @@ kp_status kp_apply(kp_ctx c, const kp_batch* b, int32_t rank, const void* precon
 
 kp_status kp_blockjacobi_exact(kp_ctx c, const kp_batch* b, double* lu, int32_t* piv,
                                int32_t* elem_status) {
-    (void)c; (void)b; (void)lu; (void)piv; (void)elem_status;
-    return KP_ERR_UNSUPPORTED;
+    if (!c) return KP_ERR_ARG;
+    kp_status st = check_batch(b, false);
+    if (st != KP_OK) return st;
+    const int64_t E = b->num_elems;
+    if (E == 0) return KP_OK;
+    const int N = b->dim == 2 ? b->n * b->n : b->n * b->n * b->n;
+    if (!b->blocks || !lu || !piv) return KP_ERR_ARG;
+    if (N > 4096) return KP_ERR_UNSUPPORTED;
+    int32_t* status = elem_status;
+    if (!status) {
+        if ((st = ensure_ws(c, E * sizeof(int32_t), &c->ws, &c->ws_bytes)) != KP_OK) return st;
+        status = (int32_t*)c->ws;
+    }
+    KP_HIP(launch_bj_factor(c->stream, E, N, b->blocks, lu, piv, status));
+    return KP_OK;
 }
 
 kp_status kp_blockjacobi_solve(kp_ctx c, const kp_batch* b, const double* lu, const int32_t* piv,
                                int32_t nrhs, const double* r, double* z) {
-    (void)c; (void)b; (void)lu; (void)piv; (void)nrhs; (void)r; (void)z;
-    return KP_ERR_UNSUPPORTED;
+    if (!c) return KP_ERR_ARG;
+    kp_status st = check_batch(b, false);
+    if (st != KP_OK) return st;
+    const int64_t E = b->num_elems;
+    if (E == 0) return KP_OK;
+    const int N = b->dim == 2 ? b->n * b->n : b->n * b->n * b->n;
+    if (!lu || !piv || !r || !z || nrhs < 1) return KP_ERR_ARG;
+    if (N > 4096) return KP_ERR_UNSUPPORTED;
+    KP_HIP(launch_bj_solve(c->stream, E, N, nrhs, lu, piv, r, z));
+    return KP_OK;
 }
 
 kp_status kp_operator_apply(kp_ctx c, const kp_batch* b, const double* x, double* y) {
-    (void)c; (void)b; (void)x; (void)y;
-    return KP_ERR_UNSUPPORTED;
+    if (!c) return KP_ERR_ARG;
+    kp_status st = check_batch(b);
+    if (st != KP_OK) return st;
+    const int64_t E = b->num_elems;
+    if (E == 0) return KP_OK;
+    if (!x || !y || x == y) return KP_ERR_ARG;
+    const int nd = b->dim == 2 ? b->n * b->n : b->n * b->n * b->n;
+    if (nd > 4096) return KP_ERR_UNSUPPORTED;
+    const Tables1D* T;
+    if ((st = get_tables(c, b->n, &T)) != KP_OK) return st;
+    KP_HIP(launch_operator(c->stream, E, b->dim, b->n, T, b->params, b->nbr, b->blocks, x, y));
+    return KP_OK;
+}
+
+// apply the selected preconditioner: z = M v
+static kp_status fg_precond(kp_ctx c, const kp_batch* b, int pc_kind, int rank, const void* pc_data,
+                            const void* pc_aux, int pc_prec, const double* v, double* z, int64_t N) {
+    if (pc_kind == KP_PC_KSVD) return kp_apply(c, b, rank, pc_data, pc_prec, 1, v, z);
+    if (pc_kind == KP_PC_BJ)
+        return kp_blockjacobi_solve(c, b, (const double*)pc_data, (const int32_t*)pc_aux, 1, v, z);
+    KP_HIP(launch_axpby(c->stream, z, v, 1.0, nullptr, 0.0, N));
+    return KP_OK;
 }
 
 kp_status kp_fgmres(kp_ctx c, const kp_batch* b, int32_t pc_kind, int32_t rank, const void* pc_data,
-                    int32_t pc_prec, const double* rhs, double* x, int32_t restart, double rtol,
-                    int32_t maxit, int32_t* iters_h, double* relres_h, double* hist_h,
-                    int32_t hist_len) {
-    (void)c; (void)b; (void)pc_kind; (void)rank; (void)pc_data; (void)pc_prec; (void)rhs; (void)x;
-    (void)restart; (void)rtol; (void)maxit; (void)iters_h; (void)relres_h; (void)hist_h;
-    (void)hist_len;
-    return KP_ERR_UNSUPPORTED;
+                    const void* pc_aux, int32_t pc_prec, const double* rhs, double* x,
+                    int32_t restart, double rtol, int32_t maxit, int32_t* iters_h, double* relres_h,
+                    double* hist_h, int32_t hist_len) {
+    if (!c) return KP_ERR_ARG;
+    kp_status st = check_batch(b);
+    if (st != KP_OK) return st;
+    if (!rhs || !x || restart < 1 || restart > 200 || maxit < 1 || !(rtol > 0.0)) return KP_ERR_ARG;
+    if (pc_kind < KP_PC_NONE || pc_kind > KP_PC_BJ) return KP_ERR_ARG;
+    if (pc_kind != KP_PC_NONE && !pc_data) return KP_ERR_ARG;
+    if (pc_kind == KP_PC_BJ && !pc_aux) return KP_ERR_ARG;
+    const int64_t E = b->num_elems;
+    const int nd = b->dim == 2 ? b->n * b->n : b->n * b->n * b->n;
+    const int64_t N = E * nd;
+    const int m = restart;
+    if (iters_h) *iters_h = 0;
+    if (relres_h) *relres_h = 0.0;
+    if (N == 0) return KP_OK;
+    // workspace: V (m+1) N, Z m N, w N, r N, partial, h (2 (m+2)), y (m)
+    const size_t vec = (size_t)N;
+    const size_t part = (size_t)kVecBlocks * (m + 2);
+    const size_t need = ((2 * (size_t)m + 3) * vec + part + 3 * (size_t)(m + 2)) * sizeof(double);
+    if ((st = ensure_ws(c, need, &c->ks, &c->ks_bytes)) != KP_OK) return st;
+    double* V = (double*)c->ks;
+    double* Z = V + (m + 1) * vec;
+    double* w = Z + m * vec;
+    double* r = w + vec;
+    double* partial = r + vec;
+    double* hd = partial + part;   // m + 2
+    double* h2 = hd + (m + 2);     // m + 2
+    double* yd = h2 + (m + 2);     // m + 2
+    hipStream_t s = c->stream;
+    // host Hessenberg and Givens state
+    double H[201 * 200], cs[200], sn[200], g[201], hh[202];
+    double nb2 = 0.0;
+    KP_HIP(launch_mdot(s, rhs, 0, 1, rhs, N, partial, hd, 0));
+    KP_HIP(hipMemcpyAsync(&nb2, hd, sizeof(double), hipMemcpyDeviceToHost, s));
+    KP_HIP(hipStreamSynchronize(s));
+    const double nb = sqrt(nb2);
+    KP_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
+    if (!(nb > 0.0)) return KP_OK;
+    KP_HIP(launch_axpby(s, r, rhs, 1.0, nullptr, 0.0, N));
+    double beta = nb;
+    int iters = 0;
+    bool converged = false;
+    while (true) {
+        KP_HIP(launch_axpby(s, V, r, 1.0 / beta, nullptr, 0.0, N));
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double* vj = V + j * vec;
+            double* zj = Z + j * vec;
+            if ((st = fg_precond(c, b, pc_kind, rank, pc_data, pc_aux, pc_prec, vj, zj, N)) != KP_OK)
+                return st;
+            if ((st = kp_operator_apply(c, b, zj, w)) != KP_OK) return st;
+            // classical Gram-Schmidt, twice
+            KP_HIP(launch_mdot(s, V, vec, j + 1, w, N, partial, hd, 0));
+            KP_HIP(launch_mgs_update(s, V, vec, j + 1, hd, w, N));
+            KP_HIP(launch_mdot(s, V, vec, j + 1, w, N, partial, h2, 0));
+            KP_HIP(launch_mgs_update(s, V, vec, j + 1, h2, w, N));
+            KP_HIP(launch_mdot(s, w, 0, 1, w, N, partial, h2 + j + 1, 0));
+            KP_HIP(hipMemcpyAsync(hh, hd, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+            KP_HIP(hipMemcpyAsync(hh + j + 1, h2, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+            KP_HIP(hipStreamSynchronize(s));
+            // column j: projections of both passes, then the norm
+            double* col = H + j * (m + 1);
+            for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[j + 1 + i];
+            const double hn = sqrt(fmax(hh[2 * j + 2], 0.0));
+            col[j + 1] = hn;
+            if (hn > 0.0) {
+                double* vn = V + (j + 1) * vec;
+                KP_HIP(launch_axpby(s, vn, w, 1.0 / hn, nullptr, 0.0, N));
+            }
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                col[i] = t;
+            }
+            const double den = hypot(col[j], col[j + 1]);
+            cs[j] = den > 0.0 ? col[j] / den : 1.0;
+            sn[j] = den > 0.0 ? col[j + 1] / den : 0.0;
+            col[j] = den;
+            col[j + 1] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++iters;
+            k = j + 1;
+            if (hist_h && iters <= hist_len) hist_h[iters - 1] = fabs(g[j + 1]) / nb;
+            if (fabs(g[j + 1]) <= rtol * nb || iters >= maxit || hn == 0.0) break;
+        }
+        // y = H(0:k,0:k)^{-1} g, x += Z y
+        double y[200];
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int q = i + 1; q < k; ++q) t -= H[q * (m + 1) + i] * y[q];
+            const double d = H[i * (m + 1) + i];
+            y[i] = d != 0.0 ? t / d : 0.0;
+        }
+        KP_HIP(hipMemcpyAsync(yd, y, k * sizeof(double), hipMemcpyHostToDevice, s));
+        KP_HIP(launch_combine(s, Z, vec, k, yd, x, N));
+        // true residual
+        if ((st = kp_operator_apply(c, b, x, w)) != KP_OK) return st;
+        KP_HIP(launch_axpby(s, r, rhs, 1.0, w, -1.0, N));
+        double rr = 0.0;
+        KP_HIP(launch_mdot(s, r, 0, 1, r, N, partial, hd, 0));
+        KP_HIP(hipMemcpyAsync(&rr, hd, sizeof(double), hipMemcpyDeviceToHost, s));
+        KP_HIP(hipStreamSynchronize(s));
+        beta = sqrt(fmax(rr, 0.0));
+        if (beta <= rtol * nb) { converged = true; break; }
+        if (iters >= maxit || !(beta > 0.0)) break;
+    }
+    if (iters_h) *iters_h = iters;
+    if (relres_h) *relres_h = beta / nb;
+    return converged ? KP_OK : KP_ERR_NOCONV;
 }
 
 }  // extern "C"

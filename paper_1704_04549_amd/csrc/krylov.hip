@@ -1,0 +1,230 @@
+// Global operator (S8) and the vector kernels of FGMRES (S9).
+//
+// The operator is the implicit system M - tau*J of the synthetic DG
+// discretisation: each element's diagonal block (explicit, or matrix-free from
+// its record) plus the upwind inflow coupling to the neighbour across every
+// inflow face (Sec. 3.3, face part of eq. jac-entries).  With the velocity
+// a = -beta, the inflow face of axis k is the low face when beta_k < 0 (low
+// neighbour, its trace taken at its high face) and the high face when
+// beta_k > 0; the coupling block is -tau*|beta_k| (l_in l_out^T on axis k)
+// times W on the other axes.
+#include <hip/hip_runtime.h>
+
+#include "elem_ops.h"
+#include "krylov.h"
+
+namespace kp {
+
+// One workgroup per element.  LDS: x_e, mass, X_ax, one face trace.
+__global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, const Tables1D* tab,
+                                                  const double* params, const int32_t* nbr,
+                                                  const double* blocks, const double* x,
+                                                  double* y) {
+    extern __shared__ double lds[];
+    __shared__ double red[4 * kMaxReduce];
+    __shared__ Tables1D T;
+    BlockTeam tm{red};
+    {
+        const double* src = (const double*)tab;
+        double* dst = (double*)&T;
+        for (int i = threadIdx.x; i < (int)(sizeof(Tables1D) / sizeof(double)); i += blockDim.x)
+            dst[i] = src[i];
+        __syncthreads();
+    }
+    const int nn = n * n;
+    const int nd = dim == 2 ? nn : nn * n;
+    const int nf = nd / n;  // face size n^(d-1)
+    double* xe = lds;
+    double* mass = xe + nd;
+    double* Xax = mass + nd;
+    double* tr = Xax + 3 * nn;
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        const double* rec = params + e * kRecLen;
+        for (int t = threadIdx.x; t < nd; t += blockDim.x) xe[t] = x[e * nd + t];
+        record_structure(tm, rec, T, dim, mass, Xax);  // ends with a barrier
+        double acc[16];
+        const int per = (nd + blockDim.x - 1) / blockDim.x;
+        for (int q = 0; q < per && q < 16; ++q) {
+            const int I = threadIdx.x + q * blockDim.x;
+            double v = 0.0;
+            if (I < nd) {
+                if (blocks) {
+                    const double* row = blocks + (e * nd + I) * (int64_t)nd;
+                    for (int J = 0; J < nd; ++J) v += row[J] * xe[J];
+                } else {
+                    v = mass[I] * xe[I];
+                    int idx[3];
+                    if (dim == 2) { idx[0] = I / n; idx[1] = I % n; }
+                    else { idx[0] = I / nn; idx[1] = (I / n) % n; idx[2] = I % n; }
+                    for (int ax = 0; ax < dim; ++ax) {
+                        int stride = 1;
+                        for (int k = ax + 1; k < dim; ++k) stride *= n;
+                        double wp = 1.0;
+                        for (int k = 0; k < dim; ++k)
+                            if (k != ax) wp *= T.w[idx[k]];
+                        const double* Xr = Xax + ax * nn + idx[ax] * n;
+                        const int base = I - idx[ax] * stride;
+                        double s = 0.0;
+                        for (int k = 0; k < n; ++k) s += Xr[k] * xe[base + k * stride];
+                        v += wp * s;
+                    }
+                }
+            }
+            acc[q] = v;
+        }
+        // upwind coupling
+        if (nbr && rec[7] != 0.0) {
+            for (int ax = 0; ax < dim; ++ax) {
+                const double beta = rec[ax];
+                if (beta == 0.0) continue;  // uniform across the workgroup
+                const double* l_in = beta < 0.0 ? T.l0 : T.l1;
+                const double* l_out = beta < 0.0 ? T.l1 : T.l0;
+                const int64_t f = nbr[e * 2 * dim + 2 * ax + (beta < 0.0 ? 0 : 1)];
+                int stride = 1;
+                for (int k = ax + 1; k < dim; ++k) stride *= n;
+                // trace of the neighbour on its outflow face: tr[J] = sum_k l_out[k] x_f[..k..]
+                const double* xf = x + f * nd;
+                for (int J = threadIdx.x; J < nf; J += blockDim.x) {
+                    const int lo = J % stride, hi = J / stride;
+                    const int base = hi * stride * n + lo;
+                    double s = 0.0;
+                    for (int k = 0; k < n; ++k) s += l_out[k] * xf[base + k * stride];
+                    tr[J] = s;
+                }
+                __syncthreads();
+                const double coef = -rec[6] * fabs(beta);
+                for (int q = 0; q < per && q < 16; ++q) {
+                    const int I = threadIdx.x + q * blockDim.x;
+                    if (I >= nd) continue;
+                    int idx[3];
+                    if (dim == 2) { idx[0] = I / n; idx[1] = I % n; }
+                    else { idx[0] = I / nn; idx[1] = (I / n) % n; idx[2] = I % n; }
+                    double wp = 1.0;
+                    for (int k = 0; k < dim; ++k)
+                        if (k != ax) wp *= T.w[idx[k]];
+                    const int lo = I % stride, hi = I / (stride * n);
+                    acc[q] += coef * l_in[idx[ax]] * wp * tr[hi * stride + lo];
+                }
+                __syncthreads();
+            }
+        }
+        for (int q = 0; q < per && q < 16; ++q) {
+            const int I = threadIdx.x + q * blockDim.x;
+            if (I < nd) y[e * nd + I] = acc[q];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------- vector kernels
+// partial[b * k + i] = sum over block b's chunk of V_i . w   (i < k)
+__global__ void __launch_bounds__(256) k_mdot_partial(const double* V, int64_t ldv, int k,
+                                                      const double* w, int64_t N, double* partial) {
+    __shared__ double red[4 * 64];
+    const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < N ? lo + chunk : N;
+    for (int i = 0; i < k; ++i) {
+        const double* v = V + i * ldv;
+        double s = 0.0;
+        for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) s += v[t] * w[t];
+        s = wave_sum(s);
+        if (lane == 0) red[wv] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0;
+            for (int q = 0; q < nw; ++q) a += red[q];
+            partial[blockIdx.x * (int64_t)k + i] = a;
+        }
+        __syncthreads();
+    }
+}
+
+// out[i] = sum_b partial[b * k + i] (fixed order), optionally accumulated
+__global__ void k_mdot_reduce(const double* partial, int nblocks, int k, double* out, int accumulate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    double a = 0.0;
+    for (int b = 0; b < nblocks; ++b) a += partial[(int64_t)b * k + i];
+    out[i] = accumulate ? out[i] + a : a;
+}
+
+// w -= sum_i h[i] V_i
+__global__ void k_mgs_update(const double* V, int64_t ldv, int k, const double* h, double* w,
+                             int64_t N) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        double s = w[t];
+        for (int i = 0; i < k; ++i) s -= h[i] * V[i * ldv + t];
+        w[t] = s;
+    }
+}
+
+// x += sum_i y[i] Z_i
+__global__ void k_combine(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t N) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        double s = x[t];
+        for (int i = 0; i < k; ++i) s += y[i] * Z[i * ldz + t];
+        x[t] = s;
+    }
+}
+
+// dst = a * src + b * other  (other may be null)
+__global__ void k_axpby(double* dst, const double* src, double a, const double* other, double b,
+                        int64_t N) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N;
+         t += (int64_t)gridDim.x * blockDim.x)
+        dst[t] = a * src[t] + (other ? b * other[t] : 0.0);
+}
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                           const double* params, const int32_t* nbr, const double* blocks,
+                           const double* x, double* y) {
+    const int nn = n * n;
+    const int nd = dim == 2 ? nn : nn * n;
+    if (nd > 16 * 256) return hipErrorInvalidValue;
+    size_t lds = (2 * nd + 3 * nn + nd / n) * sizeof(double);
+    int grid = (int)(E < 65536 ? E : 65536);
+    hipLaunchKernelGGL(k_operator, dim3(grid), dim3(256), lds, s, E, dim, n, tab, params, nbr, blocks,
+                       x, y);
+    return hipGetLastError();
+}
+
+int vec_grid(int64_t N) {
+    int64_t g = (N + 255) / 256;
+    if (g > kVecBlocks) g = kVecBlocks;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_mdot(hipStream_t s, const double* V, int64_t ldv, int k, const double* w,
+                       int64_t N, double* partial, double* out, int accumulate) {
+    const int g = vec_grid(N);
+    hipLaunchKernelGGL(k_mdot_partial, dim3(g), dim3(256), 0, s, V, ldv, k, w, N, partial);
+    hipLaunchKernelGGL(k_mdot_reduce, dim3((k + 63) / 64), dim3(64), 0, s, partial, g, k, out,
+                       accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_mgs_update(hipStream_t s, const double* V, int64_t ldv, int k, const double* h,
+                             double* w, int64_t N) {
+    hipLaunchKernelGGL(k_mgs_update, dim3(vec_grid(N)), dim3(256), 0, s, V, ldv, k, h, w, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(hipStream_t s, const double* Z, int64_t ldz, int k, const double* y,
+                          double* x, int64_t N) {
+    hipLaunchKernelGGL(k_combine, dim3(vec_grid(N)), dim3(256), 0, s, Z, ldz, k, y, x, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(hipStream_t s, double* dst, const double* src, double a, const double* other,
+                        double b, int64_t N) {
+    hipLaunchKernelGGL(k_axpby, dim3(vec_grid(N)), dim3(256), 0, s, dst, src, a, other, b, N);
+    return hipGetLastError();
+}
+
+}  // namespace kp

@@ -63,7 +63,7 @@ def lib() -> ctypes.CDLL:
             "kp_blockjacobi_exact": ([vp, bp, vp, vp, vp], ctypes.c_int),
             "kp_blockjacobi_solve": ([vp, bp, vp, vp, i32, vp, vp], ctypes.c_int),
             "kp_operator_apply": ([vp, bp, vp, vp], ctypes.c_int),
-            "kp_fgmres": ([vp, bp, i32, i32, vp, i32, vp, vp, i32, dbl, i32,
+            "kp_fgmres": ([vp, bp, i32, i32, vp, vp, i32, vp, vp, i32, dbl, i32,
                            ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, i32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
@@ -222,8 +222,8 @@ class Ctx:
         _check(lib().kp_operator_apply(self.h, ctypes.byref(b.c), _ptr(x), _ptr(y)), "kp_operator_apply")
         return y
 
-    def fgmres(self, b: Batch, rhs, pc_kind=KP_PC_KSVD, rank=2, pc_data=None, pc_prec=KP_FP64,
-               x=None, restart=30, rtol=1e-10, maxit=3000, hist_len=0):
+    def fgmres(self, b: Batch, rhs, pc_kind=KP_PC_KSVD, rank=2, pc_data=None, pc_aux=None,
+               pc_prec=KP_FP64, x=None, restart=30, rtol=1e-10, maxit=3000, hist_len=0):
         pc_prec = PREC.get(pc_prec, pc_prec)
         if x is None:
             x = torch.empty_like(rhs)
@@ -231,7 +231,7 @@ class Ctx:
         rr = ctypes.c_double(0.0)
         hist = (ctypes.c_double * max(hist_len, 1))()
         st = lib().kp_fgmres(self.h, ctypes.byref(b.c), int(pc_kind), int(rank), _ptr(pc_data),
-                             int(pc_prec), _ptr(rhs), _ptr(x), int(restart), float(rtol), int(maxit),
+                             _ptr(pc_aux), int(pc_prec), _ptr(rhs), _ptr(x), int(restart), float(rtol), int(maxit),
                              ctypes.byref(it), ctypes.byref(rr), hist if hist_len > 0 else None,
                              int(hist_len))
         if st not in (KP_OK, KP_ERR_NOCONV):

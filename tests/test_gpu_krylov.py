@@ -1,0 +1,109 @@
+"""GPU parity of the global operator (S8), exact block Jacobi (S7) and FGMRES (S9).
+
+Bars: operator and block-Jacobi solves within 1e-13 / 1e-12 relative of the
+oracle; FGMRES converges to rtol 1e-10 with the same solution as a dense
+solve (1e-8 relative) and, with the FP64 preconditioners, the same iteration
+count as the oracle's FGMRES within +-1 (the oracle orthogonalises with
+modified Gram-Schmidt, the GPU with classical Gram-Schmidt applied twice);
+FP32 / BF16 preconditioners need at most one more iteration than FP64.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import operator
+from oracle.apply import dense_solve
+from oracle.blocks import element_block
+from oracle.krylov import bj_factor, bj_solve, fgmres
+from oracle.ksvd import ksvd2d, ksvd3d
+from oracle.tables import tables
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1704_04549_amd import kp
+    c = kp.Ctx(0)
+    yield c
+    c.close()
+
+
+MESHES = [(2, 5, 4, 31), (3, 4, 3, 32), (3, 8, 2, 33)]  # dim, n, mesh, seed
+
+
+@pytest.mark.parametrize("dim,n,mesh,seed", MESHES)
+def test_operator_matches_oracle(ctx, dim, n, mesh, seed):
+    from tests.gpu_util import batch, rel, to_dev
+    print(f"operator dim={dim} n={n} mesh={mesh}", flush=True)
+    E = mesh ** dim
+    params = synth.draw_params(E, dim, seed, face=True)
+    nbr = synth.periodic_neighbours(mesh, dim)
+    x = np.random.default_rng(seed).standard_normal((E, n ** dim))
+    yref = operator.apply(params, nbr, n, dim, x)
+    b = batch(params, dim, n, nbr=nbr)
+    y = ctx.operator_apply(b, to_dev(x)).cpu().numpy()
+    assert rel(y, yref) <= 1e-13
+    blocks = ctx.build_blocks(b)
+    be = batch(params, dim, n, blocks=blocks, nbr=nbr)
+    y2 = ctx.operator_apply(be, to_dev(x)).cpu().numpy()
+    assert rel(y2, yref) <= 1e-13
+
+
+@pytest.mark.parametrize("dim,n,E", [(2, 8, 64), (3, 4, 40), (3, 8, 6)])
+def test_block_jacobi_matches_oracle(ctx, dim, n, E):
+    from tests.gpu_util import batch, rel, to_dev
+    print(f"bj dim={dim} n={n} E={E}", flush=True)
+    params = synth.draw_params(E, dim, 60 + n, face=True)
+    T = tables(n)
+    blocks = np.stack([element_block(r, n, dim, T) for r in params])
+    b = batch(params, dim, n, blocks=blocks)
+    lu, piv, st = ctx.blockjacobi_exact(b)
+    r = np.random.default_rng(1).standard_normal((E, 2, n ** dim))
+    z = ctx.blockjacobi_solve(b, lu, piv, to_dev(r)).cpu().numpy()
+    assert int(st.abs().sum()) == 0
+    zref = bj_solve(bj_factor(blocks), r)
+    assert rel(z, zref) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,n,mesh,seed", [(2, 5, 4, 41), (3, 4, 3, 42), (3, 8, 2, 43)])
+def test_fgmres_iterations_and_solution(ctx, dim, n, mesh, seed):
+    from paper_1704_04549_amd import kp
+    from tests.gpu_util import batch, rel, to_dev
+    print(f"fgmres dim={dim} n={n} mesh={mesh}", flush=True)
+    E = mesh ** dim
+    params = synth.draw_params(E, dim, seed, face=True)
+    nbr = synth.periodic_neighbours(mesh, dim)
+    rhs = np.random.default_rng(seed).standard_normal((E, n ** dim))
+    T = tables(n)
+    blocks = np.stack([element_block(r, n, dim, T) for r in params])
+    G = operator.assemble(params, nbr, n, dim)
+    xref = np.linalg.solve(G.toarray(), rhs.ravel())
+    fo = [ksvd2d(A, n, 2) if dim == 2 else ksvd3d(A, n) for A in blocks]
+    Aop = lambda v: G @ v
+    Mk = lambda v: np.concatenate([dense_solve(fo[e], v.reshape(E, -1)[e]) for e in range(E)])
+    lus = bj_factor(blocks)
+    Mj = lambda v: bj_solve(lus, v.reshape(E, -1)).ravel()
+    _, it_k, _, ok_k = fgmres(Aop, Mk, rhs.ravel(), m=30, rtol=1e-10)
+    _, it_j, _, ok_j = fgmres(Aop, Mj, rhs.ravel(), m=30, rtol=1e-10)
+    assert ok_k and ok_j
+    b = batch(params, dim, n, nbr=nbr)
+    pc, st = ctx.setup(b, 2)
+    bd = batch(params, dim, n, blocks=ctx.build_blocks(b), nbr=nbr)
+    lu, piv, _ = ctx.blockjacobi_exact(bd)
+    rd = to_dev(rhs)
+    res = {}
+    for name, kw in (("ksvd64", dict(pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec="fp64")),
+                     ("ksvd32", dict(pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec="fp32")),
+                     ("ksvd16", dict(pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec="bf16")),
+                     ("bj", dict(pc_kind=kp.KP_PC_BJ, pc_data=lu, pc_aux=piv))):
+        out = ctx.fgmres(b, rd, restart=30, rtol=1e-10, maxit=2000, **kw)
+        res[name] = out["iters"]
+        print(f"  {name}: iters {out['iters']} relres {out['relres']:.2e}", flush=True)
+        assert out["converged"] and out["relres"] <= 1e-10
+        assert rel(out["x"].cpu().numpy(), xref.reshape(E, -1)) <= 1e-8
+    print(f"  oracle iters: ksvd {it_k} bj {it_j}", flush=True)
+    assert abs(res["ksvd64"] - it_k) <= 1
+    assert abs(res["bj"] - it_j) <= 1
+    assert res["ksvd32"] <= res["ksvd64"] + 1
