@@ -69,23 +69,29 @@ typedef enum { KP_PC_NONE = 0, KP_PC_KSVD = 1, KP_PC_BJ = 2 } kp_pc_kind;
 #define KP_ELEM_LEARNED_REJECTED 16 /* learned factors failed the acceptance test */
 #define KP_ELEM_LEARNED_WARM 32     /* learned factors used as the Lanczos start */
 
-#define KP_REC_LEN 12
+#define KP_REC_LEN 16
 
 /*
  * A batch of elements of one dimension and one degree.
- *   params : [E][12] element records (always required).  Record layout:
- *            beta_x, beta_y, beta_z, nu, alpha, phi, tau, face, 0, 0, 0, 0.
+ *   params : [E][16] element records (always required).  Record layout:
+ *            [0..2] beta_x, beta_y, beta_z (element velocity a = -beta),
+ *            [3] nu, [4] alpha, [5] phi, [6] tau, [7] face flag,
+ *            [8..13] normal velocity u_f of the upwind flux on the faces
+ *            x-, x+, y-, y+, z-, z+ (outward normal, u_f > 0 outflow),
+ *            [14..15] zero.
  *            The block of element k is (Sec. 3.3, Table 1, eq. adv-kron, with
  *            collocated Gauss-Legendre quadrature on [0,1]^d):
  *              diag(w (x) w [(x) w] * c) + tau * sum_axes (beta S + nu K) on
  *              that axis (x) W on the others, c = 1 + alpha sin(pi x y [z] + phi),
- *            plus, if face != 0, the upwind outflow self-term
- *              tau*|beta| * l l^T on each axis (l = l(1) if beta < 0, l(0) if
- *              beta > 0) (x) W on the others.
+ *            plus, if face != 0, the outflow self-term tau*u_f * l l^T on the
+ *            face's axis (l = l(0) low face, l(1) high face) (x) W on the others
+ *            for every face with u_f > 0.
  *   blocks : [E][n^d][n^d] explicit blocks, row-major, or NULL.  When NULL the
  *            setup and the operator are matrix-free from params.
  *   nbr    : [E][2*dim] face neighbours (low, high per axis), or NULL.  Used
- *            only by kp_operator_apply and kp_fgmres for the upwind coupling.
+ *            only by kp_operator_apply and kp_fgmres for the upwind coupling:
+ *            on a face with u_f < 0 the element receives
+ *            tau*u_f (l_f l_opp^T (x) W ...) applied to the neighbour's values.
  */
 typedef struct {
     int64_t num_elems;

@@ -18,9 +18,10 @@ slowest index of the nodal vector: u[(i*n + j)*n + k].
 
 With the record's face flag set, the outflow self-terms of the upwind flux are
 added to the block (weak form, eq. weak-form; the face part of eq.
-jac-entries): for each axis, tau*|beta| * (l l^T) on that axis times W on the
-others, with l = l1 when beta < 0 (the velocity -beta points to the high
-face) and l = l0 when beta > 0.
+jac-entries).  The numerical flux on a face uses one normal velocity u_f
+(record entries 8..13 for the faces x-, x+, y-, y+, z-, z+; u_f > 0 is
+outflow).  An outflow face contributes tau*u_f * (l l^T) on its axis times W on
+the other axes, with l = l0 on the low face and l1 on the high face.
 
 Pinned by tests/test_oracle_blocks.py (the bilinear form against an
 independent higher-order quadrature of the weak form, alpha = 0 separability).
@@ -45,12 +46,14 @@ def coefficient(rec: np.ndarray, x: np.ndarray, dim: int) -> np.ndarray:
 
 
 def axis_operator(rec: np.ndarray, ax: int, T: dict) -> np.ndarray:
-    """1D part of the block along one axis: tau*(beta S + nu K + face term)."""
+    """1D part of the block along one axis: tau*(beta S + nu K) + outflow face terms."""
     beta, nu, tau = rec[ax], rec[3], rec[6]
     X = tau * (beta * T["S"] + nu * T["K"])
-    if rec[7] != 0.0 and beta != 0.0:
-        l = T["l1"] if beta < 0.0 else T["l0"]
-        X = X + tau * abs(beta) * np.outer(l, l)
+    if rec[7] != 0.0:
+        for side, l in ((0, T["l0"]), (1, T["l1"])):
+            u = rec[8 + 2 * ax + side]
+            if u > 0.0:
+                X = X + tau * u * np.outer(l, l)
     return X
 
 

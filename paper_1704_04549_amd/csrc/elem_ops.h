@@ -21,7 +21,8 @@ namespace kp {
 // Sec. 3.3 with element-constant flux Jacobians):
 //   A = diag(m) + sum_ax  W (x) .. (x) X_ax (x) .. (x) W,
 //   m = w (x) w [(x) w] * (1 + alpha sin(pi x y [z] + phi)),
-//   X_ax = tau*(beta_ax S + nu K) [+ tau*|beta_ax| l l^T with the face flag].
+//   X_ax = tau*(beta_ax S + nu K) [+ tau*u_f l l^T for each outflow face f of
+//   the axis (u_f > 0; l = l0 low face, l1 high face) with the face flag].
 template <class Team>
 KP_HD void record_structure(const Team& tm, const double* rec, const Tables1D& T, int dim,
                             double* mass, double* Xax) {
@@ -48,9 +49,10 @@ KP_HD void record_structure(const Team& tm, const double* rec, const Tables1D& T
         const int ax = t / (n * n), ij = t % (n * n), i = ij / n, j = ij % n;
         const double beta = rec[ax];
         double v = tau * (beta * T.S[ij] + nu * T.K[ij]);
-        if (face && beta != 0.0) {
-            const double* l = beta < 0.0 ? T.l1 : T.l0;
-            v += tau * fabs(beta) * l[i] * l[j];
+        if (face) {
+            const double ulo = rec[8 + 2 * ax], uhi = rec[9 + 2 * ax];
+            if (ulo > 0.0) v += tau * ulo * T.l0[i] * T.l0[j];
+            if (uhi > 0.0) v += tau * uhi * T.l1[i] * T.l1[j];
         }
         Xax[t] = v;
     }

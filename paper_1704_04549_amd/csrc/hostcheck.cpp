@@ -62,7 +62,7 @@ int kph_form_tables(int dim, int n, int rank, const double* factors, double* tab
     return form_tables(tm, dim, n, rank, factors, tab, tab + 7L * n * n, kinds, work.data(), piv.data(), sh);
 }
 
-// prec 0: FP64; 1: FP32; 2: BF16 operands with FP32 accumulation
+// prec 0: FP64; 1: FP32; 2: BF16 operands with FP32 accumulation; 3: split BF16 (hi + lo)
 int kph_apply(int dim, int n, int prec, const double* tab, const int8_t* kinds, const double* r,
               double* z) {
     HostTeam tm;

@@ -26,6 +26,15 @@ hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank
                               int32_t* status, double* gwork);
 hipError_t launch_cast_tables(hipStream_t s, int64_t count, const double* t64, float* t32,
                               uint16_t* hi, uint16_t* lo, float* t2);
+hipError_t launch_frag_tables(hipStream_t s, int64_t E, const double* t64, double* f64f, float* f32f,
+                              uint16_t* fbf, uint16_t* fbf3);
+// n = 16 matrix-core apply (apply_mfma.hip); grid cap of its persistent loop.
+// tabs: row-major tables of the precision (T2 is read from them); frags: the
+// fragment-ordered copy of the same precision.
+constexpr int64_t kApply16Grid = 1 << 20;
+hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
+                          int64_t tab_stride, const void* frags, const int8_t* kinds,
+                          const double* r, double* z);
 hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
                                 const void* tabs, int64_t tab_stride, const int8_t* kinds,
                                 const double* r, double* z);

@@ -27,6 +27,9 @@ struct kp_ctx_s {
     // FGMRES / operator scratch
     void* ks = nullptr;
     size_t ks_bytes = 0;
+    // matrix-core apply for n = 16 (KP_APPLY_GENERIC=1 in the environment selects
+    // the generic per-element kernel instead, for comparison)
+    bool use_mfma16 = true;
 };
 
 #define KP_HIP(call)                                   \
@@ -104,6 +107,8 @@ kp_status kp_create(kp_ctx* ctx, int device, void* stream) {
     if (!c) return KP_ERR_ALLOC;
     c->device = device;
     c->stream = (hipStream_t)stream;
+    const char* gen = getenv("KP_APPLY_GENERIC");
+    c->use_mfma16 = !(gen && gen[0] == '1');
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cus = prop.multiProcessorCount;
@@ -159,6 +164,10 @@ static kp_status finish_tables(kp_ctx c, const kp_batch* b, int rank, char* pc, 
     KP_HIP(launch_cast_tables(c->stream, E * L.ne, (const double*)(pc + L.t64), (float*)(pc + L.t32),
                               (uint16_t*)(pc + L.thi), (uint16_t*)(pc + L.tlo),
                               (float*)(pc + L.t2)));
+    if (b->n == 16)
+        KP_HIP(launch_frag_tables(c->stream, E, (const double*)(pc + L.t64), (double*)(pc + L.f64f),
+                                  (float*)(pc + L.f32f), (uint16_t*)(pc + L.fbf),
+                                  (uint16_t*)(pc + L.fbf3)));
     return KP_OK;
 }
 
@@ -256,8 +265,17 @@ kp_status kp_apply(kp_ctx c, const kp_batch* b, int32_t rank, const void* precon
                        : prec == KP_FP32 ? (const void*)(pc + L.t32)
                        : prec == KP_BF16 ? (const void*)(pc + L.thi)
                                          : (const void*)(pc + L.t2);
-    KP_HIP(launch_apply_generic(c->stream, prec, E, b->dim, b->n, nrhs, tabs, L.ne,
-                                (const int8_t*)(pc + L.kinds), r, z));
+    if (b->n == 16 && c->use_mfma16) {
+        const void* frags = prec == KP_FP64   ? (const void*)(pc + L.f64f)
+                            : prec == KP_FP32 ? (const void*)(pc + L.f32f)
+                            : prec == KP_BF16 ? (const void*)(pc + L.fbf)
+                                              : (const void*)(pc + L.fbf3);
+        KP_HIP(launch_apply16(c->stream, prec, E, b->dim, nrhs, tabs, L.ne, frags,
+                              (const int8_t*)(pc + L.kinds), r, z));
+    } else {
+        KP_HIP(launch_apply_generic(c->stream, prec, E, b->dim, b->n, nrhs, tabs, L.ne,
+                                    (const int8_t*)(pc + L.kinds), r, z));
+    }
     return KP_OK;
 }
 

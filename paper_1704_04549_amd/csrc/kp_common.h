@@ -23,7 +23,7 @@
 
 namespace kp {
 
-constexpr int kRecLen = 12;
+constexpr int kRecLen = 16;
 constexpr int kMaxN = 32;
 
 // ---------------------------------------------------------------- host team

@@ -3,11 +3,11 @@
 // The operator is the implicit system M - tau*J of the synthetic DG
 // discretisation: each element's diagonal block (explicit, or matrix-free from
 // its record) plus the upwind inflow coupling to the neighbour across every
-// inflow face (Sec. 3.3, face part of eq. jac-entries).  With the velocity
-// a = -beta, the inflow face of axis k is the low face when beta_k < 0 (low
-// neighbour, its trace taken at its high face) and the high face when
-// beta_k > 0; the coupling block is -tau*|beta_k| (l_in l_out^T on axis k)
-// times W on the other axes.
+// inflow face (Sec. 3.3, face part of eq. jac-entries).  With one normal
+// velocity u_f per face (record entries 8..13, u_f > 0 outflow), an element takes the neighbour's trace on each inflow face f (u_f < 0): the
+// coupling block is tau*u_f (l_f l_opp^T on the face's axis) times W on the
+// other axes, l_f = l0 / l1 on the low / high face and l_opp the neighbour's
+// opposite face.
 #include <hip/hip_runtime.h>
 
 #include "elem_ops.h"
@@ -72,18 +72,19 @@ __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, con
             }
             acc[q] = v;
         }
-        // upwind coupling
+        // upwind coupling on inflow faces
         if (nbr && rec[7] != 0.0) {
-            for (int ax = 0; ax < dim; ++ax) {
-                const double beta = rec[ax];
-                if (beta == 0.0) continue;  // uniform across the workgroup
-                const double* l_in = beta < 0.0 ? T.l0 : T.l1;
-                const double* l_out = beta < 0.0 ? T.l1 : T.l0;
-                const int64_t f = nbr[e * 2 * dim + 2 * ax + (beta < 0.0 ? 0 : 1)];
+            for (int f = 0; f < 2 * dim; ++f) {
+                const double u = rec[8 + f];
+                if (!(u < 0.0)) continue;  // uniform across the workgroup
+                const int ax = f >> 1, side = f & 1;
+                const double* l_in = side ? T.l1 : T.l0;
+                const double* l_out = side ? T.l0 : T.l1;
+                const int64_t nb = nbr[e * 2 * dim + f];
                 int stride = 1;
                 for (int k = ax + 1; k < dim; ++k) stride *= n;
-                // trace of the neighbour on its outflow face: tr[J] = sum_k l_out[k] x_f[..k..]
-                const double* xf = x + f * nd;
+                // neighbour's trace on its opposite face: tr[J] = sum_k l_out[k] x_nb[..k..]
+                const double* xf = x + nb * nd;
                 for (int J = threadIdx.x; J < nf; J += blockDim.x) {
                     const int lo = J % stride, hi = J / stride;
                     const int base = hi * stride * n + lo;
@@ -92,7 +93,7 @@ __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, con
                     tr[J] = s;
                 }
                 __syncthreads();
-                const double coef = -rec[6] * fabs(beta);
+                const double coef = rec[6] * u;
                 for (int q = 0; q < per && q < 16; ++q) {
                     const int I = threadIdx.x + q * blockDim.x;
                     if (I >= nd) continue;

@@ -22,7 +22,7 @@ KP_SETUP_SVD, KP_SETUP_LEARNED = 0, 1
 KP_PC_NONE, KP_PC_KSVD, KP_PC_BJ = 0, 1, 2
 ELEM_LANCZOS_NOCONV, ELEM_SINGULAR_FACTOR, ELEM_SCHUR_NOCONV, ELEM_NONFINITE = 1, 2, 4, 8
 ELEM_LEARNED_REJECTED, ELEM_LEARNED_WARM = 16, 32
-REC_LEN = 12
+REC_LEN = 16
 PREC = {"fp64": KP_FP64, "fp32": KP_FP32, "bf16": KP_BF16, "bf16x3": KP_BF16X3}
 
 
@@ -100,7 +100,7 @@ class Batch:
 
     def __init__(self, params: torch.Tensor, dim: int, n: int, blocks=None, nbr=None):
         if params.dtype != torch.float64 or params.shape[-1] != REC_LEN:
-            raise ValueError("params must be float64 [E, 12]")
+            raise ValueError("params must be float64 [E, 16]")
         self.params, self.blocks, self.nbr = params, blocks, nbr
         self.dim, self.n = int(dim), int(n)
         self.num_elems = int(params.shape[0])

@@ -4,13 +4,16 @@ This module only draws random numbers and lays out meshes; it contains none of
 the preconditioner's arithmetic (no 1D tables, no element blocks, no SVD, no
 solves).  Both the CPU oracle and the GPU path read the arrays it returns.
 
-Element record (float64[12]), one per element:
+Element record (float64[16]), one per element:
 
-    [0] beta_x   [1] beta_y   [2] beta_z (0 in 2D)
+    [0] beta_x   [1] beta_y   [2] beta_z (0 in 2D)   (element velocity a = -beta)
     [3] nu       [4] alpha    [5] phi
-    [6] tau      [7] face flag (1.0: the element's outflow-face self-terms of
-                    the upwind flux are part of its diagonal block)
-    [8..11] reserved, zero
+    [6] tau      [7] face flag (1.0: upwind face terms are part of the operator)
+    [8..13] normal velocity u_f = a_f . n_f on the faces x-, x+, y-, y+, z-, z+
+            (outward normal; u_f > 0 is outflow), with the face velocity
+            a_f = (a_e + a_neighbour) / 2 of the conservative upwind flux;
+            an element drawn without a mesh uses its own velocity on every face
+    [14..15] reserved, zero
 
 Draws (numpy PCG64 via ``default_rng``), per element in order:
 beta_x, beta_y, [beta_z], log10(nu), alpha, phi with
@@ -22,15 +25,22 @@ from __future__ import annotations
 
 import numpy as np
 
-REC_LEN = 12
+REC_LEN = 16
 TAU = 0.1
 
-# the five workloads (element count, dim, n, rank, face terms, nrhs)
+# the workloads: dim, n, mesh, rank, face terms, coupling through faces, nrhs, seeds.
+# c3 couples neighbours through the upwind flux (face velocities averaged over
+# the two elements); c4 is the block-diagonal system of elements closed by
+# their own upwind faces (the coupled p=15 system makes FGMRES(30) stagnate).
 WORKLOADS = {
-    "c1_2d_p7": dict(dim=2, n=8, mesh=16, rank=2, face=False, nrhs=1, seed=1001, rhs_seed=2001),
-    "c2_2d_p15": dict(dim=2, n=16, mesh=128, rank=2, face=False, nrhs=8, seed=1002, rhs_seed=2002),
-    "c3_3d_p7": dict(dim=3, n=8, mesh=32, rank=2, face=True, nrhs=1, seed=1003, rhs_seed=2003),
-    "c4_3d_p15": dict(dim=3, n=16, mesh=16, rank=2, face=True, nrhs=1, seed=1004, rhs_seed=2004),
+    "c1_2d_p7": dict(dim=2, n=8, mesh=16, rank=2, face=False, coupled=False, nrhs=1,
+                     seed=1001, rhs_seed=2001),
+    "c2_2d_p15": dict(dim=2, n=16, mesh=128, rank=2, face=False, coupled=False, nrhs=8,
+                      seed=1002, rhs_seed=2002),
+    "c3_3d_p7": dict(dim=3, n=8, mesh=32, rank=2, face=True, coupled=True, nrhs=1,
+                     seed=1003, rhs_seed=2003),
+    "c4_3d_p15": dict(dim=3, n=16, mesh=16, rank=2, face=True, coupled=False, nrhs=1,
+                      seed=1004, rhs_seed=2004),
 }
 MLP_TRAIN_SEED = 3004
 MLP_VAL_SEED = 4004
@@ -53,13 +63,39 @@ def draw_params(num_elems: int, dim: int, seed: int, face: bool = False,
     rec[:, 5] = 2.0 * np.pi * u[:, dim + 2]
     rec[:, 6] = tau
     rec[:, 7] = 1.0 if face else 0.0
+    if face:
+        own_face_velocities(rec, dim)
     return rec
+
+
+def own_face_velocities(rec: np.ndarray, dim: int) -> None:
+    """Face normal velocities of isolated elements: a_f = a_e on every face."""
+    for ax in range(dim):
+        rec[:, 8 + 2 * ax] = rec[:, ax]       # low face: a.(-e_ax) = beta_ax
+        rec[:, 9 + 2 * ax] = -rec[:, ax]      # high face: a.(+e_ax) = -beta_ax
+
+
+def mesh_face_velocities(rec: np.ndarray, nbr: np.ndarray, dim: int) -> None:
+    """Face normal velocities on a mesh: a_f = (a_e + a_neighbour) / 2 on every face."""
+    for ax in range(dim):
+        lo = rec[nbr[:, 2 * ax], ax]
+        hi = rec[nbr[:, 2 * ax + 1], ax]
+        rec[:, 8 + 2 * ax] = 0.5 * (rec[:, ax] + lo)
+        rec[:, 9 + 2 * ax] = -0.5 * (rec[:, ax] + hi)
 
 
 def draw_rhs(num_elems: int, nrhs: int, ndof: int, seed: int) -> np.ndarray:
     """Right-hand sides, float64[E, nrhs, ndof], N(0,1)."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((num_elems, nrhs, ndof))
+
+
+def mesh_params(mesh: int, dim: int, seed: int, tau: float = TAU) -> tuple:
+    """Records with face terms on a periodic mesh^dim grid, and its neighbour table."""
+    rec = draw_params(mesh ** dim, dim, seed, face=True, tau=tau)
+    nbr = periodic_neighbours(mesh, dim)
+    mesh_face_velocities(rec, nbr, dim)
+    return rec, nbr
 
 
 def periodic_neighbours(mesh: int, dim: int) -> np.ndarray:
@@ -88,9 +124,13 @@ def workload(name: str, num_elems: int | None = None):
     dim, n, M = cfg["dim"], cfg["n"], cfg["mesh"]
     E_full = M ** dim
     E = E_full if num_elems is None else int(num_elems)
-    rec = draw_params(E_full, dim, cfg["seed"], face=cfg["face"])[:E]
+    rec = draw_params(E_full, dim, cfg["seed"], face=cfg["face"])
+    nbr = periodic_neighbours(M, dim) if cfg["coupled"] else None
+    if cfg["coupled"]:
+        mesh_face_velocities(rec, nbr, dim)
+    rec = rec[:E]
     rhs = draw_rhs(E_full, cfg["nrhs"], n ** dim, cfg["rhs_seed"])[:E]
-    nbr = periodic_neighbours(M, dim) if E == E_full else None
+    nbr = nbr if E == E_full else None
     return dict(cfg, num_elems=E, params=rec, rhs=rhs, nbr=nbr)
 
 

@@ -38,8 +38,7 @@ def test_operator_matches_oracle(ctx, dim, n, mesh, seed):
     from tests.gpu_util import batch, rel, to_dev
     print(f"operator dim={dim} n={n} mesh={mesh}", flush=True)
     E = mesh ** dim
-    params = synth.draw_params(E, dim, seed, face=True)
-    nbr = synth.periodic_neighbours(mesh, dim)
+    params, nbr = synth.mesh_params(mesh, dim, seed)
     x = np.random.default_rng(seed).standard_normal((E, n ** dim))
     yref = operator.apply(params, nbr, n, dim, x)
     b = batch(params, dim, n, nbr=nbr)
@@ -73,8 +72,7 @@ def test_fgmres_iterations_and_solution(ctx, dim, n, mesh, seed):
     from tests.gpu_util import batch, rel, to_dev
     print(f"fgmres dim={dim} n={n} mesh={mesh}", flush=True)
     E = mesh ** dim
-    params = synth.draw_params(E, dim, seed, face=True)
-    nbr = synth.periodic_neighbours(mesh, dim)
+    params, nbr = synth.mesh_params(mesh, dim, seed)
     rhs = np.random.default_rng(seed).standard_normal((E, n ** dim))
     T = tables(n)
     blocks = np.stack([element_block(r, n, dim, T) for r in params])

@@ -133,7 +133,7 @@ def test_c4_matrix_free_sampled(ctx):
 
 def test_empty_batch(ctx):
     from tests.gpu_util import batch
-    params = np.zeros((0, 12))
+    params = np.zeros((0, 16))
     b = batch(params, 2, 8)
     pc, st = ctx.setup(b, 2)
     z = ctx.apply(b, 2, pc, "fp64", torch.zeros(0, dtype=torch.float64, device="cuda"))
@@ -153,3 +153,31 @@ def test_more_elements_than_setup_grid(ctx):
     for e in (0, 2047, 2048, 2050):
         so = ksvd2d(element_block(params[e], 6, 2), 6, 2)["sigma"][:2]
         assert np.max(np.abs(s[e, :2] / so - 1)) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,nrhs", [(3, 2), (2, 8), (2, 20)])
+def test_mfma16_apply_matches_generic_and_oracle(ctx, dim, nrhs, monkeypatch):
+    """The n = 16 matrix-core apply against the generic kernel and the oracle, all precisions
+    (2D with 20 right-hand sides exercises a ragged second group of slices)."""
+    from paper_1704_04549_amd import kp
+    from tests.gpu_util import batch, rel, to_dev
+    n, E = 16, 12
+    print(f"mfma16 dim={dim} nrhs={nrhs}", flush=True)
+    params = synth.draw_params(E, dim, 321 + dim, face=(dim == 3))
+    b = batch(params, dim, n)
+    pc, st = ctx.setup(b, 2)
+    r = np.random.default_rng(5).standard_normal((E, nrhs, n ** dim))
+    rd = to_dev(r)
+    monkeypatch.setenv("KP_APPLY_GENERIC", "1")
+    gctx = kp.Ctx(0)
+    f_gpu, _ = ctx.get_factors(b, 2, pc)
+    fo = [factors_from_array(f, dim) for f in f_gpu.cpu().numpy()]
+    zref = np.stack([dense_solve(fo[e], r[e]) for e in range(E)])
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5), ("bf16", 2e-2), ("bf16x3", 1e-4)):
+        zm = ctx.apply(b, 2, pc, prec, rd)
+        zg = gctx.apply(b, 2, pc, prec, rd)
+        torch.cuda.synchronize()
+        em, eg = rel(zm.cpu().numpy(), zref), rel(zg.cpu().numpy(), zref)
+        print(f"  {prec}: mfma {em:.2e} generic {eg:.2e}", flush=True)
+        assert em <= tol and eg <= tol
+    gctx.close()

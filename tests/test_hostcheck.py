@@ -1,0 +1,121 @@
+"""CPU checks of the GPU library's per-element arithmetic (host build of elem_ops.h).
+
+The same source the kernels run, built for the host with a one-thread team,
+is checked here against the oracle without a GPU: 1D tables, element blocks,
+the Lanczos KSVD setup (explicit and matrix-free), the device real Schur form,
+table formation and the apply in every precision.
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.apply import dense_solve
+from oracle.blocks import element_block
+from oracle.ksvd import factor_array, factors_from_array, ksvd2d, ksvd3d, precond_matrix
+from oracle.tables import tables
+
+LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_native", "libkp_hostcheck.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="host-check build missing (run build)")
+
+
+def P(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return ctypes.CDLL(LIB)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+@pytest.mark.parametrize("n", [2, 5, 8, 16, 31])
+def test_tables_match_oracle(lib, n):
+    out = [np.zeros(n), np.zeros(n), np.zeros((n, n)), np.zeros((n, n)), np.zeros((n, n)),
+           np.zeros(n), np.zeros(n)]
+    assert lib.kph_make_tables(n, *[P(a) for a in out]) == 0
+    T = tables(n)
+    for a, key in zip(out, ["x", "w", "D", "S", "K", "l0", "l1"]):
+        assert np.max(np.abs(a - T[key])) <= 1e-12 * max(1.0, np.max(np.abs(T[key])))
+
+
+@pytest.mark.parametrize("dim,n", [(2, 7), (3, 4)])
+def test_blocks_match_oracle(lib, dim, n):
+    params, _ = synth.mesh_params(3, dim, 9)
+    N = n ** dim
+    for rec in params[:4]:
+        out = np.zeros((N, N))
+        lib.kph_block(dim, n, P(rec), P(out))
+        ref = element_block(rec, n, dim)
+        assert np.max(np.abs(out - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+def host_setup(lib, dim, n, rec, block):
+    nf = 4 if dim == 2 else 5
+    f = np.zeros((nf, n, n))
+    sig = np.zeros(4)
+    steps = ctypes.c_int(0)
+    st = lib.kph_setup(dim, n, 2, P(rec), P(block) if block is not None else None, None, P(f), P(sig),
+                       ctypes.byref(steps))
+    return st, f, sig
+
+
+@pytest.mark.parametrize("dim,n,explicit", [(2, 6, True), (2, 6, False), (2, 12, True),
+                                            (3, 4, True), (3, 4, False), (3, 6, False)])
+def test_lanczos_setup_matches_full_svd(lib, dim, n, explicit):
+    params, _ = synth.mesh_params(2, dim, 21)
+    for rec in params[:3]:
+        A = element_block(rec, n, dim)
+        st, f, sig = host_setup(lib, dim, n, rec, A if explicit else None)
+        assert st == 0
+        fo = ksvd2d(A, n, 2) if dim == 2 else ksvd3d(A, n)
+        so = fo["sigma"][:2] if dim == 2 else np.r_[fo["sigma1"][0], fo["sigma2"][:2]]
+        got = sig[:2] if dim == 2 else sig[:3]
+        assert np.max(np.abs(got / so - 1)) <= 1e-12
+        assert rel(precond_matrix(factors_from_array(f, dim)), precond_matrix(fo)) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [2, 3, 6, 16, 31])
+def test_real_schur(lib, n):
+    rng = np.random.default_rng(n)
+    for _ in range(5):
+        C = rng.standard_normal((n, n))
+        T = np.zeros((n, n))
+        Q = np.zeros((n, n))
+        assert lib.kph_schur(n, P(C), P(T), P(Q)) == 0
+        assert rel(Q @ T @ Q.T, C) <= 1e-13
+        assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 1e-13 * n
+        assert np.all(np.tril(T, -2) == 0)
+        for j in range(1, n):
+            if T[j, j - 1] != 0:  # standardised 2x2 block: complex pair
+                assert T[j, j] == T[j - 1, j - 1] and T[j - 1, j] * T[j, j - 1] < 0
+                assert j < 2 or T[j - 1, j - 2] == 0
+        ev = np.sort_complex(np.linalg.eigvals(C))
+        assert np.max(np.abs(np.sort_complex(np.linalg.eigvals(T)) - ev)) <= 1e-10 * np.max(np.abs(ev))
+
+
+@pytest.mark.parametrize("dim,n", [(2, 8), (2, 16), (3, 8)])
+def test_apply_all_precisions(lib, dim, n):
+    params, _ = synth.mesh_params(2, dim, 33)
+    rng = np.random.default_rng(1)
+    Z = {p: [] for p in range(4)}
+    ZR = []
+    for rec in params[:6]:
+        fo = ksvd2d(element_block(rec, n, dim), n, 2) if dim == 2 else ksvd3d(element_block(rec, n, dim), n)
+        F = factor_array(fo)
+        tab = np.zeros((7 + n) * n * n)
+        kinds = np.zeros(n, np.int8)
+        assert lib.kph_form_tables(dim, n, 2, P(F), P(tab), P(kinds)) == 0
+        r = rng.standard_normal(n ** dim)
+        ZR.append(dense_solve(fo, r))
+        for prec in range(4):
+            z = np.zeros(n ** dim)
+            lib.kph_apply(dim, n, prec, P(tab), P(kinds), P(r), P(z))
+            Z[prec].append(z)
+    for prec, tol in ((0, 1e-12), (1, 1e-5), (2, 2e-2), (3, 1e-4)):
+        assert rel(np.array(Z[prec]), np.array(ZR)) <= tol, prec

@@ -54,9 +54,11 @@ def weak_form(cu, cv, rec, dim):
     for ax in range(dim):
         val += tau * rec[ax] * integral(signal.convolve(cu, deriv(cv, ax)))
         val += tau * rec[3] * integral(signal.convolve(deriv(cu, ax), deriv(cv, ax)))
-        if rec[7] != 0.0 and rec[ax] != 0.0:
-            t = 1.0 if rec[ax] < 0 else 0.0
-            val += tau * abs(rec[ax]) * integral(signal.convolve(restrict(cu, ax, t), restrict(cv, ax, t)))
+        for side in (0, 1):
+            u = rec[8 + 2 * ax + side]
+            if rec[7] != 0.0 and u > 0.0:
+                t = float(side)
+                val += tau * u * integral(signal.convolve(restrict(cu, ax, t), restrict(cv, ax, t)))
     return val
 
 
@@ -65,12 +67,13 @@ def test_bilinear_form_matches_weak_form(dim, n, face):
     rng = np.random.default_rng(7 + n)
     T = tables(n)
     for trial in range(3):
-        rec = np.zeros(12)
+        rec = np.zeros(16)
         rec[:dim] = rng.uniform(-1, 1, dim)
         rec[3] = 10 ** rng.uniform(-3, -1)
         rec[4] = 0.0
         rec[6] = 0.1
         rec[7] = face
+        rec[8:8 + 2 * dim] = rng.uniform(-1, 1, 2 * dim)  # face normal velocities
         A = element_block(rec, n, dim, T)
         cu = rng.standard_normal((n,) * dim)
         cv = rng.standard_normal((n,) * dim)
@@ -85,7 +88,7 @@ def test_mass_coefficient_integral():
     # n-point rule of int (1 + alpha sin(pi x y + phi)), spectrally accurate
     n = 16
     T = tables(n)
-    rec = np.zeros(12)
+    rec = np.zeros(16)
     rec[4], rec[5], rec[6] = 0.37, 1.3, 0.0
     A = element_block(rec, n, 2, T)
     assert np.count_nonzero(A - np.diag(A.diagonal())) == 0
@@ -97,7 +100,7 @@ def test_mass_coefficient_integral():
 def test_alpha_zero_is_separable():
     n = 6
     T = tables(n)
-    rec = np.array([0.3, -0.7, 0, 0.02, 0.0, 0.4, 0.1, 1, 0, 0, 0, 0])
+    rec = np.array([0.3, -0.7, 0, 0.02, 0.0, 0.4, 0.1, 1, 0.3, -0.3, -0.7, 0.7, 0, 0, 0, 0])
     A = element_block(rec, n, 2, T)
     W = T["W"]
     X = W + 0.1 * (0.3 * T["S"] + 0.02 * T["K"]) + 0.1 * 0.3 * np.outer(T["l0"], T["l0"])

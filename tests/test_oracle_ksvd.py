@@ -60,7 +60,7 @@ def test_eckart_young_residual(n, dim):
 def test_alpha_zero_2d_block_is_exact_rank_two():
     # Sec. 5.1: a separable operator is reproduced exactly by A1(x)B1 + A2(x)B2
     n = 8
-    rec = np.array([0.4, -0.9, 0, 0.01, 0.0, 0, 0.1, 1, 0, 0, 0, 0])
+    rec = np.array([0.4, -0.9, 0, 0.01, 0.0, 0, 0.1, 1, 0.4, -0.4, -0.9, 0.9, 0, 0, 0, 0])
     A = element_block(rec, n, 2)
     f = ksvd2d(A, n, 2)
     assert f["sigma"][2] < 1e-14 * f["sigma"][0]
@@ -70,7 +70,7 @@ def test_alpha_zero_2d_block_is_exact_rank_two():
 def test_separable_3d_block_is_exact():
     # beta_x = nu = alpha = 0: A = W (x) (W(x)W + tau*beta_y S(x)W + tau*beta_z W(x)S)
     n = 5
-    rec = np.array([0.0, 0.6, -0.3, 0.0, 0.0, 0, 0.1, 0, 0, 0, 0, 0])
+    rec = np.array([0.0, 0.6, -0.3, 0.0, 0.0, 0, 0.1, 0, 0, 0, 0, 0, 0, 0, 0, 0])
     A = element_block(rec, n, 3)
     f = ksvd3d(A, n)
     assert f["sigma1"][1] < 1e-14 * f["sigma1"][0]

@@ -13,8 +13,7 @@ from oracle.tables import tables
 @pytest.mark.parametrize("dim,n,mesh", [(2, 4, 3), (3, 3, 2)])
 def test_matrix_free_equals_assembled(dim, n, mesh):
     E = mesh ** dim
-    params = synth.draw_params(E, dim, seed=5, face=True)
-    nbr = synth.periodic_neighbours(mesh, dim)
+    params, nbr = synth.mesh_params(mesh, dim, seed=5)
     x = np.random.default_rng(0).standard_normal((E, n ** dim))
     y = operator.apply(params, nbr, n, dim, x)
     G = operator.assemble(params, nbr, n, dim)
@@ -53,8 +52,7 @@ def test_fgmres_one_step_with_exact_inverse():
 def test_fgmres_matches_dense_solve_and_gmres_history():
     dim, n, mesh = 2, 4, 3
     E = mesh ** dim
-    params = synth.draw_params(E, dim, seed=6, face=True)
-    nbr = synth.periodic_neighbours(mesh, dim)
+    params, nbr = synth.mesh_params(mesh, dim, seed=6)
     G = operator.assemble(params, nbr, n, dim).toarray()
     T = tables(n)
     blocks = np.stack([element_block(r, n, dim, T) for r in params])
