@@ -501,14 +501,10 @@ KP_HD int lanczos_top(const Team& tm, const Op& op, int m, int r, int kmax, doub
 // positive (lowest index on ties); returns the sign applied
 template <class Team>
 KP_HD double canonical_sign(const Team& tm, double* u, int m, int* ctrl_slot) {
-    if (tm.leader()) {
-        int best = 0;
-        for (int i = 1; i < m; ++i)
-            if (fabs(u[i]) > fabs(u[best])) best = i;
-        ctrl_slot[0] = u[best] < 0.0 ? -1 : 1;
-    }
+    (void)ctrl_slot;
+    const int best = tm.argmax_abs(u, 1, 0, m);
+    const double sg = u[best] < 0.0 ? -1.0 : 1.0;
     tm.sync();
-    const double sg = (double)ctrl_slot[0];
     for (int i = tm.tid(); i < m; i += tm.size()) u[i] *= sg;
     tm.sync();
     return sg;
@@ -543,79 +539,62 @@ KP_HD void mtm(const Team& tm, int n, const double* A, const double* B, double* 
 // 1-norm (largest column sum of magnitudes), returned to every thread
 template <class Team>
 KP_HD double norm1(const Team& tm, int n, const double* M, double* sh) {
-    if (tm.leader()) {
-        double mx = 0.0;
-        for (int j = 0; j < n; ++j) {
-            double c = 0.0;
-            for (int i = 0; i < n; ++i) c += fabs(M[i * n + j]);
-            mx = c > mx ? c : mx;
-        }
-        sh[5] = mx;
+    (void)sh;
+    double mx = 0.0;
+    for (int j = tm.tid(); j < n; j += tm.size()) {
+        double c = 0.0;
+        for (int i = 0; i < n; ++i) c += fabs(M[i * n + j]);
+        mx = c > mx ? c : mx;
     }
-    tm.sync();
-    const double v = sh[5];
-    tm.sync();
-    return v;
+    return tm.max(mx);
 }
 
-// Ainv = A^{-1} by LU with partial pivoting; A is overwritten by its LU
-// factors.  piv: n ints of shared scratch.  Returns false on a zero pivot.
+// Ainv = A^{-1} by Gauss-Jordan elimination with partial pivoting on the pair
+// [A | I]; A is destroyed.  mult: n doubles of shared scratch; piv unused
+// (kept for the call sites).  Returns false on a zero pivot.
 template <class Team>
-KP_HD bool invert(const Team& tm, int n, double* A, double* Ainv, int* piv) {
+KP_HD bool invert(const Team& tm, int n, double* A, double* Ainv, int* piv, double* mult) {
+    (void)piv;
     bool ok = true;
+    for (int t = tm.tid(); t < n * n; t += tm.size()) Ainv[t] = (t / n == t % n) ? 1.0 : 0.0;
+    tm.sync();
     for (int k = 0; k < n; ++k) {
-        if (tm.leader()) {
-            int p = k;
-            for (int i = k + 1; i < n; ++i)
-                if (fabs(A[i * n + k]) > fabs(A[p * n + k])) p = i;
-            piv[k] = p;
-        }
-        tm.sync();
-        const int p = piv[k];
-        if (p != k)
-            for (int j = tm.tid(); j < n; j += tm.size()) {
-                const double t = A[k * n + j];
-                A[k * n + j] = A[p * n + j];
-                A[p * n + j] = t;
+        const int p = tm.argmax_abs(A + k, n, k, n);
+        if (p != k) {
+            for (int j = tm.tid(); j < 2 * n; j += tm.size()) {
+                double* M = j < n ? A : Ainv;
+                const int jj = j < n ? j : j - n;
+                const double t = M[k * n + jj];
+                M[k * n + jj] = M[p * n + jj];
+                M[p * n + jj] = t;
             }
-        tm.sync();
+            tm.sync();
+        }
         const double pv = A[k * n + k];
         if (pv == 0.0) {
             ok = false;
             continue;
         }
-        for (int i = k + 1 + tm.tid(); i < n; i += tm.size()) {
-            const double l = A[i * n + k] / pv;
-            A[i * n + k] = l;
-            for (int j = k + 1; j < n; ++j) A[i * n + j] -= l * A[k * n + j];
+        // multipliers of column k (applied to the scaled pivot row), then scale
+        // row k and eliminate every other row
+        for (int i = tm.tid(); i < n; i += tm.size()) mult[i] = (i == k) ? 0.0 : A[i * n + k];
+        tm.sync();
+        const double inv = 1.0 / pv;
+        for (int j = tm.tid(); j < 2 * n; j += tm.size()) {
+            double* M = j < n ? A : Ainv;
+            const int jj = j < n ? j : j - n;
+            M[k * n + jj] *= inv;
+        }
+        tm.sync();
+        for (int t = tm.tid(); t < 2 * n * n; t += tm.size()) {
+            const int i = t / (2 * n), j = t % (2 * n);
+            if (i == k) continue;
+            double* M = j < n ? A : Ainv;
+            const int jj = j < n ? j : j - n;
+            M[i * n + jj] -= mult[i] * M[k * n + jj];
         }
         tm.sync();
     }
-    // solve A X = P^T-permuted identity, one column per thread
-    for (int c = tm.tid(); c < n; c += tm.size()) {
-        double col[kMaxN];
-        for (int i = 0; i < n; ++i) col[i] = (i == c) ? 1.0 : 0.0;
-        for (int k = 0; k < n; ++k) {
-            const int p = piv[k];
-            if (p != k) {
-                const double t = col[k];
-                col[k] = col[p];
-                col[p] = t;
-            }
-        }
-        for (int i = 0; i < n; ++i) {
-            double s = col[i];
-            for (int k = 0; k < i; ++k) s -= A[i * n + k] * col[k];
-            col[i] = s;
-        }
-        for (int i = n - 1; i >= 0; --i) {
-            double s = col[i];
-            for (int k = i + 1; k < n; ++k) s -= A[i * n + k] * col[k];
-            col[i] = s / A[i * n + i];
-        }
-        for (int i = 0; i < n; ++i) Ainv[i * n + c] = col[i];
-    }
-    tm.sync();
     return ok;
 }
 
@@ -787,7 +766,8 @@ KP_HD bool real_schur(const Team& tm, int n, double* H, double* Q, double* sh /*
     // Francis QR
     const double eps = 2.220446049250313e-16;
     double hnorm = 0.0;
-    for (int t = 0; t < n * n; ++t) hnorm = fmax(hnorm, fabs(H[t]));
+    for (int t = tm.tid(); t < n * n; t += tm.size()) hnorm = fmax(hnorm, fabs(H[t]));
+    hnorm = tm.max(hnorm);
     int hi = n - 1, iter = 0, total = 0;
     bool ok = true;
     while (hi >= 0) {
@@ -885,46 +865,45 @@ KP_HD bool real_schur(const Team& tm, int n, double* H, double* Q, double* sh /*
 constexpr int kTabFixed = 7;
 KP_INLINE long tab_entries(int n) { return (long)(kTabFixed + n) * n * n; }
 
-// Work: >= 10 n^2 doubles + n ints.  F: factors (2D rank r: A1,B1,A2,B2,..; 3D:
-// A1,B1,C1,B2,C2).  Returns the status bits of the element.
+// The formation runs in three phases (separate kernels on the GPU, so that
+// the Schur phase can run at high occupancy):
+//   prepare: pair rotation, inverses of the factors to invert (stored in the
+//            L slots), the matrices C1, C2 to triangularise (stored in the
+//            first two N slots);
+//   schur:   T_i, Q_i of C_i (into the T and R slots);
+//   finish:  L = Q^T inverse (2D: L0, L1; 3D: L1, L2), block kinds of T2, N_j.
+
+// prepare.  Work: >= 10 n^2 doubles.  F: factors (2D rank r: A1,B1,A2,B2,..;
+// 3D: A1,B1,C1,B2,C2).  tab: the 7 + n matrices of the element.
 template <class Team>
-KP_HD int form_tables(const Team& tm, int dim, int n, int rank, const double* F, double* tab,
-                      double* N, int8_t* kinds, double* work, int* ipiv, double* sh) {
+KP_HD int tables_prepare(const Team& tm, int dim, int n, int rank, const double* F, double* tab,
+                         double* N, double* work, int* ipiv, double* sh) {
     const int nn = n * n;
     double* W0 = work;
     double* W1 = work + nn;
     double* W2 = work + 2 * nn;
     double* W3 = work + 3 * nn;
-    double* W4 = work + 4 * nn;
-    double* W5 = work + 5 * nn;
+    int status = 0;
     double* L0 = tab;
     double* L1 = tab + nn;
     double* L2 = tab + 2 * nn;
-    double* R0 = tab + 3 * nn;
-    double* R1 = tab + 4 * nn;
-    double* T1 = tab + 5 * nn;
-    double* T2 = tab + 6 * nn;
-    int status = 0;
-    for (int t = tm.tid(); t < 7 * nn; t += tm.size()) tab[t] = 0.0;
+    double* C1 = N;
+    double* C2 = N + nn;
+    for (int t = tm.tid(); t < 3 * nn; t += tm.size()) tab[t] = 0.0;
     tm.sync();
     if (dim == 2 && rank == 1) {
-        for (int t = tm.tid(); t < nn; t += tm.size()) W0[t] = F[t];
-        tm.sync();
-        if (!invert(tm, n, W0, L0, ipiv)) status |= 2;
-        for (int t = tm.tid(); t < nn; t += tm.size()) W0[t] = F[nn + t];
-        tm.sync();
-        if (!invert(tm, n, W0, L1, ipiv)) status |= 2;
-        for (int t = tm.tid(); t < nn; t += tm.size()) {
-            const bool dg = (t / n == t % n);
-            R0[t] = dg ? 1.0 : 0.0;
-            R1[t] = dg ? 1.0 : 0.0;
-            T1[t] = dg ? 0.5 : 0.0;
-            T2[t] = dg ? 0.5 : 0.0;
+        // P = A1 (x) B1: T1 = T2 = I/2, Q = I in the same form
+        for (int q = 0; q < 2; ++q) {
+            for (int t = tm.tid(); t < nn; t += tm.size()) W0[t] = F[q * nn + t];
+            tm.sync();
+            if (!invert(tm, n, W0, W1, ipiv, sh + 8)) status |= 2;
+            for (int t = tm.tid(); t < nn; t += tm.size()) (q ? L1 : L0)[t] = W1[t];
+            tm.sync();
         }
-        for (int j = tm.tid(); j < n; j += tm.size()) kinds[j] = 0;
-        tm.sync();
-        for (long t = tm.tid(); t < (long)n * nn; t += tm.size())
-            N[t] = ((t % nn) / n == (t % nn) % n) ? 1.0 : 0.0;
+        for (int t = tm.tid(); t < nn; t += tm.size()) {
+            C1[t] = (t / n == t % n) ? 0.5 : 0.0;
+            C2[t] = C1[t];
+        }
         tm.sync();
         return status;
     }
@@ -971,7 +950,7 @@ KP_HD int form_tables(const Team& tm, int dim, int n, int rank, const double* F,
             for (int q = 0; q < 2; ++q) {
                 double* M = q == 0 ? W0 : W1;
                 const double nm = norm1(tm, n, M, sh);
-                const bool ok = invert(tm, n, M, W2, ipiv);
+                const bool ok = invert(tm, n, M, W2, ipiv, sh + 8);
                 const double ni = norm1(tm, n, W2, sh);
                 score *= ok ? nm * ni : 1e300;
             }
@@ -1005,43 +984,70 @@ KP_HD int form_tables(const Team& tm, int dim, int n, int rank, const double* F,
         Gy = R6;  // B1'  -> C1' = B2'^{-1} B1'
         Gz = R9;  // C2'  -> C2' = C1'^{-1} C2'
     }
-    // inverses: W1 = inv(Fx), W2 = inv(Fy) [2D] / inv(Fy) [3D], W3 = inv(Fz) [3D]
-    for (int t = tm.tid(); t < nn; t += tm.size()) W0[t] = Fx[t];
-    tm.sync();
-    if (!invert(tm, n, W0, W1, ipiv)) status |= 2;
-    for (int t = tm.tid(); t < nn; t += tm.size()) W0[t] = Fy[t];
-    tm.sync();
-    if (!invert(tm, n, W0, W2, ipiv)) status |= 2;
-    if (dim == 3) {
-        for (int t = tm.tid(); t < nn; t += tm.size()) W0[t] = Fz[t];
+    // inverses into the L slots: 2D L0 = inv(A2'), L1 = inv(B1');
+    // 3D L0 = inv(A1), L1 = inv(B2'), L2 = inv(C1')  (formed in work, then copied)
+    double* W4 = work + 4 * nn;
+    const double* srcs[3] = {Fx, Fy, Fz};
+    double* dsts[3] = {L0, L1, L2};
+    for (int q = 0; q < (dim == 3 ? 3 : 2); ++q) {
+        for (int t = tm.tid(); t < nn; t += tm.size()) W0[t] = srcs[q][t];
         tm.sync();
-        if (!invert(tm, n, W0, W3, ipiv)) status |= 2;
-    }
-    // C matrices: 2D: C1 = W1 Gy, C2 = W2 Gz.  3D: C1' = W2 Gy, C2' = W3 Gz
-    const double* invY = dim == 2 ? W1 : W2;
-    const double* invZ = dim == 2 ? W2 : W3;
-    mm(tm, n, invY, Gy, T1);  // T1 <- C1 (Schur in place)
-    mm(tm, n, invZ, Gz, T2);
-    if (!real_schur(tm, n, T1, R0, sh)) status |= 4;
-    if (!real_schur(tm, n, T2, R1, sh)) status |= 4;
-    // left tables
-    if (dim == 2) {
-        mtm(tm, n, R0, W1, L0);  // Q1^T A2^{-1}
-        mtm(tm, n, R1, W2, L1);  // Q2^T B1^{-1}
-    } else {
-        for (int t = tm.tid(); t < nn; t += tm.size()) L0[t] = W1[t];  // A1^{-1}
+        if (!invert(tm, n, W0, W4, ipiv, sh + 8)) status |= 2;
+        for (int t = tm.tid(); t < nn; t += tm.size()) dsts[q][t] = W4[t];
         tm.sync();
-        mtm(tm, n, R0, W2, L1);  // Q1^T B2^{-1}
-        mtm(tm, n, R1, W3, L2);  // Q2^T C1^{-1}
     }
+    // C matrices: 2D: C1 = inv(A2') A1', C2 = inv(B1') B2'.  3D: C1 = inv(B2') B1', C2 = inv(C1') C2'
+    const double* invY = dim == 2 ? L0 : L1;
+    const double* invZ = dim == 2 ? L1 : L2;
+    for (int t = tm.tid(); t < nn; t += tm.size()) {
+        W2[t] = invY[t];
+        W3[t] = invZ[t];
+    }
+    tm.sync();
+    mm(tm, n, W2, Gy, W0);
+    mm(tm, n, W3, Gz, W1);
+    for (int t = tm.tid(); t < nn; t += tm.size()) {
+        C1[t] = W0[t];
+        C2[t] = W1[t];
+    }
+    tm.sync();
+    return status;
+}
+
+// finish.  tab holds the inverses (L slots), T1, T2, Q1 = R0, Q2 = R1.
+// Work: >= 6 n^2 doubles (T1, T2 and Q's are staged there).
+template <class Team>
+KP_HD int tables_finish(const Team& tm, int dim, int n, double* tab, double* N, int8_t* kinds,
+                        double* work, int* ipiv, double* sh) {
+    const int nn = n * n;
+    double* W0 = work;
+    double* W1 = work + nn;
+    double* W4 = work + 2 * nn;
+    double* W5 = work + 3 * nn;
+    double* T1 = work + 4 * nn;
+    double* Qs = work + 5 * nn;
+    int status = 0;
+    double* Ls[2] = {dim == 2 ? tab : tab + nn, dim == 2 ? tab + nn : tab + 2 * nn};
+    const double* Rs[2] = {tab + 3 * nn, tab + 4 * nn};
+    const double* T2 = tab + 6 * nn;
+    // L = Q^T inverse
+    for (int q = 0; q < 2; ++q) {
+        for (int t = tm.tid(); t < nn; t += tm.size()) {
+            W0[t] = Ls[q][t];
+            Qs[t] = Rs[q][t];
+        }
+        tm.sync();
+        mtm(tm, n, Qs, W0, W1);
+        for (int t = tm.tid(); t < nn; t += tm.size()) Ls[q][t] = W1[t];
+        tm.sync();
+    }
+    for (int t = tm.tid(); t < nn; t += tm.size()) T1[t] = tab[5 * nn + t];
     // kinds from the standardised T2
-    if (tm.leader()) {
-        for (int j = 0; j < n; ++j) kinds[j] = 0;
-        for (int j = 1; j < n; ++j)
-            if (T2[j * n + j - 1] != 0.0) {
-                kinds[j - 1] = 1;
-                kinds[j] = 2;
-            }
+    for (int j = tm.tid(); j < n; j += tm.size()) {
+        int kd = 0;
+        if (j > 0 && T2[j * n + j - 1] != 0.0) kd = 2;
+        if (j + 1 < n && T2[(j + 1) * n + j] != 0.0) kd = 1;
+        kinds[j] = (int8_t)kd;
     }
     tm.sync();
     // N_j
@@ -1049,36 +1055,62 @@ KP_HD int form_tables(const Team& tm, int dim, int n, int rank, const double* F,
         const int kd = kinds[j];
         if (kd == 1) continue;  // filled with its partner
         if (kd == 0) {
-            for (int t = tm.tid(); t < nn; t += tm.size())
-                W0[t] = T1[t] + ((t / n == t % n) ? T2[j * n + j] : 0.0);
+            const double tj = T2[j * n + j];
+            for (int t = tm.tid(); t < nn; t += tm.size()) W0[t] = T1[t] + ((t / n == t % n) ? tj : 0.0);
             tm.sync();
-            if (!invert(tm, n, W0, N + (long)j * nn, ipiv)) status |= 2;
+            if (!invert(tm, n, W0, W1, ipiv, sh + 8)) status |= 2;
+            for (int t = tm.tid(); t < nn; t += tm.size()) N[(long)j * nn + t] = W1[t];
+            tm.sync();
         } else {
             const double p = T2[j * n + j], q = T2[(j - 1) * n + j], s = T2[j * n + j - 1];
-            for (int t = tm.tid(); t < nn; t += tm.size())
-                W4[t] = T1[t] + ((t / n == t % n) ? p : 0.0);
+            for (int t = tm.tid(); t < nn; t += tm.size()) W4[t] = T1[t] + ((t / n == t % n) ? p : 0.0);
             tm.sync();
             mm(tm, n, W4, W4, W5);
-            for (int t = tm.tid(); t < nn; t += tm.size())
-                W0[t] = W5[t] - ((t / n == t % n) ? q * s : 0.0);
+            for (int t = tm.tid(); t < nn; t += tm.size()) W0[t] = W5[t] - ((t / n == t % n) ? q * s : 0.0);
             tm.sync();
-            if (!invert(tm, n, W0, N + (long)j * nn, ipiv)) status |= 2;
-            for (int t = tm.tid(); t < nn; t += tm.size())
-                N[(long)(j - 1) * nn + t] = N[(long)j * nn + t];
+            if (!invert(tm, n, W0, W1, ipiv, sh + 8)) status |= 2;
+            for (int t = tm.tid(); t < nn; t += tm.size()) {
+                N[(long)j * nn + t] = W1[t];
+                N[(long)(j - 1) * nn + t] = W1[t];
+            }
             tm.sync();
         }
     }
-    // non-finite check
-    if (tm.leader()) {
-        bool bad = false;
-        for (long t = 0; t < 7L * nn; ++t)
-            if (!(fabs(tab[t]) < 1e300)) bad = true;
-        for (long t = 0; t < (long)n * nn; ++t)
-            if (!(fabs(N[t]) < 1e300)) bad = true;
-        if (bad) sh[4] = 1.0; else sh[4] = 0.0;
+    // non-finite check (a NaN fails the comparison)
+    double bad = 0.0;
+    for (long t = tm.tid(); t < 7L * nn; t += tm.size())
+        if (!(fabs(tab[t]) < 1e300)) bad = 1.0;
+    for (long t = tm.tid(); t < (long)n * nn; t += tm.size())
+        if (!(fabs(N[t]) < 1e300)) bad = 1.0;
+    if (tm.max(bad) != 0.0) status |= 8;
+    return status;
+}
+
+// Schur phase for one of the two C matrices: H (n^2 shared, destroyed) holds C;
+// T and Q are written to Tout, Qout.
+template <class Team>
+KP_HD int tables_schur(const Team& tm, int n, const double* C, double* Tout, double* Qout, double* H,
+                       double* Q, double* sh) {
+    for (int t = tm.tid(); t < n * n; t += tm.size()) H[t] = C[t];
+    tm.sync();
+    const bool ok = real_schur(tm, n, H, Q, sh);
+    for (int t = tm.tid(); t < n * n; t += tm.size()) {
+        Tout[t] = H[t];
+        Qout[t] = Q[t];
     }
     tm.sync();
-    if (sh[4] != 0.0) status |= 8;
+    return ok ? 0 : 4;
+}
+
+// All three phases in sequence (host checks).  Work: >= 10 n^2 doubles.
+template <class Team>
+KP_HD int form_tables(const Team& tm, int dim, int n, int rank, const double* F, double* tab,
+                      double* N, int8_t* kinds, double* work, int* ipiv, double* sh) {
+    const int nn = n * n;
+    int status = tables_prepare(tm, dim, n, rank, F, tab, N, work, ipiv, sh);
+    status |= tables_schur(tm, n, N, tab + 5 * nn, tab + 3 * nn, work, work + nn, sh);
+    status |= tables_schur(tm, n, N + nn, tab + 6 * nn, tab + 4 * nn, work, work + nn, sh);
+    status |= tables_finish(tm, dim, n, tab, N, kinds, work, ipiv, sh);
     return status;
 }
 
@@ -1284,6 +1316,28 @@ KP_INLINE SetupWork carve_setup_work(double* base, int dim, int n, bool expl) {
     W.L.theta = p; p += 3;
     W.L.ctrl = (int*)p; p += 8;
     return W;
+}
+
+// Lanczos scalars and the tridiagonal eigenproblem (d, e, Z, sel, h, ...),
+// and the operator scratch d, placed in fast shared memory: doubles needed
+KP_INLINE long setup_small_doubles(int n, bool expl) {
+    const long kmax = lanczos_kmax(n, expl);
+    return (kmax + 2) + 2 * (kmax + 1) + 2 * kmax + kmax * kmax + 3 * kmax + 3 + 8 +
+           (long)n * n + 64;
+}
+KP_INLINE void carve_small(double* p, int n, bool expl, SetupWork* W) {
+    const long kmax = lanczos_kmax(n, expl);
+    W->L.h = p; p += kmax + 2;
+    W->L.alpha = p; p += kmax + 1;
+    W->L.beta = p; p += kmax + 1;
+    W->L.d = p; p += kmax;
+    W->L.e = p; p += kmax;
+    W->L.Z = p; p += kmax * kmax;
+    W->L.sel = p; p += 3 * kmax;
+    W->L.theta = p; p += 3;
+    W->L.ctrl = (int*)p; p += 8;
+    W->d = p; p += (long)n * n;
+    W->small = p;
 }
 
 // start vector of the Lanczos iteration: the caller's guess, else all ones

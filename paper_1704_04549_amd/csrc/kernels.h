@@ -15,15 +15,10 @@ hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int 
                         const Tables1D* tab, const double* params, const double* blocks,
                         const double* guess, double* factors, double* sigma, int32_t* status,
                         double* ws, int64_t ws_stride);
-// LDS budget of the table kernel; above it the 10 n^2 work doubles go to
-// global memory (kFormTablesGlobalSlots slots of 10 n^2 doubles, see
-// form_tables_gwork_doubles)
-constexpr size_t kFormTablesLdsMax = 150 * 1024;
-constexpr int kFormTablesGlobalSlots = 2048;
-inline long form_tables_gwork_doubles(int n) { return (long)kFormTablesGlobalSlots * 10 * n * n; }
+// apply tables from the factors (three kernels: prepare, Schur, finish)
 hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank,
                               const double* factors, double* tab64, int8_t* kinds,
-                              int32_t* status, double* gwork);
+                              int32_t* status);
 hipError_t launch_cast_tables(hipStream_t s, int64_t count, const double* t64, float* t32,
                               uint16_t* hi, uint16_t* lo, float* t2);
 hipError_t launch_frag_tables(hipStream_t s, int64_t E, const double* t64, double* f64f, float* f32f,

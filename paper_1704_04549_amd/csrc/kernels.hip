@@ -39,6 +39,7 @@ __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int ra
                                                double* ws, int64_t ws_stride) {
     __shared__ double red[4 * kMaxReduce];
     __shared__ Tables1D T;
+    extern __shared__ double small[];
     BlockTeam tm{red};
     // copy the tables once into LDS
     {
@@ -50,6 +51,7 @@ __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int ra
     }
     const bool expl = blocks != nullptr;
     SetupWork W = carve_setup_work(ws + blockIdx.x * ws_stride, dim, n, expl);
+    carve_small(small, n, expl, &W);
     const long nn = (long)n * n;
     const long nd = dim == 2 ? nn : nn * n;
     const int nf = dim == 2 ? 2 * rank : 5;
@@ -64,11 +66,13 @@ __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int ra
 }
 
 // ------------------------------------------------------- S5: apply tables
-// One wave per element; matrices in LDS (factors, the first seven tables and
-// the work arrays); the N_j are written straight to global memory.
-__global__ void __launch_bounds__(64) k_form_tables(int64_t E, int dim, int n, int rank,
-                                                    const double* factors, double* tab64,
-                                                    int8_t* kinds, int32_t* status, double* gwork) {
+// Three kernels: prepare (one wave per element: pair rotation, inverses, C1
+// and C2), Schur (one wave per (element, C matrix), with a small LDS
+// footprint so that many run per CU) and finish (one wave per element: L
+// tables, kinds, N_j).  Intermediates live in the element's own table slots.
+__global__ void __launch_bounds__(64) k_tables_prepare(int64_t E, int dim, int n, int rank,
+                                                       const double* factors, double* tab64,
+                                                       int32_t* status) {
     extern __shared__ double lds[];
     __shared__ double red[kMaxReduce];
     __shared__ double sh[kMaxN + 8];
@@ -77,18 +81,53 @@ __global__ void __launch_bounds__(64) k_form_tables(int64_t E, int dim, int n, i
     const long nn = (long)n * n;
     const int nf = dim == 2 ? 2 * rank : 5;
     const long ne = tab_entries(n);
-    double* F = lds;                 // nf n^2
-    double* tl = F + nf * nn;        // 7 n^2 (first seven tables)
-    // 10 n^2 work doubles: in LDS when they fit, else in a global slot per workgroup
-    double* work = gwork ? gwork + blockIdx.x * 10 * nn : tl + 7 * nn;
+    double* F = lds;              // nf n^2
+    double* work = F + nf * nn;   // 10 n^2
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         for (long t = threadIdx.x; t < nf * nn; t += blockDim.x) F[t] = factors[e * nf * nn + t];
         __syncthreads();
-        double* out = tab64 + e * ne;
-        // the seven n x n tables are formed in LDS, the N_j straight in global memory
-        int st = form_tables(tm, dim, n, rank, F, tl, out + 7 * nn, kinds + e * kMaxN, work, ipiv,
-                             sh);
-        for (long t = threadIdx.x; t < 7 * nn; t += blockDim.x) out[t] = tl[t];
+        double* tab = tab64 + e * ne;
+        const int st = tables_prepare(tm, dim, n, rank, F, tab, tab + 7 * nn, work, ipiv, sh);
+        if (threadIdx.x == 0) status[e] |= st;
+        __syncthreads();
+    }
+}
+
+// work item w = 2 e + i: real Schur form of C_(i+1), held in N slot i, into
+// the T_(i+1) and R_i slots
+__global__ void __launch_bounds__(64) k_tables_schur(int64_t E, int n, double* tab64,
+                                                     int32_t* status) {
+    extern __shared__ double lds[];
+    __shared__ double red[kMaxReduce];
+    __shared__ double sh[kMaxN + 8];
+    BlockTeam tm{red};
+    const long nn = (long)n * n;
+    const long ne = tab_entries(n);
+    double* H = lds;
+    double* Q = lds + nn;
+    for (int64_t w = blockIdx.x; w < 2 * E; w += gridDim.x) {
+        const int64_t e = w >> 1;
+        const int i = (int)(w & 1);
+        double* tab = tab64 + e * ne;
+        const int st = tables_schur(tm, n, tab + (7 + i) * nn, tab + (5 + i) * nn,
+                                    tab + (3 + i) * nn, H, Q, sh);
+        if (threadIdx.x == 0 && st) atomicOr(&status[e], st);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(64) k_tables_finish(int64_t E, int dim, int n, double* tab64,
+                                                      int8_t* kinds, int32_t* status) {
+    extern __shared__ double lds[];  // 6 n^2 work doubles
+    __shared__ double red[kMaxReduce];
+    __shared__ double sh[kMaxN + 8];
+    __shared__ int ipiv[kMaxN];
+    BlockTeam tm{red};
+    const long nn = (long)n * n;
+    const long ne = tab_entries(n);
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        double* tab = tab64 + e * ne;
+        const int st = tables_finish(tm, dim, n, tab, tab + 7 * nn, kinds + e * kMaxN, lds, ipiv, sh);
         if (threadIdx.x == 0) status[e] |= st;
         __syncthreads();
     }
@@ -149,27 +188,29 @@ hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int 
                         const Tables1D* tab, const double* params, const double* blocks,
                         const double* guess, double* factors, double* sigma, int32_t* status,
                         double* ws, int64_t ws_stride) {
-    hipLaunchKernelGGL(k_setup, dim3(grid), dim3(256), 0, s, E, dim, n, rank, tab, params, blocks,
+    const size_t lds = setup_small_doubles(n, blocks != nullptr) * sizeof(double);
+    hipLaunchKernelGGL(k_setup, dim3(grid), dim3(256), lds, s, E, dim, n, rank, tab, params, blocks,
                        guess, factors, sigma, status, ws, ws_stride);
     return hipGetLastError();
 }
 
 hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank,
                               const double* factors, double* tab64, int8_t* kinds,
-                              int32_t* status, double* gwork) {
+                              int32_t* status) {
+    if (E <= 0) return hipSuccess;
     const long nn = (long)n * n;
     const int nf = dim == 2 ? 2 * rank : 5;
-    int grid = (int)(E < 65536 ? E : 65536);
-    size_t lds = (nf + 17) * nn * sizeof(double);
-    if (lds > kFormTablesLdsMax) {
-        if (!gwork) return hipErrorInvalidValue;
-        lds = (nf + 7) * nn * sizeof(double);
-        if (grid > kFormTablesGlobalSlots) grid = kFormTablesGlobalSlots;
-    } else {
-        gwork = nullptr;
-    }
-    hipLaunchKernelGGL(k_form_tables, dim3(grid), dim3(64), lds, s, E, dim, n, rank, factors, tab64,
-                       kinds, status, gwork);
+    // at most (6 + 10) 32^2 doubles = 128 KiB of LDS (2D rank 3, n = 32)
+    const size_t lds = (nf + 10) * nn * sizeof(double);
+    const int grid = (int)(E < 65536 ? E : 65536);
+    hipLaunchKernelGGL(k_tables_prepare, dim3(grid), dim3(64), lds, s, E, dim, n, rank, factors,
+                       tab64, status);
+    const int64_t items = 2 * E;
+    const int grid2 = (int)(items < 65536 ? items : 65536);
+    hipLaunchKernelGGL(k_tables_schur, dim3(grid2), dim3(64), 2 * nn * sizeof(double), s, E, n,
+                       tab64, status);
+    hipLaunchKernelGGL(k_tables_finish, dim3(grid), dim3(64), 6 * nn * sizeof(double), s, E, dim, n,
+                       tab64, kinds, status);
     return hipGetLastError();
 }
 

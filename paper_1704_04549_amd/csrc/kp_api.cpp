@@ -154,13 +154,9 @@ kp_status kp_build_blocks(kp_ctx c, const kp_batch* b, double* out) {
 
 static kp_status finish_tables(kp_ctx c, const kp_batch* b, int rank, char* pc, const PcLayout& L) {
     const int64_t E = b->num_elems;
-    // global work slots for large n (the table kernel keeps its work in LDS otherwise);
-    // the setup workspace is no longer in use once the table kernel runs
-    kp_status st = ensure_ws(c, form_tables_gwork_doubles(b->n) * sizeof(double), &c->ws, &c->ws_bytes);
-    if (st != KP_OK) return st;
     KP_HIP(launch_form_tables(c->stream, E, b->dim, b->n, rank, (const double*)(pc + L.factors),
                               (double*)(pc + L.t64), (int8_t*)(pc + L.kinds),
-                              (int32_t*)(pc + L.status), (double*)c->ws));
+                              (int32_t*)(pc + L.status)));
     KP_HIP(launch_cast_tables(c->stream, E * L.ne, (const double*)(pc + L.t64), (float*)(pc + L.t32),
                               (uint16_t*)(pc + L.thi), (uint16_t*)(pc + L.tlo),
                               (float*)(pc + L.t2)));

@@ -32,9 +32,17 @@ struct HostTeam {
     int size() const { return 1; }
     void sync() const {}
     double sum(double v) const { return v; }
+    double max(double v) const { return v; }
     // reduce k partial sums in place (v[0..k)); identity on one thread
     void sum_many(double* /*v*/, int /*k*/) const {}
     bool leader() const { return true; }
+    // index of the largest |v[i*stride]| for i in [lo, hi) (lowest index on ties)
+    int argmax_abs(const double* v, int stride, int lo, int hi) const {
+        int best = lo;
+        for (int i = lo + 1; i < hi; ++i)
+            if (fabs(v[i * stride]) > fabs(v[best * stride])) best = i;
+        return best;
+    }
     // out[j] = sum_i Q[j*ldq + i] * v[i] for j < k
     void dots(const double* Q, long ldq, int k, const double* v, int len, double* out) const {
         for (int j = 0; j < k; ++j) {
@@ -70,6 +78,48 @@ struct BlockTeam {
         for (int w = 0; w < nw; ++w) s += scratch[w];
         __syncthreads();
         return s;
+    }
+    __device__ double max(double v) const {
+        const int nw = (int)(blockDim.x >> 6);
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+        if (nw == 1) return v;
+        if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double m = scratch[0];
+        for (int w = 1; w < nw; ++w) m = fmax(m, scratch[w]);
+        __syncthreads();
+        return m;
+    }
+    // index of the largest |v[i*stride]| for i in [lo, hi) (lowest index on ties);
+    // every thread gets the answer
+    __device__ int argmax_abs(const double* v, int stride, int lo, int hi) const {
+        double bv = -1.0;
+        int bi = lo;
+        for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x) {
+            const double a = fabs(v[i * stride]);
+            if (a > bv) { bv = a; bi = i; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        const int nw = (int)(blockDim.x >> 6);
+        if (nw == 1) return bi;
+        if ((threadIdx.x & 63) == 0) {
+            scratch[threadIdx.x >> 6] = bv;
+            scratch[nw + (threadIdx.x >> 6)] = (double)bi;
+        }
+        __syncthreads();
+        bv = scratch[0];
+        bi = (int)scratch[nw];
+        for (int w = 1; w < nw; ++w) {
+            const double ov = scratch[w];
+            const int oi = (int)scratch[nw + w];
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        __syncthreads();
+        return bi;
     }
     // out[j] = sum_i Q[j*ldq + i] * v[i] for j < k; one wave per dot product,
     // fixed summation order; out is visible to the whole team on return
