@@ -43,39 +43,75 @@ def parse():
     ap.add_argument("--workload", default="c4_3d_p15")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "bf16x3", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="CPU oracle sample: elements are added until this much time is spent")
+    ap.add_argument("--fixed-iters", type=int, default=0,
+                    help="profiling runs: skip the FGMRES counts and apply this many times per "
+                         "step (the line then carries no value)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 256 MiB device copy before the timed region (the "
+                         "reference dispatch that scales the HBM byte counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(w, n, dim, N_iter, sample):
-    """The oracle on `sample` elements: full-SVD KSVD + dense LU of P (setup), LU solves (apply)."""
-    import scipy.linalg as sla
+def cpu_baseline(w, n, dim, N_iter, budget_s):
+    """The oracle on a sample of elements: element block, KSVD by full SVD and
+    the Schur-form tables (setup), then N_iter Schur-route solves (apply).
+    Elements are taken evenly spread over the batch until budget_s is spent."""
     from threadpoolctl import threadpool_info
 
+    from oracle.apply import SchurPrecond
     from oracle.blocks import element_block
-    from oracle.ksvd import ksvd2d, ksvd3d, precond_matrix
+    from oracle.ksvd import ksvd2d, ksvd3d
     from oracle.tables import tables
 
     T = tables(n)
-    idx = np.linspace(0, w["num_elems"] - 1, sample).astype(int)
+    order = np.linspace(0, w["num_elems"] - 1, 64).astype(int)
     t_setup = 0.0
     t_apply = 0.0
-    for e in idx:
+    used = []
+    for e in order:
         t0 = time.perf_counter()
         A = element_block(w["params"][e], n, dim, T)
         f = ksvd3d(A, n) if dim == 3 else ksvd2d(A, n, 2)
-        lu = sla.lu_factor(precond_matrix(f))
+        pc = SchurPrecond(f)
         t1 = time.perf_counter()
-        sla.lu_solve(lu, w["rhs"][e, 0])
+        pc.solve(w["rhs"][e, 0])
         t2 = time.perf_counter()
         t_setup += t1 - t0
         t_apply += t2 - t1
-    dof = sample * n ** dim
+        used.append(int(e))
+        if t_setup + t_apply >= budget_s:
+            break
+    k = len(used)
+    dof = k * n ** dim
+    # per element: setup once, N_iter applies (one apply timed per element)
     value = dof * N_iter / (t_setup + N_iter * t_apply)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return dict(value=value, unit="DOF/s", cores=int(threads), kind="oracle",
-                sample=f"{sample} elements (indices {idx.tolist()}), setup {t_setup:.2f}s, "
-                       f"one apply {t_apply:.3f}s, N={N_iter}")
+                sample=f"{k} elements of the same batch (indices {used}): setup "
+                       f"{t_setup:.2f} s in total, one Schur-route apply per element "
+                       f"{t_apply:.3f} s in total, scaled to N={N_iter} applies per element")
+
+
+def kernel_source_hash():
+    """sha256 of the matrix-core apply kernel's source (the dominant kernel)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("apply_mfma.hip", "kp_common.h"):
+        with open(os.path.join(ROOT, "paper_1704_04549_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+# HBM bytes per apply launch from the FETCH_SIZE / WRITE_SIZE counter runs
+# (scaled by the same counters on a plain 256 MiB copy), keyed by precision;
+# valid only for the kernel source they were taken on (profiles/ holds the
+# counter summary and the commands).
+MEASURED_TRAFFIC = {
+    "source_sha256": "aeebf089a906ef8fb8f85059d8441f6401f1503503bdd2fa9a04fc96b1c58211",
+    "bytes": {"fp32": 365818656, "fp64": 462364300},
+}
 
 
 def main():
@@ -96,71 +132,72 @@ def main():
     nbr = torch.from_numpy(w["nbr"]).to(dev) if w["nbr"] is not None else None
     rhs = torch.from_numpy(np.ascontiguousarray(w["rhs"][:, 0, :])).to(dev)
     ctx = kp.Ctx(0)
+    stream = ctx.stream
     b = kp.Batch(params, dim, n, nbr=nbr)
     rank = w["rank"]
     ndof = E * n ** dim
     pc, st = ctx.setup(b, rank)
     z = torch.empty_like(rhs)
-    # iteration counts (outside the timed region)
-    out64 = ctx.fgmres(b, rhs, pc_kind=kp.KP_PC_KSVD, rank=rank, pc_data=pc, pc_prec="fp64",
-                       restart=30, rtol=1e-10, maxit=3000)
-    outv = ctx.fgmres(b, rhs, pc_kind=kp.KP_PC_KSVD, rank=rank, pc_data=pc, pc_prec=args.prec,
-                      restart=30, rtol=1e-10, maxit=3000)
-    n64, nv = out64["iters"], outv["iters"]
-    valid = outv["converged"] and out64["converged"] and nv <= n64 + 1
-
-    def step(prec, N):
-        ctx.setup(b, rank, precond=pc, status=st)
-        for _ in range(N):
-            ctx.apply(b, rank, pc, prec, rhs, z)
+    if args.calib_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.fixed_iters > 0:
+        n64 = nv = args.fixed_iters
+        valid = False
+    else:
+        # iteration counts (outside the timed region)
+        out64 = ctx.fgmres(b, rhs, pc_kind=kp.KP_PC_KSVD, rank=rank, pc_data=pc, pc_prec="fp64",
+                           restart=30, rtol=1e-10, maxit=3000)
+        outv = ctx.fgmres(b, rhs, pc_kind=kp.KP_PC_KSVD, rank=rank, pc_data=pc,
+                          pc_prec=args.prec, restart=30, rtol=1e-10, maxit=3000)
+        n64, nv = out64["iters"], outv["iters"]
+        valid = outv["converged"] and out64["converged"] and nv <= n64 + 1
 
     def timed(prec, N, K, W):
+        """W untimed steps, then K timed steps; HIP events on the library's
+        stream bracket the setup and the N applies of every timed step."""
         for _ in range(W):
-            step(prec, N)
+            ctx.setup(b, rank, precond=pc, status=st)
+            for _ in range(N):
+                ctx.apply(b, rank, pc, prec, rhs, z)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(K)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(K):
-            step(prec, N)
+        for k in range(K):
+            ev[k][0].record(stream)
+            ctx.setup(b, rank, precond=pc, status=st)
+            ev[k][1].record(stream)
+            for _ in range(N):
+                ctx.apply(b, rank, pc, prec, rhs, z)
+            ev[k][2].record(stream)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / K
+        sec = (time.perf_counter() - t0) / K
+        setup_ms = sum(e0.elapsed_time(e1) for e0, e1, _ in ev) / K
+        apply_ms = sum(e1.elapsed_time(e2) for _, e1, e2 in ev) / (K * N)
+        return sec, setup_ms, apply_ms
 
-    sec = timed(args.prec, nv, args.steps, args.warmup)
-    sec64 = timed("fp64", n64, max(3, args.steps // 4), 1)
+    sec, t_setup, t_apply = timed(args.prec, nv, args.steps, args.warmup)
+    sec64, _, t_apply64 = timed("fp64", n64, max(3, args.steps // 4), 1)
     value = ndof * nv / sec
     value64 = ndof * n64 / sec64
 
-    # per-kernel durations with HIP events on the library's stream
-    def event_ms(fn, reps):
-        s = torch.cuda.Event(enable_timing=True)
-        e = torch.cuda.Event(enable_timing=True)
-        fn()
-        s.record()
-        for _ in range(reps):
-            fn()
-        e.record()
-        torch.cuda.synchronize()
-        return s.elapsed_time(e) / reps
-
-    t_apply = event_ms(lambda: ctx.apply(b, rank, pc, args.prec, rhs, z), 20)
-    t_setup = event_ms(lambda: ctx.setup(b, rank, precond=pc, status=st), 5)
     tab_bytes = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}[args.prec]
     ne = (7 + n) * n * n
-    apply_bytes = ndof * 16 + E * ne * tab_bytes
-    apply_share = nv * t_apply / (nv * t_apply + t_setup)
-    if apply_share >= 0.5:
-        achieved = apply_bytes / (t_apply * 1e-3) / 1e9
-        roof = {"kernel": "apply", "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "ms_per_launch": round(t_apply, 4),
-                "algorithmic_bytes": int(apply_bytes)}
-    else:
-        # setup is a chain of latency-bound per-element solves; report its rate
-        rec_bytes = E * 12 * 8 + E * (4 + 5 * n * n + ne * 20)
-        achieved = rec_bytes / (t_setup * 1e-3) / 1e9
-        roof = {"kernel": "setup", "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "ms_per_launch": round(t_setup, 4),
-                "algorithmic_bytes": int(rec_bytes)}
+    # algorithmic bytes of one apply launch: r read and z written in FP64, the
+    # element's 7 + n tables read once, the block kinds
+    apply_bytes = ndof * 16 + E * ne * tab_bytes + E * 32
+    achieved = apply_bytes / (t_apply * 1e-3) / 1e9
+    traffic = None
+    if MEASURED_TRAFFIC["source_sha256"] == kernel_source_hash():
+        traffic = MEASURED_TRAFFIC["bytes"].get(args.prec)
+    roof = {"kernel": "apply (k_apply16, n=16 matrix-core path)", "bound": "hbm",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "ms_per_launch": round(t_apply, 5), "algorithmic_bytes": int(apply_bytes)}
     line = {
         "metric": METRIC,
         "value": value if valid else None,
@@ -178,18 +215,20 @@ def main():
                                f"blocks (block-diagonal system), rank 2 two-stage KSVD, "
                                f"matrix-free setup, {args.prec} apply, FP64 FGMRES(30) to 1e-10",
                    "elements": E, "dof": ndof, "precision": args.prec,
-                   "fgmres_iters": nv, "fgmres_iters_fp64": n64, "valid": valid},
+                   "fgmres_iters": nv, "fgmres_iters_fp64": n64, "valid": valid,
+                   "fixed_iters": args.fixed_iters or None},
         "fp64_value": value64,
         "speedup_vs_fp64": value / value64 if valid else None,
         "setup_ms": t_setup,
         "apply_ms": t_apply,
+        "apply_ms_fp64": t_apply64,
         "setup_dof_per_s": ndof / (t_setup * 1e-3),
         "apply_dof_per_s": ndof / (t_apply * 1e-3),
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, n, dim, nv, args.cpu_sample)
-    print(json.dumps(line))
+    if not args.no_cpu_baseline and args.fixed_iters == 0:
+        line["cpu_baseline"] = cpu_baseline(w, n, dim, nv, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
     ctx.close()
 
 
