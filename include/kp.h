@@ -143,11 +143,17 @@ kp_status kp_setup_from_factors(kp_ctx ctx, const kp_batch* b, int32_t rank,
 kp_status kp_get_factors(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* precond,
                          double* factors, double* sigma);
 
-/* S6: z = P^{-1} r per element (Alg. 6 in 2D, Alg. 8 in 3D) for nrhs
+/* z = P^{-1} r per element (Alg. 6 in 2D, Alg. 8 in 3D) for nrhs
  * right-hand sides.  r, z: [E][nrhs][n^d] FP64.  prec selects the arithmetic
  * of the contractions and the Sylvester solve (FP64, FP32, or BF16 operands
- * with FP32 accumulation).  2D rank 3 is solved by an inner Krylov iteration
- * on the three-term sum preconditioned by the rank-2 inverse. */
+ * with FP32 accumulation).
+ * 2D rank 3: the paper gives no direct inverse for more than two Kronecker
+ * terms (Sec. 4.2), so P = A1(x)B1 + A2(x)B2 + A3(x)B3 is solved per element by
+ * flexible GMRES (restart 8, at most 200 iterations, FP64 Arnoldi and
+ * Kronecker products) preconditioned by the rank-2 apply of the first two
+ * terms in precision prec, to a relative residual of 1e-13 (FP64), 1e-10
+ * (FP32), 1e-6 (BF16) or 1e-9 (split BF16).  An element that misses its
+ * target within the limit returns its last iterate. */
 kp_status kp_apply(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* precond,
                    int32_t prec, int32_t nrhs, const double* r, double* z);
 

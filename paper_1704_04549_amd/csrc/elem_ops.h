@@ -140,6 +140,30 @@ struct OpStruct2 {
         tm.sync();
     }
 
+    // y = R(A) v for a right vector v (n x n, row-major):
+    // y = diag_a( sum_K m_aK v_KK + w_a <Y, v> ) + (sum_K w_K v_KK) X
+    template <class Team>
+    KP_HD void forward(const Team& tm, const double* v, double* y) const {
+        double py = 0.0, pw = 0.0;
+        for (int t = tm.tid(); t < n * n; t += tm.size()) {
+            py += Y[t] * v[t];
+            if (t / n == t % n) pw += w[t / n] * v[t];
+        }
+        py = tm.sum(py);
+        pw = tm.sum(pw);
+        for (int t = tm.tid(); t < n * n; t += tm.size()) {
+            const int a = t / n, a2 = t % n;
+            double val = pw * X[t];
+            if (a == a2) {
+                double s = 0.0;
+                for (int K = 0; K < n; ++K) s += m[a * n + K] * v[K * n + K];
+                val += s + w[a] * py;
+            }
+            y[t] = val;
+        }
+        tm.sync();
+    }
+
     // B = R(A)^T x as a dense n x n matrix (row-major), scaled by sc
     template <class Team>
     KP_HD void right_factor(const Team& tm, const double* x, double sc, double* B) const {
@@ -274,6 +298,23 @@ struct OpStream {
             tm.sync();
         }
     }
+    // y = R(A) v for a right vector v (s x s): y[a n + a2] = sum_{K,K2} A[a s + K, a2 s + K2] v[K s + K2]
+    template <class Team>
+    KP_HD void forward(const Team& tm, const double* v, double* y) const {
+        const int m = n * n;
+        const long N = (long)n * s;
+        for (int t = tm.tid(); t < m; t += tm.size()) {
+            const int a = t / n, a2 = t % n;
+            double acc = 0.0;
+            for (int K = 0; K < s; ++K) {
+                const double* row = A + ((long)a * s + K) * N + (long)a2 * s;
+                for (int K2 = 0; K2 < s; ++K2) acc += row[K2] * v[(long)K * s + K2];
+            }
+            y[t] = acc;
+        }
+        tm.sync();
+    }
+
     // B = sc * R(A)^T x, an s x s matrix
     template <class Team>
     KP_HD void right_factor(const Team& tm, const double* x, double sc, double* B) const {
@@ -396,7 +437,9 @@ struct LanczosWork {
 
 template <class Team, class Op>
 KP_HD int lanczos_top(const Team& tm, const Op& op, int m, int r, int kmax, double tol,
-                      const LanczosWork& L, double* U /* r x m */) {
+                      const LanczosWork& L, double* U /* r x m */, bool full = false) {
+    // full: build the basis until it is invariant (beta <= 1e-14 of the scale)
+    // or kmax steps, for the two-sided refinement; the Ritz test is skipped
     double* Q = L.Q;
     // normalise the start vector
     double p = 0.0;
@@ -434,8 +477,10 @@ KP_HD int lanczos_top(const Team& tm, const Op& op, int m, int r, int kmax, doub
         }
         scale = fmax(scale, fabs(aco) + b);
         steps = k + 1;
-        const bool check = (steps >= r + 1 && ((steps % 4) == 0 || b <= 1e-10 * scale)) ||
-                           steps == kmax || steps == m || b == 0.0;
+        const bool invariant = b <= 1e-14 * scale;
+        const bool check = full ? (steps == kmax || steps == m || invariant)
+                                : (steps >= r + 1 && ((steps % 4) == 0 || b <= 1e-10 * scale)) ||
+                                      steps == kmax || steps == m || b == 0.0;
         if (check) {
             tm.sync();
             if (tm.leader()) {
@@ -471,6 +516,7 @@ KP_HD int lanczos_top(const Team& tm, const Op& op, int m, int r, int kmax, doub
                     }
                 }
                 if (b == 0.0 && rr == r) conv = ok;
+                if (full) conv = ok;
                 L.ctrl[0] = conv ? 1 : 0;
             }
             tm.sync();
@@ -1259,6 +1305,10 @@ struct SetupWork {
     double* U;      // 3 n^2 Ritz vectors
     double* d;      // n^2 operator scratch
     double* small;  // 64 doubles
+    double* Wm;     // (kmax + 16) x n^2 (rank >= 3: R^T of the Lanczos basis and the
+                    // block vectors of the refinement; the r unit right vectors at
+                    // row kmax + 10)
+    double* Vr;     // kmax x kmax (rank >= 3: accumulated Jacobi rotations)
     LanczosWork L;
 };
 constexpr int kGramMax = 64;  // explicit Gram kept when the left size n^2 <= this
@@ -1269,8 +1319,8 @@ KP_INLINE int lanczos_kmax(int n, bool expl) {
     return k < m ? k : m;
 }
 
-// number of doubles of a SetupWork for (dim, n, explicit)
-KP_INLINE long setup_work_doubles(int dim, int n, bool expl) {
+// number of doubles of a SetupWork for (dim, n, explicit, rank)
+KP_INLINE long setup_work_doubles(int dim, int n, bool expl, int rank = 2) {
     const long nn = (long)n * n;
     const long m = nn;
     const long kmax = lanczos_kmax(n, expl);
@@ -1285,10 +1335,11 @@ KP_INLINE long setup_work_doubles(int dim, int n, bool expl) {
     t += 64;                              // small
     t += (kmax + 1) * m + m + (kmax + 2) + 2 * (kmax + 1) + 2 * kmax + kmax * kmax + 3 * kmax + 3;
     t += 8;                               // ctrl (as doubles)
+    if (rank >= 3) t += (kmax + 16) * m + kmax * kmax + kmax + 8;  // Wm (+ block vectors), Vr, norms, order
     return (t + 31) / 32 * 32;
 }
 
-KP_INLINE SetupWork carve_setup_work(double* base, int dim, int n, bool expl) {
+KP_INLINE SetupWork carve_setup_work(double* base, int dim, int n, bool expl, int rank = 2) {
     const long nn = (long)n * n;
     const long m = nn;
     const long kmax = lanczos_kmax(n, expl);
@@ -1315,6 +1366,12 @@ KP_INLINE SetupWork carve_setup_work(double* base, int dim, int n, bool expl) {
     W.L.sel = p; p += 3 * kmax;
     W.L.theta = p; p += 3;
     W.L.ctrl = (int*)p; p += 8;
+    W.Wm = nullptr;
+    W.Vr = nullptr;
+    if (rank >= 3) {
+        W.Wm = p; p += (kmax + 16) * m;
+        W.Vr = p; p += kmax * kmax + kmax + 8;
+    }
     return W;
 }
 
@@ -1347,37 +1404,276 @@ KP_HD void lanczos_start(const Team& tm, double* q0, int m, const double* guess)
     tm.sync();
 }
 
+// One-sided (Hestenes) Jacobi: rotate pairs of the k columns of Wc (each of
+// length len, column c at Wc + c*len) until every pair is orthogonal to
+// 1e-15 relative; the rotations are accumulated in Vr (k x k, column c at
+// Vr + c*k, set to I here).  The disjoint pairs of one round of a round-robin
+// schedule are rotated in parallel, one group (wave) per pair.  Returns false
+// if 40 sweeps did not converge.
+template <class Team>
+KP_HD bool jacobi_orth(const Team& tm, double* Wc, int len, int k, double* Vr) {
+    for (int t = tm.tid(); t < k * k; t += tm.size()) Vr[t] = (t / k == t % k) ? 1.0 : 0.0;
+    tm.sync();
+    if (k < 2) return true;
+    const int kk = k + (k & 1);  // even player count; player k is a bye when k is odd
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        double rotated = 0.0;
+        for (int round = 0; round < kk - 1; ++round) {
+            for (int pr = tm.group(); pr < kk / 2; pr += tm.groups()) {
+                int p, q;
+                if (pr == 0) {
+                    p = kk - 1;
+                    q = round;
+                } else {
+                    p = (round + pr) % (kk - 1);
+                    q = (round - pr + kk - 1) % (kk - 1);
+                }
+                if (p >= k || q >= k) continue;
+                if (p > q) { const int t = p; p = q; q = t; }
+                double* wp = Wc + (long)p * len;
+                double* wq = Wc + (long)q * len;
+                double a = 0.0, b = 0.0, g = 0.0;
+                for (int i = tm.lane(); i < len; i += tm.group_size()) {
+                    a += wp[i] * wp[i];
+                    b += wq[i] * wq[i];
+                    g += wp[i] * wq[i];
+                }
+                a = tm.group_sum(a);
+                b = tm.group_sum(b);
+                g = tm.group_sum(g);
+                if (!(fabs(g) > 1e-15 * sqrt(a * b))) continue;
+                const double zeta = (b - a) / (2.0 * g);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                for (int i = tm.lane(); i < len; i += tm.group_size()) {
+                    const double x = wp[i], y = wq[i];
+                    wp[i] = c * x - sn * y;
+                    wq[i] = sn * x + c * y;
+                }
+                double* vp = Vr + (long)p * k;
+                double* vq = Vr + (long)q * k;
+                for (int i = tm.lane(); i < k; i += tm.group_size()) {
+                    const double x = vp[i], y = vq[i];
+                    vp[i] = c * x - sn * y;
+                    vq[i] = sn * x + c * y;
+                }
+                rotated = 1.0;
+            }
+            tm.sync();
+        }
+        if (tm.max(rotated) == 0.0) return true;
+    }
+    return false;
+}
+
+// nrm[c] = ||column c|| for the k columns of Wc; order[0..b) = the b largest (descending)
+template <class Team>
+KP_HD void column_order(const Team& tm, const double* Wc, int len, int k, int b, double* nrm,
+                        int* order) {
+    for (int j = tm.group(); j < k; j += tm.groups()) {
+        const double* wj = Wc + (long)j * len;
+        double a = 0.0;
+        for (int i = tm.lane(); i < len; i += tm.group_size()) a += wj[i] * wj[i];
+        a = tm.group_sum(a);
+        if (tm.lane() == 0) nrm[j] = sqrt(a);
+    }
+    tm.sync();
+    if (tm.leader()) {
+        for (int j = 0; j < b; ++j) {
+            int best = -1;
+            for (int i = 0; i < k; ++i) {
+                bool used = false;
+                for (int q = 0; q < j; ++q)
+                    if (order[q] == i) used = true;
+                if (!used && (best < 0 || nrm[i] > nrm[best])) best = i;
+            }
+            order[j] = best;
+        }
+    }
+    tm.sync();
+}
+
+// Accurate top-r singular triplets (rank 3).  The Ritz values of R R^T carry
+// absolute errors of order eps sigma_1^2, and the Lanczos vectors that carry
+// a small singular direction are formed from products of that size, so a
+// third singular value far below the first (down to 1e-6 sigma_1 on these
+// blocks) and its vectors lose many digits.  Two steps fix that:
+//  1. the Lanczos basis Q_k (built until invariant) is mapped to the right
+//     space, Wm = R^T Q_k, and orthogonalised by one-sided Jacobi: the b
+//     largest columns give starting triplets;
+//  2. two-sided block iteration with b = r + 2 vectors: V = orth(R^T U),
+//     U = orth(R V) by one-sided Jacobi, so that R v_i = sigma_i u_i holds as
+//     computed; each product with R or R^T has absolute error eps sigma_1
+//     only.  Iterates until ||R^T u_i - sigma_i v_i|| <= 32 eps sigma_1 for the
+//     r wanted triplets (at most 12 iterations).
+// Work: Wm (kmax + 16) x m, Vr kmax^2 + kmax + 8, Q the Lanczos basis (reused).
+// Outputs U (r x m) unit left vectors, Vout (r x m) unit right vectors, sig.
+template <class Team, class RightOp>
+KP_HD bool refine_triplets(const Team& tm, const RightOp& rop, int m, int k, double* Q, int r,
+                           double* Wm, double* Vr, double* U, double* Vout, double* sig) {
+    double* nrm = Vr + (long)k * k;                 // k
+    int* order = (int*)(Vr + (long)k * k + k);      // b ints
+    for (int j = 0; j < k; ++j) rop(tm, Q + (long)j * m, 1.0, Wm + (long)j * m);
+    bool ok = jacobi_orth(tm, Wm, m, k, Vr);
+    const int b = r + 2 < k ? r + 2 : k;
+    column_order(tm, Wm, m, k, b, nrm, order);
+    // starting left vectors Ub = Q_k p_c into rows [k, k + b) of Wm (Wm rows
+    // below k are not read again)
+    double* Ub = Wm + (long)k * m;
+    for (long t = tm.tid(); t < (long)b * m; t += tm.size()) {
+        const int j = (int)(t / m), i = (int)(t % m);
+        const int c = order[j];
+        double s = 0.0;
+        for (int q = 0; q < k; ++q) s += Q[(long)q * m + i] * Vr[(long)c * k + q];
+        Ub[t] = s;
+    }
+    tm.sync();
+    // move Ub to the front; Vb, Vn follow (Q is free from here on and serves as Tn)
+    double* U0 = Wm;
+    double* Vb = Wm + (long)b * m;
+    double* Vn = Wm + 2L * b * m;
+    double* Tn = Q;
+    for (long t = tm.tid(); t < (long)b * m; t += tm.size()) Tn[t] = Ub[t];
+    tm.sync();
+    for (long t = tm.tid(); t < (long)b * m; t += tm.size()) U0[t] = Tn[t];
+    tm.sync();
+    double* sg = nrm;   // b singular value estimates (nrm is free again)
+    int* ord = order;
+    bool conv = false;
+    for (int it = 0; it < 12 && !conv; ++it) {
+        // Vn = R^T U; residual of the previous pair (R v_i = sg_i u_i holds)
+        for (int j = 0; j < b; ++j) rop(tm, U0 + (long)j * m, 1.0, Vn + (long)j * m);
+        if (it > 0) {
+            double res = 0.0;
+            for (int j = tm.group(); j < r; j += tm.groups()) {
+                const double* vn = Vn + (long)j * m;
+                const double* vb = Vb + (long)j * m;
+                double a = 0.0;
+                for (int i = tm.lane(); i < m; i += tm.group_size()) {
+                    const double d = vn[i] - sg[j] * vb[i];
+                    a += d * d;
+                }
+                a = tm.group_sum(a);
+                res = fmax(res, sqrt(a));
+            }
+            res = tm.max(res);
+            if (res <= 32.0 * 2.220446049250313e-16 * sg[0]) conv = true;
+        }
+        if (conv) break;
+        // Vb = orth(Vn) (unit columns)
+        ok = jacobi_orth(tm, Vn, m, b, Vr) && ok;
+        column_order(tm, Vn, m, b, b, sg, ord);
+        for (long t = tm.tid(); t < (long)b * m; t += tm.size()) {
+            const int j = (int)(t / m), i = (int)(t % m);
+            const int c = ord[j];
+            Vb[t] = sg[c] > 0.0 ? Vn[(long)c * m + i] / sg[c] : 0.0;
+        }
+        tm.sync();
+        // Tn = R Vb, orthogonalise; the same rotations keep R (Vb P) = Tn P
+        for (int j = 0; j < b; ++j) rop.forward(tm, Vb + (long)j * m, Tn + (long)j * m);
+        ok = jacobi_orth(tm, Tn, m, b, Vr) && ok;
+        // Vn = Vb P
+        for (long t = tm.tid(); t < (long)b * m; t += tm.size()) {
+            const int j = (int)(t / m), i = (int)(t % m);
+            double s = 0.0;
+            for (int q = 0; q < b; ++q) s += Vb[(long)q * m + i] * Vr[(long)j * b + q];
+            Vn[t] = s;
+        }
+        tm.sync();
+        column_order(tm, Tn, m, b, b, sg, ord);
+        // sorted, normalised: U0 = Tn / sigma, Vb = Vn (both in descending order)
+        for (long t = tm.tid(); t < (long)b * m; t += tm.size()) {
+            const int j = (int)(t / m), i = (int)(t % m);
+            const int c = ord[j];
+            U0[t] = sg[c] > 0.0 ? Tn[(long)c * m + i] / sg[c] : 0.0;
+            Vb[t] = Vn[(long)c * m + i];
+        }
+        tm.sync();
+        // sg in sorted order (leader), shared
+        if (tm.leader()) {
+            double tmp[8];
+            for (int j = 0; j < b; ++j) tmp[j] = sg[ord[j]];
+            for (int j = 0; j < b; ++j) sg[j] = tmp[j];
+        }
+        tm.sync();
+    }
+    for (long t = tm.tid(); t < (long)r * m; t += tm.size()) {
+        U[t] = U0[t];
+        Vout[t] = Vb[t];
+    }
+    if (tm.leader())
+        for (int j = 0; j < r; ++j) sig[j] = sg[j];
+    tm.sync();
+    return ok && conv;
+}
+
 // 2D KSVD of a block given by an operator; writes r factor pairs (A_j, B_j)
 // and sigma_j.  Returns status bits.
-template <class Team, class Op, class RightOp>
+template <bool kRefine, class Team, class Op, class RightOp>
 KP_HD int ksvd_stage(const Team& tm, const Op& op, const RightOp& rop, int n, int r, int kmax,
                      const double* guess, SetupWork& W, double* Aout /* r n^2, stride sa */,
                      long sa, double* Bout, long sb, int sdim_right, double* sigma) {
     const int m = n * n;
     lanczos_start(tm, W.L.Q, m, guess);
+    if (kRefine && r >= 3 && W.Wm) {
+        const int ok = lanczos_top(tm, op, m, r, kmax, 1e-14, W.L, W.U, true);
+        const int k = W.L.ctrl[1];
+        double* sg = W.small;
+        double* V = W.Wm + (long)(kmax + 10) * m;
+        const bool jc = refine_triplets(tm, rop, m, k, W.L.Q, r, W.Wm, W.Vr, W.U, V, sg);
+        for (int j = 0; j < r; ++j) {
+            double* u = W.U + (long)j * m;
+            const double* v = V + (long)j * m;
+            const double sgn = canonical_sign(tm, u, m, W.L.ctrl + 2);
+            const double rs = sqrt(sg[j]);
+            if (tm.leader()) sigma[j] = sg[j];
+            for (int i = tm.tid(); i < m; i += tm.size()) {
+                Aout[j * sa + i] = rs * u[i];
+                Bout[j * sb + i] = sgn * rs * v[i];
+            }
+            tm.sync();
+        }
+        (void)sdim_right;
+        return (ok && jc) ? 0 : 1;
+    }
     const int conv = lanczos_top(tm, op, m, r, kmax, 1e-14, W.L, W.U);
     int status = conv ? 0 : 1;
     for (int j = 0; j < r; ++j) {
         double* u = W.U + (long)j * m;
         canonical_sign(tm, u, m, W.L.ctrl + 2);
-        const double th = W.L.theta[j];
-        const double sg = sqrt(th > 0.0 ? th : 0.0);
+        // sigma_j = ||R^T u_j|| rather than sqrt(theta_j): the Gram eigenvalue
+        // carries an absolute error of order eps * sigma_1^2, which would cost
+        // sigma_j relative accuracy (sigma_1 / sigma_j)^2 eps; the norm of the
+        // right vector loses only a factor sigma_1 / sigma_j.
+        double* B = Bout + j * sb;
+        rop(tm, u, 1.0, B);
+        double p = 0.0;
+        for (int i = tm.tid(); i < m; i += tm.size()) p += B[i] * B[i];
+        const double sg = sqrt(tm.sum(p));
         const double rs = sqrt(sg);
+        const double inv = rs > 0.0 ? 1.0 / rs : 0.0;
         if (tm.leader()) sigma[j] = sg;
-        for (int i = tm.tid(); i < m; i += tm.size()) Aout[j * sa + i] = rs * u[i];
+        for (int i = tm.tid(); i < m; i += tm.size()) {
+            Aout[j * sa + i] = rs * u[i];
+            B[i] *= inv;
+        }
         tm.sync();
-        rop(tm, u, rs > 0.0 ? 1.0 / rs : 0.0, Bout + j * sb);
         (void)sdim_right;
     }
     tm.sync();
     return status;
 }
 
+// R^T (operator()) and R (forward) of one block on left / right vectors
 struct RightStruct2 {
     const OpStruct2* op;
     template <class Team>
     KP_HD void operator()(const Team& tm, const double* x, double sc, double* B) const {
         op->right_factor(tm, x, sc, B);
+    }
+    template <class Team>
+    KP_HD void forward(const Team& tm, const double* v, double* y) const {
+        op->forward(tm, v, y);
     }
 };
 struct RightStream {
@@ -1385,6 +1681,10 @@ struct RightStream {
     template <class Team>
     KP_HD void operator()(const Team& tm, const double* x, double sc, double* B) const {
         op->right_factor(tm, x, sc, B);
+    }
+    template <class Team>
+    KP_HD void forward(const Team& tm, const double* v, double* y) const {
+        op->forward(tm, v, y);
     }
 };
 
@@ -1408,7 +1708,8 @@ KP_INLINE double struct3_nrm2(int n, const double* Y, const double* Z, const dou
 // ([A1,B1,A2,B2,..] in 2D, [A1,B1,C1,B2,C2] in 3D) and singular values.
 // block: the explicit block, or null for the structured (matrix-free) form
 // of rec.  guess: Lanczos start (left vector of the first stage) or null.
-template <class Team>
+// kRefine: compile the rank >= 3 refinement (2D) into this instance
+template <bool kRefine, class Team>
 KP_HD int setup_element(const Team& tm, int dim, int n, int rank, const Tables1D& T,
                         const double* rec, const double* block, const double* guess,
                         double* factors, double* sigma, SetupWork& W) {
@@ -1426,17 +1727,17 @@ KP_HD int setup_element(const Team& tm, int dim, int n, int rank, const Tables1D
             if (nn <= kGramMax) {
                 explicit_gram(tm, n, n, block, W.G);
                 OpGram og{nn, W.G};
-                status |= ksvd_stage(tm, og, rs, n, rank, kmax, guess, W, factors, 2L * nn,
+                status |= ksvd_stage<kRefine>(tm, og, rs, n, rank, kmax, guess, W, factors, 2L * nn,
                                      factors + nn, 2L * nn, n, sigma);
             } else {
-                status |= ksvd_stage(tm, st, rs, n, rank, kmax, guess, W, factors, 2L * nn,
+                status |= ksvd_stage<kRefine>(tm, st, rs, n, rank, kmax, guess, W, factors, 2L * nn,
                                      factors + nn, 2L * nn, n, sigma);
             }
         } else {
             OpStruct2 op{n, W.mass, W.Xax, W.Xax + nn, T.w, W.d, nullptr,
                          struct2_normY2(n, W.Xax + nn)};
             RightStruct2 rs{&op};
-            status |= ksvd_stage(tm, op, rs, n, rank, kmax, guess, W, factors, 2L * nn,
+            status |= ksvd_stage<kRefine>(tm, op, rs, n, rank, kmax, guess, W, factors, 2L * nn,
                                  factors + nn, 2L * nn, n, sigma);
         }
         return status;
@@ -1474,14 +1775,14 @@ KP_HD int setup_element(const Team& tm, int dim, int n, int rank, const Tables1D
         RightStream rs2{&st2};
         explicit_gram(tm, n, n, W.D1, W.G);
         OpGram og{nn, W.G};
-        status |= ksvd_stage(tm, og, rs2, n, 2, kmax2, nullptr, W, factors + nn, 2L * nn,
+        status |= ksvd_stage<false>(tm, og, rs2, n, 2, kmax2, nullptr, W, factors + nn, 2L * nn,
                              factors + 2 * nn, 2L * nn, n, sigma + 1);
     } else {
         OpStruct3 op{n, W.mass, W.Xax, W.Xax + nn, W.Xax + 2 * nn, T.w, W.d, 0.0};
         op.right_factor(tm, W.U, sc, W.m2, W.X2, W.Y2);
         OpStruct2 op2{n, W.m2, W.X2, W.Y2, T.w, W.d, nullptr, struct2_normY2(n, W.Y2)};
         RightStruct2 rs2{&op2};
-        status |= ksvd_stage(tm, op2, rs2, n, 2, kmax2, nullptr, W, factors + nn, 2L * nn,
+        status |= ksvd_stage<false>(tm, op2, rs2, n, 2, kmax2, nullptr, W, factors + nn, 2L * nn,
                              factors + 2 * nn, 2L * nn, n, sigma + 1);
     }
     return status;

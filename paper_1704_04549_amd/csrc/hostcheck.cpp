@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "elem_ops.h"
+#include "rank3.h"
 #include "tables.h"
 
 using namespace kp;
@@ -47,9 +48,10 @@ int kph_setup(int dim, int n, int rank, const double* rec, const double* block, 
     if (!make_tables(n, &t)) return -1;
     HostTeam tm;
     const bool expl = block != nullptr;
-    std::vector<double> ws(setup_work_doubles(dim, n, expl) + 64, 0.0);
-    SetupWork W = carve_setup_work(ws.data(), dim, n, expl);
-    int st = setup_element(tm, dim, n, rank, t, rec, block, guess, factors, sigma, W);
+    std::vector<double> ws(setup_work_doubles(dim, n, expl, rank) + 64, 0.0);
+    SetupWork W = carve_setup_work(ws.data(), dim, n, expl, rank);
+    int st = rank >= 3 ? setup_element<true>(tm, dim, n, rank, t, rec, block, guess, factors, sigma, W)
+                       : setup_element<false>(tm, dim, n, rank, t, rec, block, guess, factors, sigma, W);
     if (steps) *steps = W.L.ctrl[1];
     return st;
 }
@@ -94,6 +96,40 @@ int kph_apply(int dim, int n, int prec, const double* tab, const int8_t* kinds, 
         for (long i = 0; i < nd; ++i) z[i] = X[i];
     }
     return 0;
+}
+
+// rank-3 2D apply: F = A1,B1,A2,B2,A3,B3; tab / kinds = rank-2 tables.
+// Returns the inner iteration count (negative if the target was missed).
+int kph_apply_rank3(int n, int prec, const double* F, const double* tab, const int8_t* kinds,
+                    const double* r, double* z, int m) {
+    HostTeam tm;
+    const long nn = (long)n * n;
+    const long ne = tab_entries(n);
+    std::vector<double> work(rank3_work_doubles(n, m)), small(rank3_small_doubles(m));
+    const double rtol = rank3_rtol(prec);
+    if (prec == 0) {
+        std::vector<double> tw(3 * nn);
+        return rank3_solve(tm, n, F, tab, kinds, r, z, work.data(), tw.data(), small.data(), m, rtol,
+                           kRank3MaxIters, RoundNone());
+    }
+    std::vector<float> tw(3 * nn);
+    if (prec == 1) {
+        std::vector<float> tf(ne);
+        for (long i = 0; i < ne; ++i) tf[i] = (float)tab[i];
+        return rank3_solve(tm, n, F, tf.data(), kinds, r, z, work.data(), tw.data(), small.data(), m,
+                           rtol, kRank3MaxIters, RoundNone());
+    }
+    if (prec == 3) {
+        std::vector<float> tf(ne);
+        RoundBf16x2 rx;
+        for (long i = 0; i < ne; ++i) tf[i] = rx((float)tab[i]);
+        return rank3_solve(tm, n, F, tf.data(), kinds, r, z, work.data(), tw.data(), small.data(), m,
+                           rtol, kRank3MaxIters, rx);
+    }
+    std::vector<uint16_t> tb(ne);
+    for (long i = 0; i < ne; ++i) tb[i] = f32_to_bf16((float)tab[i]);
+    return rank3_solve(tm, n, F, tb.data(), kinds, r, z, work.data(), tw.data(), small.data(), m,
+                       rtol, kRank3MaxIters, RoundBf16());
 }
 
 int kph_schur(int n, const double* C, double* T, double* Q) {

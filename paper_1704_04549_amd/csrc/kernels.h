@@ -19,6 +19,12 @@ hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int 
 hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank,
                               const double* factors, double* tab64, int8_t* kinds,
                               int32_t* status);
+// rank-3 2D apply (inner flexible GMRES per element); LDS budget and restart length
+constexpr size_t kRank3LdsMax = 150 * 1024;
+int rank3_restart(int n);
+hipError_t launch_apply_rank3(hipStream_t s, int prec, int64_t E, int n, int nrhs,
+                              const double* factors, const void* tabs, int64_t tab_stride,
+                              const int8_t* kinds, const double* r, double* z);
 hipError_t launch_cast_tables(hipStream_t s, int64_t count, const double* t64, float* t32,
                               uint16_t* hi, uint16_t* lo, float* t2);
 hipError_t launch_frag_tables(hipStream_t s, int64_t E, const double* t64, double* f64f, float* f32f,

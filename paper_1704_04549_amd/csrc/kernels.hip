@@ -32,6 +32,7 @@ __global__ void __launch_bounds__(256) k_build_blocks(int64_t E, int dim, int n,
 // --------------------------------------------------------- S2-S4: setup
 // Persistent grid: workgroup g handles elements g, g + G, ... with its own
 // workspace slot.  Team = whole workgroup (256 threads).
+template <bool kRefine>
 __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int rank,
                                                const Tables1D* tab, const double* params,
                                                const double* blocks, const double* guess,
@@ -50,7 +51,7 @@ __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int ra
         __syncthreads();
     }
     const bool expl = blocks != nullptr;
-    SetupWork W = carve_setup_work(ws + blockIdx.x * ws_stride, dim, n, expl);
+    SetupWork W = carve_setup_work(ws + blockIdx.x * ws_stride, dim, n, expl, rank);
     carve_small(small, n, expl, &W);
     const long nn = (long)n * n;
     const long nd = dim == 2 ? nn : nn * n;
@@ -58,7 +59,7 @@ __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int ra
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const double* blk = expl ? blocks + e * nd * nd : nullptr;
         const double* g = guess ? guess + e * nn : nullptr;
-        int st = setup_element(tm, dim, n, rank, T, params + e * kRecLen, blk, g,
+        int st = setup_element<kRefine>(tm, dim, n, rank, T, params + e * kRecLen, blk, g,
                                factors + e * nf * nn, sigma + e * 4, W);
         if (threadIdx.x == 0) status[e] = st;
         __syncthreads();
@@ -189,7 +190,8 @@ hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int 
                         const double* guess, double* factors, double* sigma, int32_t* status,
                         double* ws, int64_t ws_stride) {
     const size_t lds = setup_small_doubles(n, blocks != nullptr) * sizeof(double);
-    hipLaunchKernelGGL(k_setup, dim3(grid), dim3(256), lds, s, E, dim, n, rank, tab, params, blocks,
+    auto kern = rank >= 3 ? k_setup<true> : k_setup<false>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, E, dim, n, rank, tab, params, blocks,
                        guess, factors, sigma, status, ws, ws_stride);
     return hipGetLastError();
 }

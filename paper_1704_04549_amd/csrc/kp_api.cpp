@@ -191,7 +191,7 @@ kp_status kp_setup(kp_ctx c, const kp_batch* b, int32_t rank, int32_t mode, void
     if ((st = get_tables(c, b->n, &T)) != KP_OK) return st;
     hipSetDevice(c->device);
     const bool expl = b->blocks != nullptr;
-    const int64_t wsd = setup_work_doubles(b->dim, b->n, expl);
+    const int64_t wsd = setup_work_doubles(b->dim, b->n, expl, rank);
     int grid = (int)(E < 2048 ? E : 2048);
     if ((st = ensure_ws(c, (size_t)wsd * grid * sizeof(double), &c->ws, &c->ws_bytes)) != KP_OK)
         return st;
@@ -255,13 +255,16 @@ kp_status kp_apply(kp_ctx c, const kp_batch* b, int32_t rank, const void* precon
     const int64_t E = b->num_elems;
     if (E == 0) return KP_OK;
     if (!precond || !r || !z) return KP_ERR_ARG;
-    if (rank == 3) return KP_ERR_UNSUPPORTED;
     const char* pc = (const char*)precond;
     const void* tabs = prec == KP_FP64   ? (const void*)(pc + L.t64)
                        : prec == KP_FP32 ? (const void*)(pc + L.t32)
                        : prec == KP_BF16 ? (const void*)(pc + L.thi)
                                          : (const void*)(pc + L.t2);
-    if (b->n == 16 && c->use_mfma16) {
+    if (rank == 3) {
+        // 2D only (pc_layout rejects rank 3 in 3D)
+        KP_HIP(launch_apply_rank3(c->stream, prec, E, b->n, nrhs, (const double*)(pc + L.factors),
+                                  tabs, L.ne, (const int8_t*)(pc + L.kinds), r, z));
+    } else if (b->n == 16 && c->use_mfma16) {
         const void* frags = prec == KP_FP64   ? (const void*)(pc + L.f64f)
                             : prec == KP_FP32 ? (const void*)(pc + L.f32f)
                             : prec == KP_BF16 ? (const void*)(pc + L.fbf)

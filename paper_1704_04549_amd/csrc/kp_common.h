@@ -36,6 +36,13 @@ struct HostTeam {
     // reduce k partial sums in place (v[0..k)); identity on one thread
     void sum_many(double* /*v*/, int /*k*/) const {}
     bool leader() const { return true; }
+    // groups: independent sub-teams (one wave each on the GPU) that reduce
+    // among themselves without a team barrier
+    int groups() const { return 1; }
+    int group() const { return 0; }
+    int lane() const { return 0; }
+    int group_size() const { return 1; }
+    double group_sum(double v) const { return v; }
     // index of the largest |v[i*stride]| for i in [lo, hi) (lowest index on ties)
     int argmax_abs(const double* v, int stride, int lo, int hi) const {
         int best = lo;
@@ -69,6 +76,11 @@ struct BlockTeam {
     __device__ int size() const { return (int)blockDim.x; }
     __device__ void sync() const { __syncthreads(); }
     __device__ bool leader() const { return threadIdx.x == 0; }
+    __device__ int groups() const { return (int)(blockDim.x >> 6); }
+    __device__ int group() const { return (int)(threadIdx.x >> 6); }
+    __device__ int lane() const { return (int)(threadIdx.x & 63); }
+    __device__ int group_size() const { return 64; }
+    __device__ double group_sum(double v) const { return wave_sum(v); }
     __device__ double sum(double v) const {
         const int nw = (int)(blockDim.x >> 6);
         v = wave_sum(v);

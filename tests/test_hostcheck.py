@@ -55,12 +55,12 @@ def test_blocks_match_oracle(lib, dim, n):
         assert np.max(np.abs(out - ref)) <= 1e-14 * np.max(np.abs(ref))
 
 
-def host_setup(lib, dim, n, rec, block):
-    nf = 4 if dim == 2 else 5
+def host_setup(lib, dim, n, rec, block, rank=2):
+    nf = 2 * rank if dim == 2 else 5
     f = np.zeros((nf, n, n))
     sig = np.zeros(4)
     steps = ctypes.c_int(0)
-    st = lib.kph_setup(dim, n, 2, P(rec), P(block) if block is not None else None, None, P(f), P(sig),
+    st = lib.kph_setup(dim, n, rank, P(rec), P(block) if block is not None else None, None, P(f), P(sig),
                        ctypes.byref(steps))
     return st, f, sig
 
@@ -78,6 +78,19 @@ def test_lanczos_setup_matches_full_svd(lib, dim, n, explicit):
         got = sig[:2] if dim == 2 else sig[:3]
         assert np.max(np.abs(got / so - 1)) <= 1e-12
         assert rel(precond_matrix(factors_from_array(f, dim)), precond_matrix(fo)) <= 1e-12
+
+
+@pytest.mark.parametrize("rank,n,explicit", [(1, 6, True), (1, 8, False), (3, 6, True),
+                                             (3, 8, False), (3, 16, False)])
+def test_lanczos_setup_rank1_rank3_2d(lib, rank, n, explicit):
+    params = synth.draw_params(3, 2, 1002)
+    for rec in params:
+        A = element_block(rec, n, 2)
+        st, f, sig = host_setup(lib, 2, n, rec, A if explicit else None, rank)
+        assert st == 0
+        fo = ksvd2d(A, n, rank)
+        assert np.max(np.abs(sig[:rank] / fo["sigma"][:rank] - 1)) <= 1e-12
+        assert rel(precond_matrix(factors_from_array(f, 2)), precond_matrix(fo)) <= 1e-12
 
 
 @pytest.mark.parametrize("n", [2, 3, 6, 16, 31])
@@ -119,3 +132,78 @@ def test_apply_all_precisions(lib, dim, n):
             Z[prec].append(z)
     for prec, tol in ((0, 1e-12), (1, 1e-5), (2, 2e-2), (3, 1e-4)):
         assert rel(np.array(Z[prec]), np.array(ZR)) <= tol, prec
+
+
+@pytest.mark.parametrize("n,m", [(6, 8), (16, 8), (16, 3)])
+def test_rank3_apply_all_precisions(lib, n, m):
+    """2D rank 3: inner flexible GMRES on the three-term sum, preconditioned by
+    the rank-2 apply, against the dense solve of the three-term P."""
+    params = synth.draw_params(6, 2, 1002)
+    rng = np.random.default_rng(5)
+    Z = {p: [] for p in range(4)}
+    ZR = []
+    for rec in params:
+        fo = ksvd2d(element_block(rec, n, 2), n, 3)
+        F = factor_array(fo)
+        assert F.shape[0] == 6
+        tab = np.zeros((7 + n) * n * n)
+        kinds = np.zeros(n, np.int8)
+        assert lib.kph_form_tables(2, n, 2, P(np.ascontiguousarray(F[:4])), P(tab), P(kinds)) == 0
+        r = rng.standard_normal(n * n)
+        ZR.append(dense_solve(fo, r))
+        for prec in range(4):
+            z = np.zeros(n * n)
+            it = lib.kph_apply_rank3(n, prec, P(F), P(tab), P(kinds), P(r), P(z), m)
+            assert it > 0, (prec, it)
+            Z[prec].append(z)
+    for prec, tol in ((0, 1e-12), (1, 1e-5), (2, 2e-2), (3, 1e-4)):
+        assert rel(np.array(Z[prec]), np.array(ZR)) <= tol, prec
+
+
+def test_rank3_zero_rhs_and_exact_rank2(lib):
+    """r = 0 gives z = 0 with no iterations; when A3 (x) B3 vanishes the first
+    preconditioned step already solves the system (FP64)."""
+    n = 6
+    fo = ksvd2d(element_block(synth.draw_params(1, 2, 7)[0], n, 2), n, 3)
+    F = factor_array(fo)
+    tab = np.zeros((7 + n) * n * n)
+    kinds = np.zeros(n, np.int8)
+    assert lib.kph_form_tables(2, n, 2, P(np.ascontiguousarray(F[:4])), P(tab), P(kinds)) == 0
+    z = np.ones(n * n)
+    assert lib.kph_apply_rank3(n, 0, P(F), P(tab), P(kinds), P(np.zeros(n * n)), P(z), 8) == 0
+    assert not z.any()
+    F0 = F.copy()
+    F0[4:] = 0.0
+    fo0 = factors_from_array(F0, 2)
+    r = np.random.default_rng(2).standard_normal(n * n)
+    it = lib.kph_apply_rank3(n, 0, P(F0), P(tab), P(kinds), P(r), P(z), 8)
+    assert 0 < it <= 2
+    assert rel(z, dense_solve(fo0, r)) <= 1e-12
+
+
+@pytest.mark.parametrize("n,explicit", [(8, True), (16, False), (16, True)])
+def test_rank3_setup_then_apply_end_to_end(lib, n, explicit):
+    """Rank-3 Lanczos setup (two-sided refinement of the third triplet), rank-2
+    tables and the inner solve against the dense solve of the oracle's rank-3
+    P: global <= 1e-12 (FP64), <= 1e-5 (FP32)."""
+    params = synth.draw_params(12, 2, 1002)
+    rng = np.random.default_rng(11)
+    Z = {0: [], 1: []}
+    ZR = []
+    for rec in params:
+        A = element_block(rec, n, 2)
+        st, f, sig = host_setup(lib, 2, n, rec, A if explicit else None, 3)
+        assert st == 0
+        fo = ksvd2d(A, n, 3)
+        assert np.max(np.abs(sig[:3] / fo["sigma"][:3] - 1)) <= 1e-12
+        tab = np.zeros((7 + n) * n * n)
+        kinds = np.zeros(n, np.int8)
+        assert lib.kph_form_tables(2, n, 2, P(np.ascontiguousarray(f[:4])), P(tab), P(kinds)) == 0
+        r = rng.standard_normal(n * n)
+        ZR.append(dense_solve(fo, r))
+        for prec in (0, 1):
+            z = np.zeros(n * n)
+            assert lib.kph_apply_rank3(n, prec, P(f), P(tab), P(kinds), P(r), P(z), 8) > 0
+            Z[prec].append(z)
+    assert rel(np.array(Z[0]), np.array(ZR)) <= 1e-12
+    assert rel(np.array(Z[1]), np.array(ZR)) <= 1e-5
