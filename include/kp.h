@@ -3,7 +3,7 @@
  * very high order DG (Pazner & Persson, arXiv 1704.04549) on AMD MI355X.
  *
  * The preconditioner approximates each element's n^d x n^d diagonal block A_k
- * of M - tau*J (Sec. 3.3) by a short Kronecker sum of n x n factors
+ * of M - tau*J (Sec. 3.4) by a short Kronecker sum of n x n factors
  * (eqs. 2d-kron-sum, 3d-simple-precond), found with the Van Loan rearrangement
  * and a top-r SVD computed by Lanczos (Sec. 4.1, Alg. 2), and inverts that sum
  * with sum-factorised n x n contractions plus a quasi-triangular Sylvester
@@ -79,7 +79,7 @@ typedef enum { KP_PC_NONE = 0, KP_PC_KSVD = 1, KP_PC_BJ = 2 } kp_pc_kind;
  *            [8..13] normal velocity u_f of the upwind flux on the faces
  *            x-, x+, y-, y+, z-, z+ (outward normal, u_f > 0 outflow),
  *            [14..15] zero.
- *            The block of element k is (Sec. 3.3, Table 1, eq. adv-kron, with
+ *            The block of element k is (Sec. 3.4, Table 1, eq. adv-kron, with
  *            collocated Gauss-Legendre quadrature on [0,1]^d):
  *              diag(w (x) w [(x) w] * c) + tau * sum_axes (beta S + nu K) on
  *              that axis (x) W on the others, c = 1 + alpha sin(pi x y [z] + phi),
@@ -116,11 +116,11 @@ const char* kp_status_string(kp_status s);
  * FP64, FP32 and BF16; kp_get_factors reads the factors back. */
 size_t kp_precond_bytes(int32_t dim, int32_t n, int32_t rank, int64_t num_elems);
 
-/* S1: materialise the explicit blocks of a batch from its records
+/* Materialise the explicit blocks of a batch from its records
  * (out: [E][n^d][n^d] row-major FP64). */
 kp_status kp_build_blocks(kp_ctx ctx, const kp_batch* b, double* out);
 
-/* S2-S5: form the preconditioner (Alg. 5 in 2D, Alg. 7 in 3D).
+/* Form the preconditioner (Alg. 5 in 2D, Alg. 7 in 3D).
  * Lanczos (Alg. 2, full reorthogonalisation) on the rearranged block R(A_k)
  * through matrix-free products (explicit blocks when b->blocks != NULL,
  * otherwise the sum-factorised products of Sec. 4.2.1 / 4.3.2 from the
@@ -132,7 +132,7 @@ kp_status kp_build_blocks(kp_ctx ctx, const kp_batch* b, double* out);
 kp_status kp_setup(kp_ctx ctx, const kp_batch* b, int32_t rank, int32_t mode,
                    void* precond, int32_t* elem_status);
 
-/* S5 only: build the apply tables from given Kronecker factors
+/* Build only the apply tables from given Kronecker factors
  * (factors: [E][nf][n][n] FP64, 2D rank r: A1,B1,A2,B2,...; 3D: A1,B1,C1,B2,C2). */
 kp_status kp_setup_from_factors(kp_ctx ctx, const kp_batch* b, int32_t rank,
                                 const double* factors, void* precond, int32_t* elem_status);
@@ -157,7 +157,7 @@ kp_status kp_get_factors(kp_ctx ctx, const kp_batch* b, int32_t rank, const void
 kp_status kp_apply(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* precond,
                    int32_t prec, int32_t nrhs, const double* r, double* z);
 
-/* S7: exact block Jacobi.  Factor every explicit block by LU with partial
+/* Exact block Jacobi.  Factor every explicit block by LU with partial
  * pivoting: lu [E][N][N] column-major per element (entry (i,j) at j*N + i;
  * unit lower triangle below the diagonal, U on and above), piv [E][N] (row
  * swapped with row k at step k), N = n^d <= 4096.  A zero pivot sets
@@ -167,11 +167,11 @@ kp_status kp_blockjacobi_exact(kp_ctx ctx, const kp_batch* b, double* lu, int32_
 kp_status kp_blockjacobi_solve(kp_ctx ctx, const kp_batch* b, const double* lu,
                                const int32_t* piv, int32_t nrhs, const double* r, double* z);
 
-/* S8: y = G x for the global operator: diagonal blocks (explicit or
+/* y = G x for the global operator: diagonal blocks (explicit or
  * matrix-free) plus the upwind inflow coupling through nbr. x, y: [E][n^d]. */
 kp_status kp_operator_apply(kp_ctx ctx, const kp_batch* b, const double* x, double* y);
 
-/* S9: FGMRES(restart) on G x = rhs from x = 0 with flexible right
+/* FGMRES(restart) on G x = rhs from x = 0 with flexible right
  * preconditioning (Sec. 5: restarted preconditioned GMRES): pc_kind KP_PC_KSVD
  * (pc_data = kp_setup buffer of this rank, applied in pc_prec), KP_PC_BJ
  * (pc_data = lu, pc_aux = piv from kp_blockjacobi_exact) or KP_PC_NONE.

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 The block is the collocated (G = I) tensor-product form of the implicit
-system's diagonal block (Sec. 3.3, implicit time integration; Table 1; the
+system's diagonal block (Sec. 3.4, implicit time integration; Table 1; the
 advection Kronecker form of Sec. 5.1, eq. adv-kron), for the scalar problem
 with element-constant velocity a = -beta, a diffusion-like term nu*K and a
 point-wise mass coefficient c:

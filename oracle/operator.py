@@ -2,9 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
-The global matrix M - tau*J (Sec. 3.3) is block-structured: one diagonal block
+The global matrix M - tau*J (Sec. 3.4) is block-structured: one diagonal block
 per element (``oracle.blocks.element_block``) plus off-diagonal blocks that
-couple neighbours through their common face (Sec. 3.3.1, the face part of
+couple neighbours through their common face (Sec. 3.4.1, the face part of
 eq. jac-entries).  The upwind flux on each face uses one normal velocity u_f
 (record entries 8..13; u_f > 0 is outflow).  On an inflow face (u_f < 0) the
 element takes the neighbour's trace: the off-diagonal block is

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 Nodal Lagrange basis on the n = p+1 Gauss-Legendre points of [0,1]
-(Sec. 3.1); quadrature on the same points (collocation, mu = p+1, Sec. 3.3):
+(Sec. 3.1); quadrature on the same points (collocation, mu = p+1, Sec. 3.1):
   W = diag(w),  D[a, j] = phi_j'(x_a)  (rows are quadrature points, Sec. 3.2),
   S = D^T W     (so u^T S v = int u' v),   K = D^T W D,
   l0[j] = phi_j(0),  l1[j] = phi_j(1).

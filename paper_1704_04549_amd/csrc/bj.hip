@@ -1,4 +1,4 @@
-// Exact block Jacobi (S7): batched LU with partial pivoting of the explicit
+// Exact block Jacobi: batched LU with partial pivoting of the explicit
 // diagonal blocks and the matching triangular solves.  The comparator of the
 // paper (Sec. 5): O(N^3) form and O(N^2) apply per element, N = n^d.
 //

@@ -18,7 +18,7 @@ namespace kp {
 
 // ============================================================ element data
 // Structured form of the synthetic element block (the collocated operator of
-// Sec. 3.3 with element-constant flux Jacobians):
+// Sec. 3.4 with element-constant flux Jacobians):
 //   A = diag(m) + sum_ax  W (x) .. (x) X_ax (x) .. (x) W,
 //   m = w (x) w [(x) w] * (1 + alpha sin(pi x y [z] + phi)),
 //   X_ax = tau*(beta_ax S + nu K) [+ tau*u_f l l^T for each outflow face f of
@@ -892,7 +892,7 @@ KP_HD bool real_schur(const Team& tm, int n, double* H, double* Q, double* sh /*
     return ok;
 }
 
-// ================================================== apply tables (S5)
+// ================================================== apply tables
 // Layout of one element's tables (entries of n x n matrices, row-major):
 //   [0] L0 [1] L1 [2] L2 [3] R0 [4] R1 [5] T1 [6] T2 [7 .. 7+n) N_j
 // 2D (P = A1 (x) B1 + A2 (x) B2): L0 = Q1^T A2^{-1}, L1 = Q2^T B1^{-1}, L2 = 0,
@@ -1160,7 +1160,7 @@ KP_HD int form_tables(const Team& tm, int dim, int n, int rank, const double* F,
     return status;
 }
 
-// ===================================================== generic apply (S6)
+// ===================================================== generic apply
 // z = P^{-1} r for one element and one right-hand side (Alg. 6 / Alg. 8):
 // contractions with L0..L(d-1) along each axis, the quasi-triangular Sylvester
 // sweep on the last two axes of every slice, contractions with R0, R1 on the
@@ -1292,7 +1292,7 @@ KP_HD void apply_tensor(const Team& tm, int dim, int n, const TT* tab, const int
 }
 
 
-// ============================================== per-element setup (S2-S4)
+// ============================================== per-element setup
 // Workspace of one element's setup (all shared by the team).
 struct SetupWork {
     double* mass;   // n^d

@@ -9,7 +9,7 @@
 
 namespace kp {
 
-// ------------------------------------------------------------ S1: blocks
+// ---------------------------------------------------------------- blocks
 // One workgroup per element: structure in LDS, then every entry of the
 // n^d x n^d block, row by row (coalesced stores).
 __global__ void __launch_bounds__(256) k_build_blocks(int64_t E, int dim, int n, const Tables1D* tab,
@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(256) k_build_blocks(int64_t E, int dim, int n,
     }
 }
 
-// --------------------------------------------------------- S2-S4: setup
+// ----------------------------------------------------------------- setup
 // Persistent grid: workgroup g handles elements g, g + G, ... with its own
 // workspace slot.  Team = whole workgroup (256 threads).
 template <bool kRefine>
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int ra
     }
 }
 
-// ------------------------------------------------------- S5: apply tables
+// ---------------------------------------------------------- apply tables
 // Three kernels: prepare (one wave per element: pair rotation, inverses, C1
 // and C2), Schur (one wave per (element, C matrix), with a small LDS
 // footprint so that many run per CU) and finish (one wave per element: L
@@ -151,7 +151,7 @@ __global__ void k_cast_tables(int64_t count, const double* t64, float* t32, uint
     }
 }
 
-// ---------------------------------------------------- S6: generic apply
+// --------------------------------------------------------- generic apply
 // One workgroup per (element, rhs); tensor in LDS, tables read from global.
 template <typename T, typename TT, class Rnd>
 __global__ void __launch_bounds__(256) k_apply_generic(int64_t E, int dim, int n, int nrhs,

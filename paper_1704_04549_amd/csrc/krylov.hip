@@ -1,9 +1,9 @@
-// Global operator (S8) and the vector kernels of FGMRES (S9).
+// Global operator and the vector kernels of FGMRES.
 //
 // The operator is the implicit system M - tau*J of the synthetic DG
 // discretisation: each element's diagonal block (explicit, or matrix-free from
 // its record) plus the upwind inflow coupling to the neighbour across every
-// inflow face (Sec. 3.3, face part of eq. jac-entries).  With one normal
+// inflow face (Sec. 3.4.1, face part of eq. jac-entries).  With one normal
 // velocity u_f per face (record entries 8..13, u_f > 0 outflow), an element takes the neighbour's trace on each inflow face f (u_f < 0): the
 // coupling block is tau*u_f (l_f l_opp^T on the face's axis) times W on the
 // other axes, l_f = l0 / l1 on the low / high face and l_opp the neighbour's

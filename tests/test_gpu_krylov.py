@@ -1,4 +1,4 @@
-"""GPU parity of the global operator (S8), exact block Jacobi (S7) and FGMRES (S9).
+"""GPU parity of the global operator, exact block Jacobi and FGMRES.
 
 Bars: operator and block-Jacobi solves within 1e-13 / 1e-12 relative of the
 oracle; FGMRES converges to rtol 1e-10 with the same solution as a dense

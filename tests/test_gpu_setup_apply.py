@@ -1,11 +1,11 @@
 """GPU parity of element source, setup and apply against the FP64 oracle.
 
 Bars (stated per result):
-  * explicit blocks (S1): max |A_gpu - A_oracle| <= 1e-13 * max|A|;
-  * singular values (S3): relative <= 1e-12;
+  * explicit blocks: max |A_gpu - A_oracle| <= 1e-13 * max|A|;
+  * singular values: relative <= 1e-12;
   * preconditioner P from GPU factors vs from oracle factors: <= 1e-12 relative
     (factors themselves are compared after aligning the joint sign of each term);
-  * apply on the oracle's factors (S5+S6): global relative error over the batch
+  * apply on the oracle's factors: global relative error over the batch
     <= 1e-12 (FP64), <= 1e-5 (FP32), <= 2e-2 (BF16);
   * setup + apply end to end (FP64): global <= 1e-12, and per element
     <= max(1e-12, 100 kappa(P) eps).

@@ -3,7 +3,7 @@
 With alpha = 0 every term of the block is an integral of a polynomial that the
 n-point Gauss rule integrates exactly (degree <= 2p in each variable), so
 v^T A u must equal the weak form (mass, tau*beta*int u dv/dx_k, tau*nu*int grad u.grad v,
-upwind outflow face terms; Sec. 3.3 and eq. weak-form) evaluated in exact
+upwind outflow face terms; Sec. 3.4 and eq. weak-form) evaluated in exact
 polynomial arithmetic on monomial coefficients.  This fixes the Kronecker
 order (x slowest), the S = D^T W orientation and the face-term convention.
 """
