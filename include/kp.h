@@ -55,7 +55,7 @@ typedef enum {
 typedef enum { KP_FP64 = 0, KP_FP32 = 1, KP_BF16 = 2, KP_BF16X3 = 3 } kp_prec;
 
 /* setup modes for kp_setup */
-typedef enum { KP_SETUP_SVD = 0, KP_SETUP_LEARNED = 1 } kp_setup_mode;
+typedef enum { KP_SETUP_SVD = 0, KP_SETUP_LEARNED = 1, KP_SETUP_LEARNED_WARM = 2 } kp_setup_mode;
 
 /* preconditioner kinds for kp_fgmres */
 typedef enum { KP_PC_NONE = 0, KP_PC_KSVD = 1, KP_PC_BJ = 2 } kp_pc_kind;
@@ -67,7 +67,7 @@ typedef enum { KP_PC_NONE = 0, KP_PC_KSVD = 1, KP_PC_BJ = 2 } kp_pc_kind;
 #define KP_ELEM_SCHUR_NOCONV 4      /* Francis QR did not converge */
 #define KP_ELEM_NONFINITE 8         /* NaN/Inf in the element's data or results */
 #define KP_ELEM_LEARNED_REJECTED 16 /* learned factors failed the acceptance test */
-#define KP_ELEM_LEARNED_WARM 32     /* learned factors used as the Lanczos start */
+#define KP_ELEM_LEARNED_WARM 32     /* the factors come from a Lanczos run started at the prediction */
 
 #define KP_REC_LEN 16
 
@@ -126,8 +126,25 @@ kp_status kp_build_blocks(kp_ctx ctx, const kp_batch* b, double* out);
  * otherwise the sum-factorised products of Sec. 4.2.1 / 4.3.2 from the
  * records), factors vec(A_j) = sqrt(sigma_j) u_j, vec(B_j) = sqrt(sigma_j) v_j,
  * then LU inverses and real Schur forms in FP64 and the apply tables.
- * mode KP_SETUP_LEARNED needs a model loaded with kp_mlp_load and is only
- * valid for dim 3; it falls back to SVD per element (KP_ELEM_LEARNED_*).
+ * mode KP_SETUP_LEARNED (rank 2, records only, a model for this dim and n
+ * attached with kp_set_model): the network's factors are kept for an
+ * element when ||A - P_pred||_F^2 <= 1.1 * proxy + 1e-12 ||A||_F^2 and
+ * ||A - P_pred||_F^2 < ||A||_F^2 (the prediction explains part of A), where
+ * the proxy is the residual of the best completion of the predicted left
+ * subspaces (one Rayleigh-Ritz step, never above the prediction's own
+ * residual; equal to the SVD residual on the SVD's subspaces), with both
+ * computed in closed form from the record.  A rejected element runs the
+ * Lanczos setup started from the predicted vec(A1) (status
+ * KP_ELEM_LEARNED_REJECTED | KP_ELEM_LEARNED_WARM), and a cold Lanczos setup
+ * if that does not converge (KP_ELEM_LEARNED_REJECTED).  For accepted
+ * elements sigma holds the Rayleigh-Ritz estimates.  A Frobenius residual
+ * close to the SVD's does not bound the spectrum of P_pred: a small change of
+ * the factors can move an eigenvalue sum of the Kronecker sum onto zero, so
+ * directly used factors can break a Krylov solve.
+ * mode KP_SETUP_LEARNED_WARM: every element runs the Lanczos setup started
+ * from the prediction (vec A1; in 3D the second stage from vec B1), status
+ * KP_ELEM_LEARNED_WARM, with the cold fallback as above (status 0); the
+ * factors are the SVD's to the Lanczos tolerance.
  * precond: kp_precond_bytes bytes.  elem_status: [E] int32, or NULL. */
 kp_status kp_setup(kp_ctx ctx, const kp_batch* b, int32_t rank, int32_t mode,
                    void* precond, int32_t* elem_status);
@@ -186,6 +203,75 @@ kp_status kp_fgmres(kp_ctx ctx, const kp_batch* b, int32_t pc_kind, int32_t rank
                     const void* pc_data, const void* pc_aux, int32_t pc_prec, const double* rhs,
                     double* x, int32_t restart, double rtol, int32_t maxit, int32_t* iters_h,
                     double* relres_h, double* hist_h, int32_t hist_len);
+
+/* ------------------------------------------------------ learned setup
+ * Not part of the paper, whose SVD setup (Sec. 4.1) stays the judge.  A small
+ * MLP maps 12 features of an element record to its Kronecker factors:
+ *   features: beta_x, beta_y, beta_z (0 in 2D), log10 nu, tau, alpha, sin phi,
+ *     cos phi, and c = 1 + alpha sin(pi x y [z] + phi) at the reference
+ *     points (1/4,1/4,1/4), (3/4,1/4,3/4), (1/4,3/4,3/4), (3/4,3/4,1/4)
+ *     (2D: the same (x, y));
+ *   xn = (features - x_mean) / x_std, h1 = silu(W1 xn + b1),
+ *   h2 = silu(W2 h1 + b2), y = W3 h2 + b3 (W1: H x 12, W2: H x H, W3: O x H,
+ *   row-major FP32; silu(z) = z / (1 + e^-z));
+ *   factors = y times a scale per factor block, O = 5 n^2 in 3D
+ *   (A1,B1,C1,B2,C2), 4 n^2 in 2D rank 2 (A1,B1,A2,B2).
+ * The model is one opaque device buffer of kp_mlp_bytes bytes holding a
+ * header, the parameters (W1,b1,W2,b2,W3,b3 in that order, P floats), the
+ * Adam moments and the normalisation.  prec for the network: KP_FP32 (FP32
+ * matrix-core GEMMs) or KP_BF16 (bf16 operands, FP32 accumulation).
+ * Training loss: mean squared error of the scaled outputs, each sample
+ * compared with the sign pattern of its target closest to the prediction
+ * among the sign changes that leave P unchanged (3D: A1 -> s0 A1,
+ * B_j -> s_j B_j, C_j -> s0 s_j C_j; 2D: (A_j, B_j) -> s_j (A_j, B_j)). */
+
+/* Bytes of a model for (dim, n) and H hidden units; 0 if unsupported. */
+size_t kp_mlp_bytes(int32_t dim, int32_t n, int32_t hidden);
+
+/* Write the header, copy params (P FP32 values, device) or zeros when NULL,
+ * clear the optimiser state, set x_mean = 0, x_std = 1, scales = 1.
+ * Synchronises. */
+kp_status kp_mlp_init(kp_ctx ctx, void* model, int32_t dim, int32_t n, int32_t hidden,
+                      const float* params);
+
+/* Copy parameters (P), x_mean (12), x_std (12), block scales (5 or 4) out of
+ * a model; any output may be NULL. */
+kp_status kp_mlp_get(kp_ctx ctx, const void* model, float* params, float* x_mean, float* x_std,
+                     float* yscale);
+
+/* Overwrite the normalisation of a model (any argument may be NULL). */
+kp_status kp_mlp_set_norm(kp_ctx ctx, void* model, const float* x_mean, const float* x_std,
+                          const float* yscale);
+
+/* y = network(xn) for rows normalised inputs xn [rows][12]; y: [rows][O]
+ * scaled outputs. */
+kp_status kp_mlp_forward(kp_ctx ctx, const void* model, int32_t prec, int64_t rows, const float* xn,
+                         float* y);
+
+/* Loss of rows samples (xn [rows][12], scaled targets t [rows][O]) and its
+ * gradient with respect to the parameters (grad: P floats, loss: 1 float,
+ * both device). */
+kp_status kp_mlp_loss_grad(kp_ctx ctx, const void* model, int32_t prec, int64_t rows, const float* xn,
+                           const float* t, float* grad, float* loss);
+
+/* Train on a batch of elements and their SVD factors (factors [E][O] FP64,
+ * the kp_get_factors layout): features and their mean / standard deviation
+ * and the per-block RMS scales of the targets are computed and stored in the
+ * model, then epochs passes of Adam (beta1 0.9, beta2 0.999, eps 1e-8,
+ * learning rate lr) over minibatches of `batch` elements in an order drawn
+ * by a splitmix64 / Fisher-Yates shuffle from seed.  loss_hist_h: host array
+ * of epochs mean minibatch losses, or NULL.  Synchronises once per epoch. */
+kp_status kp_mlp_train(kp_ctx ctx, void* model, const kp_batch* b, const double* factors,
+                       int32_t epochs, int32_t batch, float lr, uint64_t seed, int32_t prec,
+                       float* loss_hist_h);
+
+/* Predicted factors of a batch ([E][O] FP64) from its records. */
+kp_status kp_mlp_predict(kp_ctx ctx, const void* model, const kp_batch* b, int32_t prec,
+                         double* factors);
+
+/* Attach a model to the context for kp_setup(mode = KP_SETUP_LEARNED); NULL
+ * detaches.  The model must stay alive and unchanged while attached. */
+kp_status kp_set_model(kp_ctx ctx, const void* model);
 
 #ifdef __cplusplus
 }

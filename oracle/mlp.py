@@ -31,7 +31,7 @@ proxy of a prediction keeps only its left subspaces and completes them
 optimally (2D: U = orth[vec A1, vec A2], proxy = ||A||^2 - ||U^T R(A)||_F^2;
 3D: u = vec A1 / ||vec A1||, D = unvec(R(A)^T u), U2 = orth[vec B1, vec B2],
 proxy = ||A||^2 - ||U2^T R(D)||_F^2).  A prediction is accepted when
-res(pred) <= 1.1 * proxy.
+res(pred) <= 1.1 * proxy and res(pred) < ||A||^2.
 
 Pinned by tests/test_oracle_mlp.py (central differences, sign invariance of
 P and of the loss, residual identities, proxy = SVD residual on the SVD's
@@ -187,7 +187,10 @@ def proxy_residual(A: np.ndarray, farr: np.ndarray, dim: int, n: int) -> float:
 
 
 def accept(A: np.ndarray, farr: np.ndarray, dim: int, n: int, factor: float = 1.1):
-    """Acceptance test of a predicted factor stack; returns (accepted, res, proxy)."""
+    """Acceptance test of a predicted factor stack; returns (accepted, res, proxy).
+
+    A prediction that explains nothing (res >= ||A||^2) is rejected: the proxy
+    of degenerate (e.g. zero) left subspaces is ||A||^2 too."""
     res = residual(A, farr, dim)
     prox = proxy_residual(A, farr, dim, n)
-    return res <= factor * prox, res, prox
+    return (res <= factor * prox) and (res < float(np.sum(A * A))), res, prox

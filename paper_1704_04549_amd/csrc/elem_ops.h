@@ -1707,12 +1707,14 @@ KP_INLINE double struct3_nrm2(int n, const double* Y, const double* Z, const dou
 // Full setup of one element (Alg. 5 / Alg. 7, first steps): factors
 // ([A1,B1,A2,B2,..] in 2D, [A1,B1,C1,B2,C2] in 3D) and singular values.
 // block: the explicit block, or null for the structured (matrix-free) form
-// of rec.  guess: Lanczos start (left vector of the first stage) or null.
+// of rec.  guess: Lanczos start (left vector of the first stage) or null;
+// guess2: 3D only, Lanczos start of the second stage (vec B1) or null.
 // kRefine: compile the rank >= 3 refinement (2D) into this instance
 template <bool kRefine, class Team>
 KP_HD int setup_element(const Team& tm, int dim, int n, int rank, const Tables1D& T,
                         const double* rec, const double* block, const double* guess,
-                        double* factors, double* sigma, SetupWork& W) {
+                        double* factors, double* sigma, SetupWork& W,
+                        const double* guess2 = nullptr) {
     const int nn = n * n;
     const bool expl = block != nullptr;
     const int kmax = lanczos_kmax(n, expl);
@@ -1775,14 +1777,14 @@ KP_HD int setup_element(const Team& tm, int dim, int n, int rank, const Tables1D
         RightStream rs2{&st2};
         explicit_gram(tm, n, n, W.D1, W.G);
         OpGram og{nn, W.G};
-        status |= ksvd_stage<false>(tm, og, rs2, n, 2, kmax2, nullptr, W, factors + nn, 2L * nn,
+        status |= ksvd_stage<false>(tm, og, rs2, n, 2, kmax2, guess2, W, factors + nn, 2L * nn,
                              factors + 2 * nn, 2L * nn, n, sigma + 1);
     } else {
         OpStruct3 op{n, W.mass, W.Xax, W.Xax + nn, W.Xax + 2 * nn, T.w, W.d, 0.0};
         op.right_factor(tm, W.U, sc, W.m2, W.X2, W.Y2);
         OpStruct2 op2{n, W.m2, W.X2, W.Y2, T.w, W.d, nullptr, struct2_normY2(n, W.Y2)};
         RightStruct2 rs2{&op2};
-        status |= ksvd_stage<false>(tm, op2, rs2, n, 2, kmax2, nullptr, W, factors + nn, 2L * nn,
+        status |= ksvd_stage<false>(tm, op2, rs2, n, 2, kmax2, guess2, W, factors + nn, 2L * nn,
                              factors + 2 * nn, 2L * nn, n, sigma + 1);
     }
     return status;

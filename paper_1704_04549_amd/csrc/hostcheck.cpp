@@ -10,6 +10,7 @@
 
 #include "elem_ops.h"
 #include "rank3.h"
+#include "learned.h"
 #include "tables.h"
 
 using namespace kp;
@@ -130,6 +131,17 @@ int kph_apply_rank3(int n, int prec, const double* F, const double* tab, const i
     for (long i = 0; i < ne; ++i) tb[i] = f32_to_bf16((float)tab[i]);
     return rank3_solve(tm, n, F, tb.data(), kinds, r, z, work.data(), tw.data(), small.data(), m,
                        rtol, kRank3MaxIters, RoundBf16());
+}
+
+// acceptance test of predicted factors: out[0..6) = res, proxy, ||A||^2, sigma estimates
+int kph_learned_check(int dim, int n, const double* rec, const double* F, double factor, double* out) {
+    Tables1D t;
+    if (!make_tables(n, &t)) return -1;
+    HostTeam tm;
+    const long nn = (long)n * n;
+    const long nd = dim == 2 ? nn : nn * n;
+    std::vector<double> mass(nd), Xax(3 * nn), work(8 * nn + n);
+    return learned_check(tm, dim, n, t, rec, F, mass.data(), Xax.data(), work.data(), factor, out) ? 1 : 0;
 }
 
 int kph_schur(int n, const double* C, double* T, double* Q) {

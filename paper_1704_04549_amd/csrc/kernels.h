@@ -14,7 +14,20 @@ hipError_t launch_build_blocks(hipStream_t s, int64_t E, int dim, int n, const T
 hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int rank,
                         const Tables1D* tab, const double* params, const double* blocks,
                         const double* guess, double* factors, double* sigma, int32_t* status,
-                        double* ws, int64_t ws_stride);
+                        double* ws, int64_t ws_stride, const int32_t* skip = nullptr,
+                        int32_t status_or = 0);
+// learned setup: per-element acceptance of predicted factors (in `factors`);
+// accept[e] = 1 keeps them; guess[e] = vec A1 (and vec B1 in 3D) for a warm
+// Lanczos start ([E][2 or 1][n^2])
+hipError_t launch_learned_check(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                                const double* params, const double* factors, double* sigma,
+                                int32_t* status, double* guess, int32_t* accept, double factor);
+// guess[e] = vec A1 (and vec B1 in 3D) of predicted factors: [E][2 or 1][n^2]; accept[e] = 0
+hipError_t launch_learned_guess(hipStream_t s, int64_t E, int dim, int n, const double* factors,
+                                double* guess, int32_t* accept);
+// skip[e] = accept[e] || !(status[e] & KP_ELEM_LANCZOS_NOCONV)
+hipError_t launch_fallback_mask(hipStream_t s, int64_t E, const int32_t* accept, const int32_t* status,
+                                int32_t* skip);
 // apply tables from the factors (three kernels: prepare, Schur, finish)
 hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank,
                               const double* factors, double* tab64, int8_t* kinds,

@@ -37,7 +37,8 @@ __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int ra
                                                const Tables1D* tab, const double* params,
                                                const double* blocks, const double* guess,
                                                double* factors, double* sigma, int32_t* status,
-                                               double* ws, int64_t ws_stride) {
+                                               double* ws, int64_t ws_stride, const int32_t* skip,
+                                               int32_t status_or) {
     __shared__ double red[4 * kMaxReduce];
     __shared__ Tables1D T;
     extern __shared__ double small[];
@@ -57,11 +58,15 @@ __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int ra
     const long nd = dim == 2 ? nn : nn * n;
     const int nf = dim == 2 ? 2 * rank : 5;
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        if (skip && skip[e]) continue;  // uniform across the workgroup
         const double* blk = expl ? blocks + e * nd * nd : nullptr;
-        const double* g = guess ? guess + e * nn : nullptr;
+        // guesses: [E][gs][n^2], gs = 2 in 3D (stage-1 and stage-2 starts), 1 in 2D
+        const long gs = dim == 3 ? 2 : 1;
+        const double* g = guess ? guess + e * gs * nn : nullptr;
+        const double* g2 = (guess && dim == 3) ? g + nn : nullptr;
         int st = setup_element<kRefine>(tm, dim, n, rank, T, params + e * kRecLen, blk, g,
-                               factors + e * nf * nn, sigma + e * 4, W);
-        if (threadIdx.x == 0) status[e] = st;
+                               factors + e * nf * nn, sigma + e * 4, W, g2);
+        if (threadIdx.x == 0) status[e] = st | status_or;
         __syncthreads();
     }
 }
@@ -188,11 +193,11 @@ hipError_t launch_build_blocks(hipStream_t s, int64_t E, int dim, int n, const T
 hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int rank,
                         const Tables1D* tab, const double* params, const double* blocks,
                         const double* guess, double* factors, double* sigma, int32_t* status,
-                        double* ws, int64_t ws_stride) {
+                        double* ws, int64_t ws_stride, const int32_t* skip, int32_t status_or) {
     const size_t lds = setup_small_doubles(n, blocks != nullptr) * sizeof(double);
     auto kern = rank >= 3 ? k_setup<true> : k_setup<false>;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, E, dim, n, rank, tab, params, blocks,
-                       guess, factors, sigma, status, ws, ws_stride);
+                       guess, factors, sigma, status, ws, ws_stride, skip, status_or);
     return hipGetLastError();
 }
 

@@ -14,72 +14,9 @@
 #include "krylov.h"
 #include "layout.h"
 #include "tables.h"
+#include "ctx_internal.h"
 
 using namespace kp;
-
-struct kp_ctx_s {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    Tables1D* d_tables[kMaxN + 1] = {};
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    int num_cus = 256;
-    // FGMRES / operator scratch
-    void* ks = nullptr;
-    size_t ks_bytes = 0;
-    // matrix-core apply for n = 16 (KP_APPLY_GENERIC=1 in the environment selects
-    // the generic per-element kernel instead, for comparison)
-    bool use_mfma16 = true;
-};
-
-#define KP_HIP(call)                                   \
-    do {                                               \
-        hipError_t err_ = (call);                      \
-        if (err_ != hipSuccess) return KP_ERR_HIP;     \
-    } while (0)
-
-static kp_status ensure_ws(kp_ctx c, size_t bytes, void** slot, size_t* cap) {
-    if (*cap >= bytes && *slot) return KP_OK;
-    if (*slot) {
-        if (hipStreamSynchronize(c->stream) != hipSuccess) return KP_ERR_HIP;
-        hipFree(*slot);
-        *slot = nullptr;
-        *cap = 0;
-    }
-    size_t want = bytes + bytes / 8 + 256;
-    if (hipMalloc(slot, want) != hipSuccess) {
-        *slot = nullptr;
-        return KP_ERR_ALLOC;
-    }
-    *cap = want;
-    return KP_OK;
-}
-
-static kp_status get_tables(kp_ctx c, int n, const Tables1D** out) {
-    if (n < 2 || n > kMaxN) return KP_ERR_ARG;
-    if (!c->d_tables[n]) {
-        Tables1D h;
-        if (!make_tables(n, &h)) return KP_ERR_ARG;
-        Tables1D* d = nullptr;
-        if (hipMalloc((void**)&d, sizeof(Tables1D)) != hipSuccess) return KP_ERR_ALLOC;
-        if (hipMemcpy(d, &h, sizeof(Tables1D), hipMemcpyHostToDevice) != hipSuccess) {
-            hipFree(d);
-            return KP_ERR_HIP;
-        }
-        c->d_tables[n] = d;
-    }
-    *out = c->d_tables[n];
-    return KP_OK;
-}
-
-static kp_status check_batch(const kp_batch* b, bool need_params = true) {
-    if (!b) return KP_ERR_ARG;
-    if (b->num_elems < 0) return KP_ERR_ARG;
-    if (b->dim != 2 && b->dim != 3) return KP_ERR_ARG;
-    if (b->n < 2 || b->n > kMaxN) return KP_ERR_ARG;
-    if (need_params && !b->params && b->num_elems > 0) return KP_ERR_ARG;
-    return KP_OK;
-}
 
 extern "C" {
 
@@ -124,6 +61,7 @@ kp_status kp_destroy(kp_ctx c) {
         if (c->d_tables[n]) hipFree(c->d_tables[n]);
     if (c->ws) hipFree(c->ws);
     if (c->ks) hipFree(c->ks);
+    if (c->mw) hipFree(c->mw);
     delete c;
     return KP_OK;
 }
@@ -183,8 +121,14 @@ kp_status kp_setup(kp_ctx c, const kp_batch* b, int32_t rank, int32_t mode, void
     PcLayout L;
     if (!pc_layout(b->dim, b->n, rank, b->num_elems, &L)) return KP_ERR_ARG;
     if (!precond && b->num_elems > 0) return KP_ERR_ARG;
-    if (mode != KP_SETUP_SVD) return KP_ERR_UNSUPPORTED;
+    if (mode != KP_SETUP_SVD && mode != KP_SETUP_LEARNED && mode != KP_SETUP_LEARNED_WARM)
+        return KP_ERR_ARG;
     if (b->dim == 3 && b->blocks && b->n * b->n > 64) return KP_ERR_UNSUPPORTED;
+    if (mode != KP_SETUP_SVD) {
+        // a model for this (dim, n), rank 2, records only
+        if (!c->model || c->model_dim != b->dim || c->model_n != b->n) return KP_ERR_ARG;
+        if (rank != 2 || b->blocks) return KP_ERR_UNSUPPORTED;
+    }
     const int64_t E = b->num_elems;
     if (E == 0) return KP_OK;
     const Tables1D* T;
@@ -196,9 +140,42 @@ kp_status kp_setup(kp_ctx c, const kp_batch* b, int32_t rank, int32_t mode, void
     if ((st = ensure_ws(c, (size_t)wsd * grid * sizeof(double), &c->ws, &c->ws_bytes)) != KP_OK)
         return st;
     char* pc = (char*)precond;
-    KP_HIP(launch_setup(c->stream, grid, E, b->dim, b->n, rank, T, b->params, b->blocks, nullptr,
-                        (double*)(pc + L.factors), (double*)(pc + L.sigma),
-                        (int32_t*)(pc + L.status), (double*)c->ws, wsd));
+    double* factors = (double*)(pc + L.factors);
+    double* sigma = (double*)(pc + L.sigma);
+    int32_t* status = (int32_t*)(pc + L.status);
+    if (mode == KP_SETUP_SVD) {
+        KP_HIP(launch_setup(c->stream, grid, E, b->dim, b->n, rank, T, b->params, b->blocks, nullptr,
+                            factors, sigma, status, (double*)c->ws, wsd));
+    } else {
+        // 1. predicted factors straight into the factor section
+        if ((st = kp_mlp_predict(c, c->model, b, KP_FP32, factors)) != KP_OK) return st;
+        // 2. acceptance test (LEARNED) or none (LEARNED_WARM); the Lanczos
+        //    starts vec A1 (and vec B1 in 3D) come from the prediction
+        const size_t nn = (size_t)b->n * b->n;
+        const size_t gs = b->dim == 3 ? 2 : 1;
+        if ((st = ensure_ws(c, E * gs * nn * sizeof(double) + 2 * E * sizeof(int32_t) + 1024, &c->ks,
+                            &c->ks_bytes)) != KP_OK)
+            return st;
+        double* guess = (double*)c->ks;
+        int32_t* accept = (int32_t*)(guess + E * gs * nn);
+        int32_t* skip = accept + E;
+        const bool direct = mode == KP_SETUP_LEARNED;
+        if (direct) {
+            KP_HIP(launch_learned_check(c->stream, E, b->dim, b->n, T, b->params, factors, sigma, status,
+                                        guess, accept, 1.1));
+        } else {
+            KP_HIP(launch_learned_guess(c->stream, E, b->dim, b->n, factors, guess, accept));
+        }
+        // 3. warm-started Lanczos for the elements not accepted
+        const int32_t warm_bits = (direct ? KP_ELEM_LEARNED_REJECTED : 0) | KP_ELEM_LEARNED_WARM;
+        KP_HIP(launch_setup(c->stream, grid, E, b->dim, b->n, rank, T, b->params, nullptr, guess, factors,
+                            sigma, status, (double*)c->ws, wsd, direct ? accept : nullptr, warm_bits));
+        // 4. cold SVD where the warm start did not converge
+        KP_HIP(launch_fallback_mask(c->stream, E, accept, status, skip));
+        KP_HIP(launch_setup(c->stream, grid, E, b->dim, b->n, rank, T, b->params, nullptr, nullptr,
+                            factors, sigma, status, (double*)c->ws, wsd, skip,
+                            direct ? KP_ELEM_LEARNED_REJECTED : 0));
+    }
     if ((st = finish_tables(c, b, rank, pc, L)) != KP_OK) return st;
     return copy_status(c, b, pc, L, elem_status);
 }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libkp.so")
 
 KP_OK, KP_ERR_ARG, KP_ERR_ALLOC, KP_ERR_HIP, KP_ERR_NUMERIC, KP_ERR_NOCONV, KP_ERR_UNSUPPORTED = range(7)
 KP_FP64, KP_FP32, KP_BF16, KP_BF16X3 = 0, 1, 2, 3
-KP_SETUP_SVD, KP_SETUP_LEARNED = 0, 1
+KP_SETUP_SVD, KP_SETUP_LEARNED, KP_SETUP_LEARNED_WARM = 0, 1, 2
 KP_PC_NONE, KP_PC_KSVD, KP_PC_BJ = 0, 1, 2
 ELEM_LANCZOS_NOCONV, ELEM_SINGULAR_FACTOR, ELEM_SCHUR_NOCONV, ELEM_NONFINITE = 1, 2, 4, 8
 ELEM_LEARNED_REJECTED, ELEM_LEARNED_WARM = 16, 32
@@ -65,6 +65,16 @@ def lib() -> ctypes.CDLL:
             "kp_operator_apply": ([vp, bp, vp, vp], ctypes.c_int),
             "kp_fgmres": ([vp, bp, i32, i32, vp, vp, i32, vp, vp, i32, dbl, i32,
                            ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, i32], ctypes.c_int),
+            "kp_mlp_bytes": ([i32, i32, i32], ctypes.c_size_t),
+            "kp_mlp_init": ([vp, vp, i32, i32, i32, vp], ctypes.c_int),
+            "kp_mlp_get": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+            "kp_mlp_set_norm": ([vp, vp, vp, vp, vp], ctypes.c_int),
+            "kp_mlp_forward": ([vp, vp, i32, i64, vp, vp], ctypes.c_int),
+            "kp_mlp_loss_grad": ([vp, vp, i32, i64, vp, vp, vp, vp], ctypes.c_int),
+            "kp_mlp_train": ([vp, vp, bp, vp, i32, i32, ctypes.c_float, ctypes.c_uint64, i32, vp],
+                             ctypes.c_int),
+            "kp_mlp_predict": ([vp, vp, bp, i32, vp], ctypes.c_int),
+            "kp_set_model": ([vp, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -238,3 +248,66 @@ class Ctx:
             raise KpError(st, "kp_fgmres")
         return dict(x=x, iters=it.value, relres=rr.value, converged=(st == KP_OK),
                     hist=list(hist)[:min(hist_len, it.value)])
+
+    # ------------------------------------------------------ learned setup
+    def mlp_param_count(self, dim, n, hidden):
+        O = (5 if dim == 3 else 4) * n * n
+        return hidden * 12 + hidden + hidden * hidden + hidden + O * hidden + O
+
+    def mlp_create(self, dim, n, hidden, params=None):
+        """A model buffer initialised with params (FP32 device tensor of P values) or zeros."""
+        nbytes = int(lib().kp_mlp_bytes(dim, n, hidden))
+        if nbytes == 0:
+            raise KpError(KP_ERR_ARG, "kp_mlp_bytes")
+        model = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if params is not None and (params.dtype != torch.float32 or
+                                   params.numel() != self.mlp_param_count(dim, n, hidden)):
+            raise ValueError("params: float32 tensor of the model's parameter count expected")
+        _check(lib().kp_mlp_init(self.h, _ptr(model), dim, n, hidden, _ptr(params)), "kp_mlp_init")
+        return model
+
+    def mlp_get(self, model, dim, n, hidden):
+        P = self.mlp_param_count(dim, n, hidden)
+        params = torch.empty(P, dtype=torch.float32, device=self.device)
+        xm = torch.empty(12, dtype=torch.float32, device=self.device)
+        xs = torch.empty(12, dtype=torch.float32, device=self.device)
+        ys = torch.empty(5 if dim == 3 else 4, dtype=torch.float32, device=self.device)
+        _check(lib().kp_mlp_get(self.h, _ptr(model), _ptr(params), _ptr(xm), _ptr(xs), _ptr(ys)), "kp_mlp_get")
+        return params, xm, xs, ys
+
+    def mlp_set_norm(self, model, x_mean=None, x_std=None, yscale=None):
+        _check(lib().kp_mlp_set_norm(self.h, _ptr(model), _ptr(x_mean), _ptr(x_std), _ptr(yscale)),
+               "kp_mlp_set_norm")
+
+    def mlp_forward(self, model, xn, out_dim, prec="fp32"):
+        prec = PREC.get(prec, prec)
+        y = torch.empty((xn.shape[0], out_dim), dtype=torch.float32, device=self.device)
+        _check(lib().kp_mlp_forward(self.h, _ptr(model), int(prec), int(xn.shape[0]), _ptr(xn), _ptr(y)),
+               "kp_mlp_forward")
+        return y
+
+    def mlp_loss_grad(self, model, xn, t, n_params, prec="fp32"):
+        prec = PREC.get(prec, prec)
+        g = torch.empty(n_params, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(lib().kp_mlp_loss_grad(self.h, _ptr(model), int(prec), int(xn.shape[0]), _ptr(xn), _ptr(t),
+                                      _ptr(g), _ptr(loss)), "kp_mlp_loss_grad")
+        return loss, g
+
+    def mlp_train(self, model, b: Batch, factors, epochs, batch=256, lr=1e-3, seed=3004, prec="fp32"):
+        prec = PREC.get(prec, prec)
+        hist = (ctypes.c_float * max(epochs, 1))()
+        _check(lib().kp_mlp_train(self.h, _ptr(model), ctypes.byref(b.c), _ptr(factors), int(epochs),
+                                  int(batch), float(lr), int(seed), int(prec), hist), "kp_mlp_train")
+        return list(hist)[:epochs]
+
+    def mlp_predict(self, model, b: Batch, prec="fp32"):
+        prec = PREC.get(prec, prec)
+        f = torch.empty((b.num_elems, 5 if b.dim == 3 else 4, b.n, b.n), dtype=torch.float64,
+                        device=self.device)
+        _check(lib().kp_mlp_predict(self.h, _ptr(model), ctypes.byref(b.c), int(prec), _ptr(f)),
+               "kp_mlp_predict")
+        return f
+
+    def set_model(self, model):
+        _check(lib().kp_set_model(self.h, _ptr(model)), "kp_set_model")

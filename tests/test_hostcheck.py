@@ -207,3 +207,35 @@ def test_rank3_setup_then_apply_end_to_end(lib, n, explicit):
             Z[prec].append(z)
     assert rel(np.array(Z[0]), np.array(ZR)) <= 1e-12
     assert rel(np.array(Z[1]), np.array(ZR)) <= 1e-5
+
+
+@pytest.mark.parametrize("dim,n,face", [(2, 6, False), (2, 8, True), (3, 4, True), (3, 5, False)])
+def test_learned_check_matches_oracle_residual_and_proxy(lib, dim, n, face):
+    """Closed-form residual ||A - P||^2 and the Rayleigh-Ritz proxy of the
+    learned-setup acceptance test against the oracle's dense definitions, on
+    SVD factors (accepted, proxy = residual) and on perturbed factors."""
+    from oracle import mlp as omlp
+    params = synth.draw_params(4, dim, 41, face=face)
+    rng = np.random.default_rng(7)
+    lib.kph_learned_check.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_double, ctypes.c_void_p]
+    for rec in params:
+        A = element_block(rec, n, dim)
+        fo = ksvd2d(A, n, 2) if dim == 2 else ksvd3d(A, n)
+        F = factor_array(fo)
+        for pert in (0.0, 0.02, 0.3):
+            Fp = np.ascontiguousarray(F + pert * rng.standard_normal(F.shape) * np.abs(F).max())
+            out = np.zeros(8)
+            ok = lib.kph_learned_check(dim, n, P(rec), P(Fp), 1.1, P(out))
+            a2 = np.sum(A * A)
+            assert out[2] == pytest.approx(a2, rel=1e-13)
+            res = omlp.residual(A, Fp, dim)
+            prox = omlp.proxy_residual(A, Fp, dim, n)
+            assert abs(out[0] - res) <= 1e-12 * a2
+            assert abs(out[1] - prox) <= 1e-12 * a2
+            assert ok == int(res <= 1.1 * prox + 1e-12 * a2 and res < a2)
+            if pert == 0.0:
+                assert ok == 1
+        # an all-zero prediction explains nothing and is rejected (its proxy is ||A||^2 too)
+        out = np.zeros(8)
+        assert lib.kph_learned_check(dim, n, P(rec), P(np.zeros_like(F)), 1.1, P(out)) == 0
