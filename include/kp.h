@@ -204,6 +204,58 @@ kp_status kp_fgmres(kp_ctx ctx, const kp_batch* b, int32_t pc_kind, int32_t rank
                     double* x, int32_t restart, double rtol, int32_t maxit, int32_t* iters_h,
                     double* relres_h, double* hist_h, int32_t hist_len);
 
+/* ------------------------------------------------------ mixed batches
+ * Elements of different dimension and degree in one batch (records
+ * [E][16] as for kp_batch, block-diagonal: no face coupling).  Vectors are
+ * packed in element order: element e holds its n_e^d_e values after those of
+ * the elements before it.  A plan holds the layout and the per-element
+ * descriptors that let one persistent launch serve the whole batch; the
+ * setup, the apply and the block-diagonal operator each take one launch
+ * (the setup also runs the three table kernels and the precision copies).
+ * Rank 2 (2D) and the two-stage rank-2 form (3D), SVD setup. */
+typedef struct kp_mixed_plan_s* kp_mixed_plan;
+
+/* dim_n_h: host [E][2] = (dim, n) per element, dim 2 or 3, 2 <= n <= 32.
+ * Allocates the plan's device descriptors (owned by the plan). */
+kp_status kp_mixed_plan_create(kp_ctx ctx, int64_t num_elems, const int32_t* dim_n_h, kp_mixed_plan* plan);
+kp_status kp_mixed_plan_destroy(kp_mixed_plan plan);
+
+/* Packed vector length (sum of n_e^d_e) and preconditioner bytes. */
+kp_status kp_mixed_plan_info(kp_mixed_plan plan, int64_t* vec_len_h, size_t* precond_bytes_h);
+
+/* Setup of every element (Alg. 5 / Alg. 7 with its own n); elem_status [E] or NULL. */
+kp_status kp_mixed_setup(kp_ctx ctx, kp_mixed_plan plan, const double* params, void* precond,
+                         int32_t* elem_status);
+
+/* Factors (packed: 4 n_e^2 doubles per 2D element, 5 n_e^2 per 3D element, in
+ * element order) and sigma [E][4]; either may be NULL. */
+kp_status kp_mixed_get_factors(kp_ctx ctx, kp_mixed_plan plan, const void* precond, double* factors,
+                               double* sigma);
+
+/* z = P^{-1} r for every element in one launch (r, z packed). */
+kp_status kp_mixed_apply(kp_ctx ctx, kp_mixed_plan plan, const void* precond, int32_t prec,
+                         const double* r, double* z);
+
+/* Autotune the apply launch: for every (dim, n) in the batch, time its
+ * elements applied by a whole workgroup each and by one wave each (four per
+ * workgroup), keep the faster, and rebuild the plan's work list.  r and z
+ * are used as scratch (z is overwritten).  modes_h (or NULL): triples
+ * (dim, n, mode 0 workgroup / 1 wave), -1 after the last.  Synchronises. */
+kp_status kp_mixed_autotune(kp_ctx ctx, kp_mixed_plan plan, const void* precond, int32_t prec,
+                            const double* r, double* z, int32_t* modes_h, int32_t modes_len);
+
+/* y = blockdiag(A_e) x from the records (packed vectors). */
+kp_status kp_mixed_operator_apply(kp_ctx ctx, kp_mixed_plan plan, const double* params, const double* x,
+                                  double* y);
+
+/* FGMRES(restart) on the block-diagonal system of the batch, as kp_fgmres;
+ * pc_kind KP_PC_KSVD (precond from kp_mixed_setup, applied in pc_prec) or
+ * KP_PC_NONE. */
+kp_status kp_mixed_fgmres(kp_ctx ctx, kp_mixed_plan plan, const double* params, int32_t pc_kind,
+                          const void* precond, int32_t pc_prec, const double* rhs, double* x,
+                          int32_t restart, double rtol, int32_t maxit, int32_t* iters_h, double* relres_h,
+                          double* hist_h, int32_t hist_len);
+
 /* ------------------------------------------------------ learned setup
  * Not part of the paper, whose SVD setup (Sec. 4.1) stays the judge.  A small
  * MLP maps 12 features of an element record to its Kronecker factors:

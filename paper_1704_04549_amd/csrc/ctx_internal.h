@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include <functional>
+
 #include "../../include/kp.h"
 #include "tables.h"
 
@@ -79,3 +81,9 @@ static inline kp_status check_batch(const kp_batch* b, bool need_params = true) 
     return KP_OK;
 }
 
+
+// a device-vector map (operator or preconditioner) for the FGMRES driver
+typedef std::function<kp_status(const double*, double*)> VecFn;
+kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, const double* rhs, double* x,
+                      int32_t restart, double rtol, int32_t maxit, int32_t* iters_h, double* relres_h,
+                      double* hist_h, int32_t hist_len);

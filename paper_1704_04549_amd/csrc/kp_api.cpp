@@ -313,20 +313,15 @@ static kp_status fg_precond(kp_ctx c, const kp_batch* b, int pc_kind, int rank, 
     return KP_OK;
 }
 
-kp_status kp_fgmres(kp_ctx c, const kp_batch* b, int32_t pc_kind, int32_t rank, const void* pc_data,
-                    const void* pc_aux, int32_t pc_prec, const double* rhs, double* x,
-                    int32_t restart, double rtol, int32_t maxit, int32_t* iters_h, double* relres_h,
-                    double* hist_h, int32_t hist_len) {
-    if (!c) return KP_ERR_ARG;
-    kp_status st = check_batch(b);
-    if (st != KP_OK) return st;
-    if (!rhs || !x || restart < 1 || restart > 200 || maxit < 1 || !(rtol > 0.0)) return KP_ERR_ARG;
-    if (pc_kind < KP_PC_NONE || pc_kind > KP_PC_BJ) return KP_ERR_ARG;
-    if (pc_kind != KP_PC_NONE && !pc_data) return KP_ERR_ARG;
-    if (pc_kind == KP_PC_BJ && !pc_aux) return KP_ERR_ARG;
-    const int64_t E = b->num_elems;
-    const int nd = b->dim == 2 ? b->n * b->n : b->n * b->n * b->n;
-    const int64_t N = E * nd;
+}  // extern "C"
+
+// FGMRES(restart) from x = 0 on N unknowns with the operator op and the
+// preconditioner pc (each maps a device vector to another); the driver of
+// kp_fgmres and kp_mixed_fgmres.
+kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, const double* rhs, double* x,
+                      int32_t restart, double rtol, int32_t maxit, int32_t* iters_h, double* relres_h,
+                      double* hist_h, int32_t hist_len) {
+    kp_status st;
     const int m = restart;
     if (iters_h) *iters_h = 0;
     if (relres_h) *relres_h = 0.0;
@@ -352,7 +347,7 @@ kp_status kp_fgmres(kp_ctx c, const kp_batch* b, int32_t pc_kind, int32_t rank, 
     KP_HIP(hipMemcpyAsync(&nb2, hd, sizeof(double), hipMemcpyDeviceToHost, s));
     KP_HIP(hipStreamSynchronize(s));
     const double nb = sqrt(nb2);
-    KP_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
+    KP_HIP(launch_axpby(s, x, rhs, 0.0, nullptr, 0.0, N));
     if (!(nb > 0.0)) return KP_OK;
     KP_HIP(launch_axpby(s, r, rhs, 1.0, nullptr, 0.0, N));
     double beta = nb;
@@ -366,9 +361,8 @@ kp_status kp_fgmres(kp_ctx c, const kp_batch* b, int32_t pc_kind, int32_t rank, 
         for (int j = 0; j < m; ++j) {
             double* vj = V + j * vec;
             double* zj = Z + j * vec;
-            if ((st = fg_precond(c, b, pc_kind, rank, pc_data, pc_aux, pc_prec, vj, zj, N)) != KP_OK)
-                return st;
-            if ((st = kp_operator_apply(c, b, zj, w)) != KP_OK) return st;
+            if ((st = pc(vj, zj)) != KP_OK) return st;
+            if ((st = op(zj, w)) != KP_OK) return st;
             // classical Gram-Schmidt, twice
             KP_HIP(launch_mdot(s, V, vec, j + 1, w, N, partial, hd, 0));
             KP_HIP(launch_mgs_update(s, V, vec, j + 1, hd, w, N));
@@ -415,7 +409,7 @@ kp_status kp_fgmres(kp_ctx c, const kp_batch* b, int32_t pc_kind, int32_t rank, 
         KP_HIP(hipMemcpyAsync(yd, y, k * sizeof(double), hipMemcpyHostToDevice, s));
         KP_HIP(launch_combine(s, Z, vec, k, yd, x, N));
         // true residual
-        if ((st = kp_operator_apply(c, b, x, w)) != KP_OK) return st;
+        if ((st = op(x, w)) != KP_OK) return st;
         KP_HIP(launch_axpby(s, r, rhs, 1.0, w, -1.0, N));
         double rr = 0.0;
         KP_HIP(launch_mdot(s, r, 0, 1, r, N, partial, hd, 0));
@@ -428,6 +422,28 @@ kp_status kp_fgmres(kp_ctx c, const kp_batch* b, int32_t pc_kind, int32_t rank, 
     if (iters_h) *iters_h = iters;
     if (relres_h) *relres_h = beta / nb;
     return converged ? KP_OK : KP_ERR_NOCONV;
+}
+
+extern "C" {
+
+kp_status kp_fgmres(kp_ctx c, const kp_batch* b, int32_t pc_kind, int32_t rank, const void* pc_data,
+                    const void* pc_aux, int32_t pc_prec, const double* rhs, double* x,
+                    int32_t restart, double rtol, int32_t maxit, int32_t* iters_h, double* relres_h,
+                    double* hist_h, int32_t hist_len) {
+    if (!c) return KP_ERR_ARG;
+    kp_status st = check_batch(b);
+    if (st != KP_OK) return st;
+    if (!rhs || !x || restart < 1 || restart > 200 || maxit < 1 || !(rtol > 0.0)) return KP_ERR_ARG;
+    if (pc_kind < KP_PC_NONE || pc_kind > KP_PC_BJ) return KP_ERR_ARG;
+    if (pc_kind != KP_PC_NONE && !pc_data) return KP_ERR_ARG;
+    if (pc_kind == KP_PC_BJ && !pc_aux) return KP_ERR_ARG;
+    const int nd = b->dim == 2 ? b->n * b->n : b->n * b->n * b->n;
+    const int64_t N = b->num_elems * nd;
+    VecFn op = [&](const double* in, double* out) { return kp_operator_apply(c, b, in, out); };
+    VecFn pc = [&](const double* in, double* out) {
+        return fg_precond(c, b, pc_kind, rank, pc_data, pc_aux, pc_prec, in, out, N);
+    };
+    return fgmres_core(c, N, op, pc, rhs, x, restart, rtol, maxit, iters_h, relres_h, hist_h, hist_len);
 }
 
 }  // extern "C"

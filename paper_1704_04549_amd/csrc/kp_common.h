@@ -164,6 +164,26 @@ struct BlockTeam {
         __syncthreads();
     }
 };
+
+// ----------------------------------------------------------- wave team
+// One wave (64 lanes) as a team of its own, independent of the other waves
+// of its workgroup: sync is a wave-scope fence plus a wave barrier (no
+// workgroup barrier), reductions are wave shuffles.  Routines that use only
+// tid / size / sync / sum / max run unchanged on it.
+struct WaveTeam {
+    __device__ int tid() const { return (int)(threadIdx.x & 63); }
+    __device__ int size() const { return 64; }
+    __device__ void sync() const {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    __device__ bool leader() const { return (threadIdx.x & 63) == 0; }
+    __device__ double sum(double v) const { return wave_sum(v); }
+    __device__ double max(double v) const {
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+        return v;
+    }
+};
 #endif
 
 // bf16 <-> f32 (round to nearest even), host and device

@@ -1,0 +1,40 @@
+// Mixed batches: elements of different dimension and degree in one batch.
+//
+// Every element has a descriptor (dimension, n and its offsets in the packed
+// vectors, factors and tables); the persistent kernels of mixed.hip read the
+// descriptor of each element they process, so one launch covers the whole
+// batch.  Vectors are packed in element order: element e holds n_e^d_e values
+// at vec_off[e].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "elem_ops.h"
+
+namespace kp {
+
+struct MixedElem {
+    int32_t dim, n;
+    int64_t vec_off;  // doubles, in the packed vectors
+    int64_t fac_off;  // doubles, in the factor section (5 n^2 in 3D, 4 n^2 in 2D)
+    int64_t tab_off;  // entries, in every table section ((7 + n) n^2 each)
+};
+
+// Apply work list: item i < n_block is one element processed by the whole
+// workgroup (items[4 i]); the others hold up to four elements (-1: none),
+// one per wave, each processed by its wave alone.
+constexpr int kMixedItemWidth = 4;
+
+hipError_t launch_mixed_setup(hipStream_t s, int grid, int64_t E, const MixedElem* el, const int32_t* order,
+                              Tables1D* const* tabs, const double* params, double* factors, double* sigma,
+                              int32_t* status, double* ws, int64_t ws_stride, size_t small_doubles);
+hipError_t launch_mixed_tables(hipStream_t s, int64_t E, const MixedElem* el, int max_n, int nf_max,
+                               const double* factors, double* tab64, int8_t* kinds, int32_t* status);
+hipError_t launch_mixed_apply(hipStream_t s, int prec, int grid, int n_items, int n_block, const int32_t* items,
+                              const MixedElem* el, const void* tabs, const int8_t* kinds, const double* r,
+                              double* z, long block_nd, long wave_nd);
+hipError_t launch_mixed_operator(hipStream_t s, int64_t E, const MixedElem* el, Tables1D* const* tabs,
+                                 const double* params, const double* x, double* y, int max_n, int max_nd);
+
+}  // namespace kp

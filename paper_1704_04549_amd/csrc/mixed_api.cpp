@@ -1,0 +1,375 @@
+// C ABI of mixed batches (include/kp.h, "mixed batches"): the plan (layout of
+// the packed vectors and preconditioner, per-element descriptors, the apply
+// work list), setup, apply, the block-diagonal operator, FGMRES and the
+// autotuner that chooses, per (dim, n), whether an element is applied by a
+// whole workgroup or by one wave.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <utility>
+#include <vector>
+
+#include "../../include/kp.h"
+#include "ctx_internal.h"
+#include "kernels.h"
+#include "krylov.h"
+#include "mixed.h"
+
+using namespace kp;
+
+struct kp_mixed_plan_s {
+    int device = 0;
+    int64_t E = 0;
+    int64_t vec_len = 0;
+    std::vector<MixedElem> h_el;
+    MixedElem* d_el = nullptr;
+    int32_t* d_order = nullptr;        // setup order: most expensive first
+    Tables1D** d_tabs = nullptr;       // [kMaxN + 1] device table pointers
+    // preconditioner layout (bytes)
+    size_t sigma = 0, factors = 0, status = 0, kinds = 0, t64 = 0, t32 = 0, thi = 0, tlo = 0, t2 = 0, total = 0;
+    int64_t fac_total = 0, tab_total = 0;
+    int max_n = 2, max_nd = 4;
+    int64_t ws_stride = 0;
+    size_t small_doubles = 0;
+    // apply work list and its launch shape
+    std::map<std::pair<int, int>, int> mode;  // (dim, n) -> 0 workgroup, 1 wave
+    int32_t* d_items = nullptr;
+    int n_items = 0, n_block = 0;
+    long block_nd = 0, wave_nd = 0;
+    bool tuned = false;
+};
+
+namespace {
+
+#define MX_HIP(call)                                   \
+    do {                                               \
+        hipError_t err_ = (call);                      \
+        if (err_ != hipSuccess) return KP_ERR_HIP;     \
+    } while (0)
+
+size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+long elem_nd(const MixedElem& d) { return d.dim == 2 ? (long)d.n * d.n : (long)d.n * d.n * d.n; }
+
+// work list from the current per-(dim, n) modes: workgroup items first
+kp_status build_items(kp_mixed_plan p) {
+    std::vector<int32_t> blk, wav;
+    p->block_nd = 0;
+    p->wave_nd = 0;
+    for (int64_t e = 0; e < p->E; ++e) {
+        const MixedElem& d = p->h_el[e];
+        const int md = p->mode[{d.dim, d.n}];
+        if (md == 0) {
+            blk.push_back((int32_t)e);
+            p->block_nd = std::max(p->block_nd, elem_nd(d));
+        } else {
+            wav.push_back((int32_t)e);
+            p->wave_nd = std::max(p->wave_nd, elem_nd(d));
+        }
+    }
+    // longest first within each kind, for the tail of the persistent grid
+    auto cost = [&](int32_t a, int32_t b) { return elem_nd(p->h_el[a]) > elem_nd(p->h_el[b]); };
+    std::stable_sort(blk.begin(), blk.end(), cost);
+    std::stable_sort(wav.begin(), wav.end(), cost);
+    const int nw = (int)((wav.size() + kMixedItemWidth - 1) / kMixedItemWidth);
+    std::vector<int32_t> items((blk.size() + nw) * kMixedItemWidth, -1);
+    for (size_t i = 0; i < blk.size(); ++i) items[i * kMixedItemWidth] = blk[i];
+    for (size_t i = 0; i < wav.size(); ++i) items[(blk.size() + i / kMixedItemWidth) * kMixedItemWidth + i % kMixedItemWidth] = wav[i];
+    if (p->d_items) hipFree(p->d_items);
+    p->d_items = nullptr;
+    if (!items.empty()) {
+        if (hipMalloc((void**)&p->d_items, items.size() * sizeof(int32_t)) != hipSuccess) return KP_ERR_ALLOC;
+        MX_HIP(hipMemcpy(p->d_items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    p->n_block = (int)blk.size();
+    p->n_items = (int)blk.size() + nw;
+    return KP_OK;
+}
+
+const void* table_section(kp_mixed_plan p, const char* pc, int prec) {
+    return prec == KP_FP64 ? (const void*)(pc + p->t64)
+           : prec == KP_FP32 ? (const void*)(pc + p->t32)
+           : prec == KP_BF16 ? (const void*)(pc + p->thi)
+                             : (const void*)(pc + p->t2);
+}
+
+kp_status mixed_apply_launch(kp_ctx c, kp_mixed_plan p, const void* precond, int prec, const double* r, double* z) {
+    const char* pc = (const char*)precond;
+    const int grid = p->n_items < 65536 ? p->n_items : 65536;
+    MX_HIP(launch_mixed_apply(c->stream, prec, grid, p->n_items, p->n_block, p->d_items, p->d_el,
+                              table_section(p, pc, prec), (const int8_t*)(pc + p->kinds), r, z, p->block_nd,
+                              p->wave_nd));
+    return KP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kp_status kp_mixed_plan_create(kp_ctx c, int64_t num_elems, const int32_t* dim_n_h, kp_mixed_plan* out) {
+    if (!c || !out || num_elems < 0 || (num_elems > 0 && !dim_n_h)) return KP_ERR_ARG;
+    *out = nullptr;
+    kp_mixed_plan p = new (std::nothrow) kp_mixed_plan_s;
+    if (!p) return KP_ERR_ALLOC;
+    p->device = c->device;
+    p->E = num_elems;
+    p->h_el.resize(num_elems);
+    int64_t vo = 0, fo = 0, to = 0;
+    long wsd = 0;
+    size_t smd = 0;
+    bool present[kMaxN + 1] = {};
+    for (int64_t e = 0; e < num_elems; ++e) {
+        const int dim = dim_n_h[2 * e], n = dim_n_h[2 * e + 1];
+        if ((dim != 2 && dim != 3) || n < 2 || n > kMaxN) {
+            delete p;
+            return KP_ERR_ARG;
+        }
+        MixedElem& d = p->h_el[e];
+        d.dim = dim;
+        d.n = n;
+        d.vec_off = vo;
+        d.fac_off = fo;
+        d.tab_off = to;
+        vo += elem_nd(d);
+        fo += (int64_t)(dim == 2 ? 4 : 5) * n * n;
+        to += tab_entries(n);
+        p->max_n = std::max(p->max_n, n);
+        p->max_nd = (int)std::max<long>(p->max_nd, elem_nd(d));
+        wsd = std::max(wsd, setup_work_doubles(dim, n, false, 2));
+        smd = std::max(smd, (size_t)setup_small_doubles(n, false));
+        present[n] = true;
+        p->mode[{dim, n}] = 0;
+    }
+    p->vec_len = vo;
+    p->fac_total = fo;
+    p->tab_total = to;
+    p->ws_stride = wsd;
+    p->small_doubles = smd;
+    size_t off = 0;
+    p->sigma = off; off = al256(off + num_elems * 4 * sizeof(double));
+    p->factors = off; off = al256(off + fo * sizeof(double));
+    p->status = off; off = al256(off + num_elems * sizeof(int32_t));
+    p->kinds = off; off = al256(off + num_elems * kMaxN);
+    p->t64 = off; off = al256(off + to * sizeof(double));
+    p->t32 = off; off = al256(off + to * sizeof(float));
+    p->thi = off; off = al256(off + to * sizeof(uint16_t));
+    p->tlo = off; off = al256(off + to * sizeof(uint16_t));
+    p->t2 = off; off = al256(off + to * sizeof(float));
+    p->total = off;
+    hipSetDevice(c->device);
+    // descriptors, setup order, table pointers
+    std::vector<int32_t> order(num_elems);
+    for (int64_t e = 0; e < num_elems; ++e) order[e] = (int32_t)e;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const MixedElem &x = p->h_el[a], &y = p->h_el[b];
+        if (elem_nd(x) != elem_nd(y)) return elem_nd(x) > elem_nd(y);
+        return x.n > y.n;
+    });
+    Tables1D* tabs[kMaxN + 1] = {};
+    for (int n = 2; n <= kMaxN; ++n)
+        if (present[n]) {
+            const Tables1D* t;
+            kp_status st = get_tables(c, n, &t);
+            if (st != KP_OK) {
+                kp_mixed_plan_destroy(p);
+                return st;
+            }
+            tabs[n] = (Tables1D*)t;
+        }
+    if (num_elems > 0) {
+        if (hipMalloc((void**)&p->d_el, num_elems * sizeof(MixedElem)) != hipSuccess ||
+            hipMalloc((void**)&p->d_order, num_elems * sizeof(int32_t)) != hipSuccess) {
+            kp_mixed_plan_destroy(p);
+            return KP_ERR_ALLOC;
+        }
+        hipMemcpy(p->d_el, p->h_el.data(), num_elems * sizeof(MixedElem), hipMemcpyHostToDevice);
+        hipMemcpy(p->d_order, order.data(), num_elems * sizeof(int32_t), hipMemcpyHostToDevice);
+    }
+    if (hipMalloc((void**)&p->d_tabs, sizeof(tabs)) != hipSuccess) {
+        kp_mixed_plan_destroy(p);
+        return KP_ERR_ALLOC;
+    }
+    hipMemcpy(p->d_tabs, tabs, sizeof(tabs), hipMemcpyHostToDevice);
+    kp_status st = build_items(p);
+    if (st != KP_OK) {
+        kp_mixed_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return KP_OK;
+}
+
+kp_status kp_mixed_plan_destroy(kp_mixed_plan p) {
+    if (!p) return KP_ERR_ARG;
+    hipSetDevice(p->device);
+    hipDeviceSynchronize();
+    if (p->d_el) hipFree(p->d_el);
+    if (p->d_order) hipFree(p->d_order);
+    if (p->d_tabs) hipFree(p->d_tabs);
+    if (p->d_items) hipFree(p->d_items);
+    delete p;
+    return KP_OK;
+}
+
+kp_status kp_mixed_plan_info(kp_mixed_plan p, int64_t* vec_len_h, size_t* precond_bytes_h) {
+    if (!p) return KP_ERR_ARG;
+    if (vec_len_h) *vec_len_h = p->vec_len;
+    if (precond_bytes_h) *precond_bytes_h = p->total;
+    return KP_OK;
+}
+
+kp_status kp_mixed_setup(kp_ctx c, kp_mixed_plan p, const double* params, void* precond, int32_t* elem_status) {
+    if (!c || !p) return KP_ERR_ARG;
+    if (p->E == 0) return KP_OK;
+    if (!params || !precond) return KP_ERR_ARG;
+    hipSetDevice(c->device);
+    const int grid = (int)(p->E < 2048 ? p->E : 2048);
+    kp_status st = ensure_ws(c, (size_t)p->ws_stride * grid * sizeof(double), &c->ws, &c->ws_bytes);
+    if (st != KP_OK) return st;
+    char* pc = (char*)precond;
+    MX_HIP(launch_mixed_setup(c->stream, grid, p->E, p->d_el, p->d_order, p->d_tabs, params,
+                              (double*)(pc + p->factors), (double*)(pc + p->sigma), (int32_t*)(pc + p->status),
+                              (double*)c->ws, p->ws_stride, p->small_doubles));
+    int nf_max = 4;
+    for (auto& kv : p->mode)
+        if (kv.first.first == 3) nf_max = 5;
+    MX_HIP(launch_mixed_tables(c->stream, p->E, p->d_el, p->max_n, nf_max, (const double*)(pc + p->factors),
+                               (double*)(pc + p->t64), (int8_t*)(pc + p->kinds), (int32_t*)(pc + p->status)));
+    MX_HIP(launch_cast_tables(c->stream, p->tab_total, (const double*)(pc + p->t64), (float*)(pc + p->t32),
+                              (uint16_t*)(pc + p->thi), (uint16_t*)(pc + p->tlo), (float*)(pc + p->t2)));
+    if (elem_status)
+        MX_HIP(hipMemcpyAsync(elem_status, pc + p->status, p->E * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                              c->stream));
+    return KP_OK;
+}
+
+kp_status kp_mixed_get_factors(kp_ctx c, kp_mixed_plan p, const void* precond, double* factors, double* sigma) {
+    if (!c || !p || !precond) return KP_ERR_ARG;
+    const char* pc = (const char*)precond;
+    if (factors)
+        MX_HIP(hipMemcpyAsync(factors, pc + p->factors, p->fac_total * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+    if (sigma)
+        MX_HIP(hipMemcpyAsync(sigma, pc + p->sigma, p->E * 4 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return KP_OK;
+}
+
+kp_status kp_mixed_apply(kp_ctx c, kp_mixed_plan p, const void* precond, int32_t prec, const double* r, double* z) {
+    if (!c || !p) return KP_ERR_ARG;
+    if (prec < KP_FP64 || prec > KP_BF16X3) return KP_ERR_ARG;
+    if (p->E == 0) return KP_OK;
+    if (!precond || !r || !z) return KP_ERR_ARG;
+    return mixed_apply_launch(c, p, precond, prec, r, z);
+}
+
+kp_status kp_mixed_autotune(kp_ctx c, kp_mixed_plan p, const void* precond, int32_t prec, const double* r,
+                            double* z, int32_t* modes_h, int32_t modes_len) {
+    if (!c || !p) return KP_ERR_ARG;
+    if (prec < KP_FP64 || prec > KP_BF16X3) return KP_ERR_ARG;
+    if (p->E == 0) return KP_OK;
+    if (!precond || !r || !z) return KP_ERR_ARG;
+    hipEvent_t e0, e1;
+    MX_HIP(hipEventCreate(&e0));
+    MX_HIP(hipEventCreate(&e1));
+    kp_status st = KP_OK;
+    // one (dim, n) class at a time: only its elements in the work list, both modes timed
+    std::map<std::pair<int, int>, int> chosen;
+    for (auto& kv : p->mode) {
+        float best_t = 0.f;
+        int best_m = 0;
+        for (int md = 0; md < 2 && st == KP_OK; ++md) {
+            // a work list of this class only
+            std::vector<int32_t> items;
+            long nd = 0;
+            std::vector<int32_t> members;
+            for (int64_t e = 0; e < p->E; ++e)
+                if (p->h_el[e].dim == kv.first.first && p->h_el[e].n == kv.first.second) {
+                    members.push_back((int32_t)e);
+                    nd = elem_nd(p->h_el[e]);
+                }
+            const int width = md == 0 ? 1 : kMixedItemWidth;
+            const int nit = (int)((members.size() + width - 1) / width);
+            items.assign((size_t)nit * kMixedItemWidth, -1);
+            for (size_t i = 0; i < members.size(); ++i)
+                items[(i / width) * kMixedItemWidth + i % width] = members[i];
+            int32_t* d_items = nullptr;
+            if (hipMalloc((void**)&d_items, items.size() * sizeof(int32_t)) != hipSuccess) {
+                st = KP_ERR_ALLOC;
+                break;
+            }
+            hipMemcpy(d_items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+            const char* pc = (const char*)precond;
+            const int grid = nit < 65536 ? nit : 65536;
+            float tsum = 0.f;
+            for (int rep = 0; rep < 4 && st == KP_OK; ++rep) {
+                hipEventRecord(e0, c->stream);
+                if (launch_mixed_apply(c->stream, prec, grid, nit, md == 0 ? nit : 0, d_items, p->d_el,
+                                       table_section(p, pc, prec), (const int8_t*)(pc + p->kinds), r, z,
+                                       md == 0 ? nd : 0, md == 0 ? 0 : nd) != hipSuccess)
+                    st = KP_ERR_HIP;
+                hipEventRecord(e1, c->stream);
+                hipEventSynchronize(e1);
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0) tsum += ms;  // the first launch warms up
+            }
+            hipFree(d_items);
+            if (md == 0 || tsum < best_t) {
+                best_t = tsum;
+                best_m = md;
+            }
+        }
+        chosen[kv.first] = best_m;
+        if (st != KP_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != KP_OK) {
+        for (auto& q : p->mode) q.second = 0;
+        build_items(p);
+        return st;
+    }
+    p->mode = chosen;
+    if ((st = build_items(p)) != KP_OK) return st;
+    p->tuned = true;
+    if (modes_h) {
+        int i = 0;
+        for (auto& kv : p->mode) {
+            if (i + 3 > modes_len) break;
+            modes_h[i++] = kv.first.first;
+            modes_h[i++] = kv.first.second;
+            modes_h[i++] = kv.second;
+        }
+        for (; i < modes_len; ++i) modes_h[i] = -1;
+    }
+    return KP_OK;
+}
+
+kp_status kp_mixed_operator_apply(kp_ctx c, kp_mixed_plan p, const double* params, const double* x, double* y) {
+    if (!c || !p) return KP_ERR_ARG;
+    if (p->E == 0) return KP_OK;
+    if (!params || !x || !y) return KP_ERR_ARG;
+    MX_HIP(launch_mixed_operator(c->stream, p->E, p->d_el, p->d_tabs, params, x, y, p->max_n, p->max_nd));
+    return KP_OK;
+}
+
+kp_status kp_mixed_fgmres(kp_ctx c, kp_mixed_plan p, const double* params, int32_t pc_kind, const void* precond,
+                          int32_t pc_prec, const double* rhs, double* x, int32_t restart, double rtol,
+                          int32_t maxit, int32_t* iters_h, double* relres_h, double* hist_h, int32_t hist_len) {
+    if (!c || !p) return KP_ERR_ARG;
+    if (!rhs || !x || restart < 1 || restart > 200 || maxit < 1 || !(rtol > 0.0)) return KP_ERR_ARG;
+    if (pc_kind != KP_PC_NONE && pc_kind != KP_PC_KSVD) return KP_ERR_ARG;
+    if (pc_kind == KP_PC_KSVD && !precond) return KP_ERR_ARG;
+    if (p->E > 0 && !params) return KP_ERR_ARG;
+    VecFn op = [&](const double* in, double* out) { return kp_mixed_operator_apply(c, p, params, in, out); };
+    VecFn pcf = [&](const double* in, double* out) -> kp_status {
+        if (pc_kind == KP_PC_KSVD) return kp_mixed_apply(c, p, precond, pc_prec, in, out);
+        MX_HIP(launch_axpby(c->stream, out, in, 1.0, nullptr, 0.0, p->vec_len));
+        return KP_OK;
+    };
+    return fgmres_core(c, p->vec_len, op, pcf, rhs, x, restart, rtol, maxit, iters_h, relres_h, hist_h, hist_len);
+}
+
+}  // extern "C"

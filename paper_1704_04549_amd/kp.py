@@ -75,6 +75,16 @@ def lib() -> ctypes.CDLL:
                              ctypes.c_int),
             "kp_mlp_predict": ([vp, vp, bp, i32, vp], ctypes.c_int),
             "kp_set_model": ([vp, vp], ctypes.c_int),
+            "kp_mixed_plan_create": ([vp, i64, vp, ctypes.POINTER(vp)], ctypes.c_int),
+            "kp_mixed_plan_destroy": ([vp], ctypes.c_int),
+            "kp_mixed_plan_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+            "kp_mixed_setup": ([vp, vp, vp, vp, vp], ctypes.c_int),
+            "kp_mixed_get_factors": ([vp, vp, vp, vp, vp], ctypes.c_int),
+            "kp_mixed_apply": ([vp, vp, vp, i32, vp, vp], ctypes.c_int),
+            "kp_mixed_autotune": ([vp, vp, vp, i32, vp, vp, vp, i32], ctypes.c_int),
+            "kp_mixed_operator_apply": ([vp, vp, vp, vp, vp], ctypes.c_int),
+            "kp_mixed_fgmres": ([vp, vp, vp, i32, vp, i32, vp, vp, i32, dbl, i32,
+                                 ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, i32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -311,3 +321,94 @@ class Ctx:
 
     def set_model(self, model):
         _check(lib().kp_set_model(self.h, _ptr(model)), "kp_set_model")
+
+
+class MixedPlan:
+    """A mixed batch (per-element dim and n) and its plan; records on the device."""
+
+    def __init__(self, ctx: "Ctx", dims, ns, params: torch.Tensor):
+        import numpy as np
+        self.ctx = ctx
+        self.dims = np.asarray(dims, dtype=np.int32)
+        self.ns = np.asarray(ns, dtype=np.int32)
+        self.E = int(self.dims.size)
+        if params.dtype != torch.float64 or tuple(params.shape) != (self.E, REC_LEN):
+            raise ValueError("params: float64 [E, 16] device tensor expected")
+        self.params = params
+        dn = np.ascontiguousarray(np.stack([self.dims, self.ns], axis=1).astype(np.int32))
+        h = ctypes.c_void_p()
+        _check(lib().kp_mixed_plan_create(ctx.h, self.E, dn.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
+               "kp_mixed_plan_create")
+        self.h = h
+        vl = ctypes.c_int64(0)
+        pb = ctypes.c_size_t(0)
+        _check(lib().kp_mixed_plan_info(self.h, ctypes.byref(vl), ctypes.byref(pb)), "kp_mixed_plan_info")
+        self.vec_len = vl.value
+        self.precond_bytes = pb.value
+        offs = np.zeros(self.E + 1, dtype=np.int64)
+        offs[1:] = np.cumsum(self.ns.astype(np.int64) ** self.dims)
+        self.offsets = offs
+
+    def close(self):
+        if self.h:
+            lib().kp_mixed_plan_destroy(self.h)
+            self.h = None
+
+    def setup(self, precond=None, status=None):
+        if precond is None:
+            precond = torch.empty(max(self.precond_bytes, 1), dtype=torch.uint8, device=self.ctx.device)
+        if status is None:
+            status = torch.empty(self.E, dtype=torch.int32, device=self.ctx.device)
+        _check(lib().kp_mixed_setup(self.ctx.h, self.h, _ptr(self.params), _ptr(precond), _ptr(status)),
+               "kp_mixed_setup")
+        return precond, status
+
+    def get_factors(self, precond):
+        import numpy as np
+        total = int(np.sum(np.where(self.dims == 3, 5, 4) * self.ns.astype(np.int64) ** 2))
+        f = torch.empty(total, dtype=torch.float64, device=self.ctx.device)
+        sg = torch.empty((self.E, 4), dtype=torch.float64, device=self.ctx.device)
+        _check(lib().kp_mixed_get_factors(self.ctx.h, self.h, _ptr(precond), _ptr(f), _ptr(sg)),
+               "kp_mixed_get_factors")
+        return f, sg
+
+    def apply(self, precond, prec, r, z=None):
+        prec = PREC.get(prec, prec)
+        if z is None:
+            z = torch.empty_like(r)
+        _check(lib().kp_mixed_apply(self.ctx.h, self.h, _ptr(precond), int(prec), _ptr(r), _ptr(z)),
+               "kp_mixed_apply")
+        return z
+
+    def autotune(self, precond, prec, r, z):
+        prec = PREC.get(prec, prec)
+        buf = (ctypes.c_int32 * 300)()
+        _check(lib().kp_mixed_autotune(self.ctx.h, self.h, _ptr(precond), int(prec), _ptr(r), _ptr(z), buf, 300),
+               "kp_mixed_autotune")
+        out = {}
+        for i in range(0, 300, 3):
+            if buf[i] < 0:
+                break
+            out[(buf[i], buf[i + 1])] = buf[i + 2]
+        return out
+
+    def operator_apply(self, x, y=None):
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().kp_mixed_operator_apply(self.ctx.h, self.h, _ptr(self.params), _ptr(x), _ptr(y)),
+               "kp_mixed_operator_apply")
+        return y
+
+    def fgmres(self, rhs, pc_kind=KP_PC_KSVD, precond=None, pc_prec=KP_FP64, x=None, restart=30, rtol=1e-10,
+               maxit=3000):
+        pc_prec = PREC.get(pc_prec, pc_prec)
+        if x is None:
+            x = torch.empty_like(rhs)
+        it = ctypes.c_int32(0)
+        rr = ctypes.c_double(0.0)
+        st = lib().kp_mixed_fgmres(self.ctx.h, self.h, _ptr(self.params), int(pc_kind), _ptr(precond),
+                                   int(pc_prec), _ptr(rhs), _ptr(x), int(restart), float(rtol), int(maxit),
+                                   ctypes.byref(it), ctypes.byref(rr), None, 0)
+        if st not in (KP_OK, KP_ERR_NOCONV):
+            raise KpError(st, "kp_mixed_fgmres")
+        return dict(x=x, iters=it.value, relres=rr.value, converged=(st == KP_OK))

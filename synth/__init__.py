@@ -137,7 +137,11 @@ def workload(name: str, num_elems: int | None = None):
 def mixed_batch(n2d: int = 50000, n3d: int = 2000, seed: int = MIXED_SEED):
     """Mixed-degree batch: 2D elements with p ~ U{3..30}, then 3D with p ~ U{3..15}.
 
-    p is drawn before each element's parameters.  Returns (dims, ns, params).
+    p is drawn before each element's parameters.  Every element is closed by
+    the outflow terms of its own upwind faces (face flag set, face velocities
+    from its own velocity), as the block-diagonal 3D p = 15 workload: without
+    them an advection-dominated block is nearly singular (S is) and the
+    block-diagonal system does not converge.  Returns (dims, ns, params).
     """
     rng = np.random.default_rng(seed)
     dims, ns, recs = [], [], []
@@ -151,6 +155,10 @@ def mixed_batch(n2d: int = 50000, n3d: int = 2000, seed: int = MIXED_SEED):
             rec[4] = 0.5 * u[dim + 1]
             rec[5] = 2.0 * np.pi * u[dim + 2]
             rec[6] = TAU
+            rec[7] = 1.0
+            for ax in range(dim):
+                rec[8 + 2 * ax] = rec[ax]
+                rec[9 + 2 * ax] = -rec[ax]
             dims.append(dim)
             ns.append(p + 1)
             recs.append(rec)
