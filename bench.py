@@ -114,12 +114,89 @@ MEASURED_TRAFFIC = {
 }
 
 
+def bench_mixed(args):
+    """The mixed batch: 50000 2D elements (p 3..30) and 2000 3D elements
+    (p 3..15), block-diagonal, one persistent launch per stage, autotuned
+    apply launch.  Reports the whole batch's setup + N applies DOF/s (N = the
+    FGMRES count of the FP32-applied preconditioner), per-(dim, p) setup and
+    apply rates, and the FGMRES iteration delta against the FP64 apply."""
+    import torch
+
+    import synth
+    from paper_1704_04549_amd import kp
+
+    dims, ns, recs = synth.mixed_batch()
+    ctx = kp.Ctx(0)
+    dev = torch.device("cuda", 0)
+    stream = ctx.stream
+
+    def ev_ms(fn, reps):
+        fn()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    plan = kp.MixedPlan(ctx, dims, ns, torch.from_numpy(recs).to(dev))
+    pc, st = plan.setup()
+    r = torch.from_numpy(np.random.default_rng(synth.MIXED_RHS_SEED).standard_normal(plan.vec_len)).to(dev)
+    z = torch.empty_like(r)
+    modes = plan.autotune(pc, args.prec, r, z)
+    out64 = plan.fgmres(r, pc_kind=kp.KP_PC_KSVD, precond=pc, pc_prec="fp64")
+    outv = plan.fgmres(r, pc_kind=kp.KP_PC_KSVD, precond=pc, pc_prec=args.prec)
+    N = outv["iters"]
+    t_setup = ev_ms(lambda: plan.setup(pc, st), 3)
+    t_apply = ev_ms(lambda: plan.apply(pc, args.prec, r, z), 10)
+    dof = plan.vec_len
+    per_p = {}
+    for d in (2, 3):
+        for n in sorted(set(ns[dims == d].tolist())):
+            sel = (dims == d) & (ns == n)
+            sub = kp.MixedPlan(ctx, dims[sel], ns[sel], torch.from_numpy(np.ascontiguousarray(recs[sel])).to(dev))
+            spc, sst = sub.setup()
+            sr = torch.from_numpy(np.random.default_rng(1).standard_normal(sub.vec_len)).to(dev)
+            sz = torch.empty_like(sr)
+            sub.autotune(spc, args.prec, sr, sz)
+            ts = ev_ms(lambda: sub.setup(spc, sst), 2)
+            ta = ev_ms(lambda: sub.apply(spc, args.prec, sr, sz), 5)
+            per_p[f"{d}d_p{n - 1}"] = {"elements": int(sel.sum()), "dof": int(sub.vec_len),
+                                       "setup_dof_per_s": sub.vec_len / (ts * 1e-3),
+                                       "apply_dof_per_s": sub.vec_len / (ta * 1e-3)}
+            sub.close()
+    valid = outv["converged"] and out64["converged"] and N <= out64["iters"] + 1
+    line = {
+        "metric": "mixed-degree batch precond setup+apply DOF/s at equal FGMRES iterations",
+        "value": dof * N / ((t_setup + N * t_apply) * 1e-3) if valid else None,
+        "unit": "DOF/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": "mixed batch: 50000 2D elements p~U{3..30}, 2000 3D elements p~U{3..15}, "
+                               "own upwind faces (block-diagonal), rank 2, SVD setup, FGMRES(30) to 1e-10",
+                   "elements": int(len(dims)), "dof": int(dof), "fgmres_iters": N,
+                   "fgmres_iters_fp64": out64["iters"], "iteration_delta": N - out64["iters"], "valid": valid},
+        "setup_ms": t_setup, "apply_ms": t_apply,
+        "setup_status_nonzero": int((st != 0).sum()),
+        "learned_fallback_rate": 1.0,
+        "autotune_wave_classes": sorted(f"{d}d_p{n - 1}" for (d, n), m in modes.items() if m == 1),
+        "per_p": per_p,
+    }
+    print(json.dumps(line), flush=True)
+    plan.close()
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "c5_mixed":
+        bench_mixed(args)
+        return
     import torch
 
     import synth

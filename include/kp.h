@@ -107,6 +107,18 @@ typedef struct {
 kp_status kp_create(kp_ctx* ctx, int device, void* stream);
 kp_status kp_destroy(kp_ctx ctx);
 kp_status kp_set_stream(kp_ctx ctx, void* stream);
+
+/* Context options (kp_set_option):
+ *   KP_OPT_FGMRES_GRAPHS (default 0): run every Arnoldi step of kp_fgmres /
+ *     kp_mixed_fgmres as a HIP graph (preconditioner, operator, both
+ *     Gram-Schmidt passes, the norm and the copies of the projections into
+ *     pinned host memory), captured once per solve on a private stream and
+ *     replayed every restart cycle; the same kernels in the same order as
+ *     without graphs.  A step that cannot be captured runs without graphs.
+ *   KP_OPT_APPLY_MFMA16 (default 1): the matrix-core apply for n = 16; 0
+ *     selects the generic per-element kernel. */
+typedef enum { KP_OPT_FGMRES_GRAPHS = 1, KP_OPT_APPLY_MFMA16 = 2 } kp_option;
+kp_status kp_set_option(kp_ctx ctx, int32_t option, int64_t value);
 const char* kp_status_string(kp_status s);
 
 /* Bytes of the opaque preconditioner buffer for a batch and rank.

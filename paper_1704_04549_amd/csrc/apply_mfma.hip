@@ -305,24 +305,45 @@ __global__ void __launch_bounds__(256) k_apply16(int64_t E, int nrhs, const type
         const int grp = (int)(w % groups);
         const typename P::Tab* tab = tabs + e * tab_stride;
         const FT* fr = frags + e * tab_stride * P::kFragStride;
-        // fragments of L0..L2, R0, R1 and T1 in registers; N_0..N_15 to LDS
+        // All global loads of the element are issued before the first LDS
+        // write (a load followed by its store in one loop iteration would wait
+        // for each load in turn): fragments of L0..L2, R0, R1 and T1 stay in
+        // registers; N_0..N_15, T2 and the right-hand side go to LDS.
         typename P::Frag fL[5];
 #pragma unroll
         for (int m = 0; m < 5; ++m) fL[m] = P::load_frag(fr, m, l);
         const typename P::Frag fT1 = P::load_frag(fr, 5, l);
+        constexpr int n16 = kNfEntries * (int)sizeof(FT) / 16;  // 16-byte chunks of N_0..N_15
+        static_assert(n16 % 256 == 0, "N fragments: whole 16-byte chunks per thread");
+        uint4 nbuf[n16 / 256];
         {
             const uint4* src = (const uint4*)(fr + 7 * 64 * 4 * P::kFragStride);
-            uint4* dst = (uint4*)Nf;
-            constexpr int n16 = kNfEntries * (int)sizeof(FT) / 16;
-            for (int q = tid; q < n16; q += 256) dst[q] = src[q];
+#pragma unroll
+            for (int i = 0; i < n16 / 256; ++i) nbuf[i] = src[tid + 256 * i];
         }
+        double2 rbuf[8];
+        if (DIM == 3) {
+            const double2* rw = (const double2*)(r + w * 4096);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) rbuf[i] = rw[tid + 256 * i];
+        }
+        const T t2v = (T)P::tab(tab + 6 * 256, tid);
         int kd[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) kd[j] = kinds[e * kMaxN + j];
-        T2s[tid] = (T)P::tab(tab + 6 * 256, tid);
+        {
+            uint4* dst = (uint4*)Nf;
+#pragma unroll
+            for (int i = 0; i < n16 / 256; ++i) dst[tid + 256 * i] = nbuf[i];
+        }
+        T2s[tid] = t2v;
         if (DIM == 3) {
-            const double* rw = r + w * 4096;
-            for (int t = tid; t < 4096; t += 256) X[xidx(t >> 8, (t >> 4) & 15, t & 15)] = (T)rw[t];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int t = 2 * (tid + 256 * i);
+                X[xidx(t >> 8, (t >> 4) & 15, t & 15)] = (T)rbuf[i].x;
+                X[xidx(t >> 8, (t >> 4) & 15, (t & 15) + 1)] = (T)rbuf[i].y;
+            }
         } else {
             const int s0 = grp * 16;
             for (int t = tid; t < 4096; t += 256) {
@@ -344,8 +365,15 @@ __global__ void __launch_bounds__(256) k_apply16(int64_t E, int nrhs, const type
         contract<P, 1>(fL[3], X, g, c, wv);
         contract<P, 2>(fL[4], X, g, c, wv);
         if (DIM == 3) {
-            double* zw = z + w * 4096;
-            for (int t = tid; t < 4096; t += 256) zw[t] = (double)X[xidx(t >> 8, (t >> 4) & 15, t & 15)];
+            double2* zw = (double2*)(z + w * 4096);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int t = 2 * (tid + 256 * i);
+                double2 v;
+                v.x = (double)X[xidx(t >> 8, (t >> 4) & 15, t & 15)];
+                v.y = (double)X[xidx(t >> 8, (t >> 4) & 15, (t & 15) + 1)];
+                zw[tid + 256 * i] = v;
+            }
         } else {
             const int s0 = grp * 16;
             for (int t = tid; t < 4096; t += 256) {

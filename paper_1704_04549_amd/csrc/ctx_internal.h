@@ -30,6 +30,12 @@ struct kp_ctx_s {
     size_t mw_bytes = 0;
     const void* model = nullptr;
     int model_dim = 0, model_n = 0, model_hidden = 0;
+    // FGMRES steps as HIP graphs: a private stream for capture (default
+    // priority) and pinned host memory for the projections
+    bool use_graphs = false;
+    hipStream_t cap_stream = nullptr;
+    double* pinned = nullptr;
+    size_t pinned_doubles = 0;
 };
 
 #define KP_HIP(call)                                   \

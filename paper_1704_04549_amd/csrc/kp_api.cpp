@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "../../include/kp.h"
 #include "kernels.h"
@@ -62,8 +63,19 @@ kp_status kp_destroy(kp_ctx c) {
     if (c->ws) hipFree(c->ws);
     if (c->ks) hipFree(c->ks);
     if (c->mw) hipFree(c->mw);
+    if (c->pinned) hipHostFree(c->pinned);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     delete c;
     return KP_OK;
+}
+
+kp_status kp_set_option(kp_ctx c, int32_t option, int64_t value) {
+    if (!c) return KP_ERR_ARG;
+    switch (option) {
+        case KP_OPT_FGMRES_GRAPHS: c->use_graphs = value != 0; return KP_OK;
+        case KP_OPT_APPLY_MFMA16: c->use_mfma16 = value != 0; return KP_OK;
+    }
+    return KP_ERR_ARG;
 }
 
 kp_status kp_set_stream(kp_ctx c, void* stream) {
@@ -341,7 +353,37 @@ kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, con
     double* yd = h2 + (m + 2);     // m + 2
     hipStream_t s = c->stream;
     // host Hessenberg and Givens state
-    double H[201 * 200], cs[200], sn[200], g[201], hh[202];
+    double H[201 * 200], cs[200], sn[200], g[201], hh_local[202];
+    double* hh = hh_local;
+    // graph mode: step j (preconditioner, operator, both Gram-Schmidt passes,
+    // the norm and the copies of the projections) is captured once per solve
+    // into graphs[j] and replayed every restart cycle
+    bool graphs = c->use_graphs;
+    std::vector<hipGraphExec_t> execs;
+    if (graphs) {
+        if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            graphs = false;
+        if (graphs && c->pinned_doubles < 202) {
+            if (c->pinned) hipHostFree(c->pinned);
+            c->pinned = nullptr;
+            c->pinned_doubles = 0;
+            if (hipHostMalloc((void**)&c->pinned, 202 * sizeof(double)) == hipSuccess)
+                c->pinned_doubles = 202;
+            else
+                graphs = false;
+        }
+        if (graphs) {
+            hh = c->pinned;
+            execs.assign(m, nullptr);
+        }
+    }
+    struct ExecGuard {
+        std::vector<hipGraphExec_t>* v;
+        ~ExecGuard() {
+            for (auto& e : *v)
+                if (e) hipGraphExecDestroy(e);
+        }
+    } guard{&execs};
     double nb2 = 0.0;
     KP_HIP(launch_mdot(s, rhs, 0, 1, rhs, N, partial, hd, 0));
     KP_HIP(hipMemcpyAsync(&nb2, hd, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -361,16 +403,46 @@ kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, con
         for (int j = 0; j < m; ++j) {
             double* vj = V + j * vec;
             double* zj = Z + j * vec;
-            if ((st = pc(vj, zj)) != KP_OK) return st;
-            if ((st = op(zj, w)) != KP_OK) return st;
-            // classical Gram-Schmidt, twice
-            KP_HIP(launch_mdot(s, V, vec, j + 1, w, N, partial, hd, 0));
-            KP_HIP(launch_mgs_update(s, V, vec, j + 1, hd, w, N));
-            KP_HIP(launch_mdot(s, V, vec, j + 1, w, N, partial, h2, 0));
-            KP_HIP(launch_mgs_update(s, V, vec, j + 1, h2, w, N));
-            KP_HIP(launch_mdot(s, w, 0, 1, w, N, partial, h2 + j + 1, 0));
-            KP_HIP(hipMemcpyAsync(hh, hd, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-            KP_HIP(hipMemcpyAsync(hh + j + 1, h2, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+            // the step's device work, enqueued on c->stream
+            auto step = [&]() -> kp_status {
+                kp_status s2;
+                hipStream_t q = c->stream;
+                if ((s2 = pc(vj, zj)) != KP_OK) return s2;
+                if ((s2 = op(zj, w)) != KP_OK) return s2;
+                // classical Gram-Schmidt, twice
+                KP_HIP(launch_mdot(q, V, vec, j + 1, w, N, partial, hd, 0));
+                KP_HIP(launch_mgs_update(q, V, vec, j + 1, hd, w, N));
+                KP_HIP(launch_mdot(q, V, vec, j + 1, w, N, partial, h2, 0));
+                KP_HIP(launch_mgs_update(q, V, vec, j + 1, h2, w, N));
+                KP_HIP(launch_mdot(q, w, 0, 1, w, N, partial, h2 + j + 1, 0));
+                KP_HIP(hipMemcpyAsync(hh, hd, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, q));
+                KP_HIP(hipMemcpyAsync(hh + j + 1, h2, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, q));
+                return KP_OK;
+            };
+            if (graphs && !execs[j]) {
+                // capture on the private stream (nothing runs during capture)
+                c->stream = c->cap_stream;
+                hipGraph_t graph = nullptr;
+                bool ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                const kp_status cst = ok ? step() : KP_ERR_HIP;
+                ok = (hipStreamEndCapture(c->cap_stream, &graph) == hipSuccess) && ok && cst == KP_OK;
+                c->stream = s;
+                if (ok && hipGraphInstantiate(&execs[j], graph, nullptr, nullptr, 0) != hipSuccess) {
+                    execs[j] = nullptr;
+                    ok = false;
+                }
+                if (graph) hipGraphDestroy(graph);
+                if (!ok) {
+                    hipGetLastError();
+                    graphs = false;  // this solve continues without graphs
+                    hh = hh_local;
+                }
+            }
+            if (graphs) {
+                KP_HIP(hipGraphLaunch(execs[j], s));
+            } else if ((st = step()) != KP_OK) {
+                return st;
+            }
             KP_HIP(hipStreamSynchronize(s));
             // column j: projections of both passes, then the norm
             double* col = H + j * (m + 1);

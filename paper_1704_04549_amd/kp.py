@@ -20,6 +20,7 @@ KP_OK, KP_ERR_ARG, KP_ERR_ALLOC, KP_ERR_HIP, KP_ERR_NUMERIC, KP_ERR_NOCONV, KP_E
 KP_FP64, KP_FP32, KP_BF16, KP_BF16X3 = 0, 1, 2, 3
 KP_SETUP_SVD, KP_SETUP_LEARNED, KP_SETUP_LEARNED_WARM = 0, 1, 2
 KP_PC_NONE, KP_PC_KSVD, KP_PC_BJ = 0, 1, 2
+KP_OPT_FGMRES_GRAPHS, KP_OPT_APPLY_MFMA16 = 1, 2
 ELEM_LANCZOS_NOCONV, ELEM_SINGULAR_FACTOR, ELEM_SCHUR_NOCONV, ELEM_NONFINITE = 1, 2, 4, 8
 ELEM_LEARNED_REJECTED, ELEM_LEARNED_WARM = 16, 32
 REC_LEN = 16
@@ -75,6 +76,7 @@ def lib() -> ctypes.CDLL:
                              ctypes.c_int),
             "kp_mlp_predict": ([vp, vp, bp, i32, vp], ctypes.c_int),
             "kp_set_model": ([vp, vp], ctypes.c_int),
+            "kp_set_option": ([vp, i32, i64], ctypes.c_int),
             "kp_mixed_plan_create": ([vp, i64, vp, ctypes.POINTER(vp)], ctypes.c_int),
             "kp_mixed_plan_destroy": ([vp], ctypes.c_int),
             "kp_mixed_plan_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -158,6 +160,9 @@ class Ctx:
             self.close()
         except Exception:
             pass
+
+    def set_option(self, option, value):
+        _check(lib().kp_set_option(self.h, int(option), int(value)), "kp_set_option")
 
     def set_stream(self, stream):
         self.stream = stream
