@@ -28,6 +28,9 @@ hipError_t launch_learned_guess(hipStream_t s, int64_t E, int dim, int n, const 
 // skip[e] = accept[e] || !(status[e] & KP_ELEM_LANCZOS_NOCONV)
 hipError_t launch_fallback_mask(hipStream_t s, int64_t E, const int32_t* accept, const int32_t* status,
                                 int32_t* skip);
+// apply tables from the factors (three kernels: prepare, Schur, finish);
+// prepare and finish run on four waves per element when their scratch fits
+constexpr size_t kTables4LdsMax = 144 * 1024;
 // apply tables from the factors (three kernels: prepare, Schur, finish)
 hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank,
                               const double* factors, double* tab64, int8_t* kinds,

@@ -99,6 +99,225 @@ __global__ void __launch_bounds__(64) k_tables_prepare(int64_t E, int dim, int n
     }
 }
 
+// Four-wave variants of prepare and finish (256 threads per element): the
+// independent pieces of the work run on separate waves, each with its own
+// LDS scratch, and give the same results as the one-wave kernels (every
+// matrix is formed by the same arithmetic; the angle search compares the
+// same scores with the same tie rule).
+//   prepare: wave w scores the rotation angles k = w and w + 4; waves 0..2
+//            form the inverses; waves 0, 1 form C1, C2.
+//   finish:  waves 0, 1 form the two L = Q^T inverse tables; wave w forms
+//            the N_j with j = w mod 4 (a 2 x 2 block of T2 stays on one wave).
+__global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int n, int rank,
+                                                         const double* factors, double* tab64,
+                                                         int32_t* status) {
+    extern __shared__ double lds[];
+    __shared__ double red[4 * kMaxReduce];
+    __shared__ double sh[4][kMaxN + 8];
+    __shared__ int ipiv[4][kMaxN];
+    __shared__ double scores[8];
+    __shared__ int fail[4];
+    BlockTeam bt{red};
+    WaveTeam wt;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long nn = (long)n * n;
+    const int nf = dim == 2 ? 2 * rank : 5;
+    const long ne = tab_entries(n);
+    double* F = lds;                       // nf n^2
+    double* R6 = F + nf * nn;              // left 1
+    double* R7 = R6 + nn;                  // left 2 (inverted)
+    double* R8 = R7 + nn;                  // right 1 (inverted)
+    double* R9 = R8 + nn;                  // right 2
+    double* Wv = R9 + nn + wv * 3 * nn;    // this wave's scratch: 3 n^2
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        for (long t = threadIdx.x; t < nf * nn; t += blockDim.x) F[t] = factors[e * nf * nn + t];
+        if (threadIdx.x < 4) fail[threadIdx.x] = 0;
+        __syncthreads();
+        double* tab = tab64 + e * ne;
+        double* N = tab + 7 * nn;
+        if (dim == 2 && rank == 1) {
+            // no pair to rotate: the one-team path (its work fits in R6.. onward)
+            const int st = tables_prepare(bt, dim, n, rank, F, tab, N, R6, ipiv[0], sh[0]);
+            if (threadIdx.x == 0) status[e] |= st;
+            __syncthreads();
+            continue;
+        }
+        for (long t = threadIdx.x; t < 3 * nn; t += blockDim.x) tab[t] = 0.0;
+        // balance the norms within each term
+        const double* l1 = dim == 2 ? F : F + nn;
+        const double* l2 = dim == 2 ? F + 2 * nn : F + 3 * nn;
+        const double* r1 = dim == 2 ? F + nn : F + 2 * nn;
+        const double* r2 = dim == 2 ? F + 3 * nn : F + 4 * nn;
+        double p1 = 0.0, p2 = 0.0;
+        for (long t = threadIdx.x; t < nn; t += blockDim.x) {
+            p1 += l1[t] * l1[t];
+            p2 += l2[t] * l2[t];
+        }
+        const double s1 = sqrt(bt.sum(p1)), s2 = sqrt(bt.sum(p2));
+        const double a1 = s1 > 0.0 ? s1 : 1.0, a2 = s2 > 0.0 ? s2 : 1.0;
+        for (long t = threadIdx.x; t < nn; t += blockDim.x) {
+            R6[t] = l1[t] / a1;
+            R9[t] = r1[t] * a1;  // temporarily: balanced right 1
+            R7[t] = l2[t] / a2;
+            R8[t] = r2[t] * a2;  // temporarily: balanced right 2
+        }
+        __syncthreads();
+        // angle search: kappa_1 of the two factors to invert for k = wv, wv + 4
+        const double pi = 3.14159265358979323846;
+        for (int k = wv; k < 8; k += 4) {
+            const double c = cos(pi * k / 8.0), sn = sin(pi * k / 8.0);
+            double* W0 = Wv;
+            double* W1 = Wv + nn;
+            double* W2 = Wv + 2 * nn;
+            for (long t = lane; t < nn; t += 64) {
+                W0[t] = -sn * R6[t] + c * R7[t];
+                W1[t] = c * R9[t] + sn * R8[t];
+            }
+            wt.sync();
+            double score = 1.0;
+            for (int q = 0; q < 2; ++q) {
+                double* M = q == 0 ? W0 : W1;
+                const double nm = norm1(wt, n, M, sh[wv]);
+                const bool ok = invert(wt, n, M, W2, ipiv[wv], sh[wv] + 8);
+                const double ni = norm1(wt, n, W2, sh[wv]);
+                score *= ok ? nm * ni : 1e300;
+            }
+            if (!(score == score)) score = 1e300;
+            if (lane == 0) scores[k] = score;
+            wt.sync();
+        }
+        __syncthreads();
+        int bestk = 0;
+        for (int k = 1; k < 8; ++k)
+            if (scores[k] < scores[bestk]) bestk = k;
+        {
+            const double c = cos(pi * bestk / 8.0), sn = sin(pi * bestk / 8.0);
+            for (long t = threadIdx.x; t < nn; t += blockDim.x) {
+                const double bl1 = R6[t], bl2 = R7[t], br1 = R9[t], br2 = R8[t];
+                R6[t] = c * bl1 + sn * bl2;
+                R7[t] = -sn * bl1 + c * bl2;
+                R8[t] = c * br1 + sn * br2;
+                R9[t] = -sn * br1 + c * br2;
+            }
+        }
+        __syncthreads();
+        // inverses into the L slots: 2D L0 = inv(A2'), L1 = inv(B1');
+        // 3D L0 = inv(A1), L1 = inv(B2'), L2 = inv(C1')
+        const double* srcs[3] = {dim == 2 ? R7 : F, dim == 2 ? R8 : R7, R8};
+        const int nq = dim == 3 ? 3 : 2;
+        if (wv < nq) {
+            double* W0 = Wv;
+            double* W2 = Wv + 2 * nn;
+            for (long t = lane; t < nn; t += 64) W0[t] = srcs[wv][t];
+            wt.sync();
+            if (!invert(wt, n, W0, W2, ipiv[wv], sh[wv] + 8) && lane == 0) fail[wv] = 1;
+            double* dst = tab + wv * nn;
+            for (long t = lane; t < nn; t += 64) dst[t] = W2[t];
+            // keep the inverse in the wave's scratch for C below
+            for (long t = lane; t < nn; t += 64) W0[t] = W2[t];
+            wt.sync();
+        }
+        __syncthreads();
+        // C1 = inv(Y) G_y, C2 = inv(Z) G_z (2D: Y = A2', Z = B1'; 3D: Y = B2', Z = C1')
+        if (wv < 2) {
+            const int src_wave = dim == 2 ? wv : wv + 1;  // the wave that holds inv(Y) / inv(Z)
+            const double* inv = lds + nf * nn + 4 * nn + src_wave * 3 * nn;
+            const double* G = wv == 0 ? R6 : R9;
+            double* out = Wv + nn;
+            mm(wt, n, inv, G, out);
+            for (long t = lane; t < nn; t += 64) N[wv * nn + t] = out[t];
+            wt.sync();
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) status[e] |= (fail[0] | fail[1] | fail[2]) ? 2 : 0;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_tables_finish4(int64_t E, int dim, int n, double* tab64,
+                                                        int8_t* kinds, int32_t* status) {
+    extern __shared__ double lds[];
+    __shared__ double red[4 * kMaxReduce];
+    __shared__ double sh[4][kMaxN + 8];
+    __shared__ int ipiv[4][kMaxN];
+    __shared__ int fail[4];
+    BlockTeam bt{red};
+    WaveTeam wt;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long nn = (long)n * n;
+    const long ne = tab_entries(n);
+    double* T1 = lds;
+    double* Wv = lds + nn + wv * 4 * nn;  // W0, W1, W4, W5
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        double* tab = tab64 + e * ne;
+        double* N = tab + 7 * nn;
+        const double* T2 = tab + 6 * nn;
+        int8_t* kd = kinds + e * kMaxN;
+        if (threadIdx.x < 4) fail[threadIdx.x] = 0;
+        for (long t = threadIdx.x; t < nn; t += blockDim.x) T1[t] = tab[5 * nn + t];
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            int k = 0;
+            if (j > 0 && T2[j * n + j - 1] != 0.0) k = 2;
+            if (j + 1 < n && T2[(j + 1) * n + j] != 0.0) k = 1;
+            kd[j] = (int8_t)k;
+        }
+        __syncthreads();
+        double* W0 = Wv;
+        double* W1 = Wv + nn;
+        double* W4 = Wv + 2 * nn;
+        double* W5 = Wv + 3 * nn;
+        // L = Q^T inverse: 2D L0, L1; 3D L1, L2 (waves 0 and 1)
+        if (wv < 2) {
+            double* Lq = dim == 2 ? tab + wv * nn : tab + (wv + 1) * nn;
+            const double* Rq = tab + (3 + wv) * nn;
+            for (long t = lane; t < nn; t += 64) {
+                W0[t] = Lq[t];
+                W4[t] = Rq[t];
+            }
+            wt.sync();
+            mtm(wt, n, W4, W0, W1);
+            for (long t = lane; t < nn; t += 64) Lq[t] = W1[t];
+            wt.sync();
+        }
+        // N_j, j = wv mod 4
+        for (int j = wv; j < n; j += 4) {
+            const int k = kd[j];
+            if (k == 1) continue;  // formed with its partner j + 1
+            if (k == 0) {
+                const double tj = T2[j * n + j];
+                for (long t = lane; t < nn; t += 64) W0[t] = T1[t] + ((t / n == t % n) ? tj : 0.0);
+                wt.sync();
+                if (!invert(wt, n, W0, W1, ipiv[wv], sh[wv] + 8) && lane == 0) fail[wv] = 1;
+                for (long t = lane; t < nn; t += 64) N[(long)j * nn + t] = W1[t];
+                wt.sync();
+            } else {
+                const double p = T2[j * n + j], q = T2[(j - 1) * n + j], sv = T2[j * n + j - 1];
+                for (long t = lane; t < nn; t += 64) W4[t] = T1[t] + ((t / n == t % n) ? p : 0.0);
+                wt.sync();
+                mm(wt, n, W4, W4, W5);
+                for (long t = lane; t < nn; t += 64) W0[t] = W5[t] - ((t / n == t % n) ? q * sv : 0.0);
+                wt.sync();
+                if (!invert(wt, n, W0, W1, ipiv[wv], sh[wv] + 8) && lane == 0) fail[wv] = 1;
+                for (long t = lane; t < nn; t += 64) {
+                    N[(long)j * nn + t] = W1[t];
+                    N[(long)(j - 1) * nn + t] = W1[t];
+                }
+                wt.sync();
+            }
+        }
+        __syncthreads();
+        // non-finite check (a NaN fails the comparison)
+        double bad = 0.0;
+        for (long t = threadIdx.x; t < 7L * nn; t += blockDim.x)
+            if (!(fabs(tab[t]) < 1e300)) bad = 1.0;
+        for (long t = threadIdx.x; t < (long)n * nn; t += blockDim.x)
+            if (!(fabs(N[t]) < 1e300)) bad = 1.0;
+        bad = bt.max(bad);
+        if (threadIdx.x == 0) status[e] |= ((fail[0] | fail[1] | fail[2] | fail[3]) ? 2 : 0) | (bad != 0.0 ? 8 : 0);
+        __syncthreads();
+    }
+}
+
 // work item w = 2 e + i: real Schur form of C_(i+1), held in N slot i, into
 // the T_(i+1) and R_i slots
 __global__ void __launch_bounds__(64) k_tables_schur(int64_t E, int n, double* tab64,
@@ -210,14 +429,25 @@ hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank
     // at most (6 + 10) 32^2 doubles = 128 KiB of LDS (2D rank 3, n = 32)
     const size_t lds = (nf + 10) * nn * sizeof(double);
     const int grid = (int)(E < 65536 ? E : 65536);
-    hipLaunchKernelGGL(k_tables_prepare, dim3(grid), dim3(64), lds, s, E, dim, n, rank, factors,
-                       tab64, status);
+    // four-wave kernels where their scratch fits in LDS, else one wave per element
+    const size_t lds4p = (nf + 4 + 12) * nn * sizeof(double);
+    const size_t lds4f = 17 * nn * sizeof(double);
+    if (lds4p <= kTables4LdsMax)
+        hipLaunchKernelGGL(k_tables_prepare4, dim3(grid), dim3(256), lds4p, s, E, dim, n, rank, factors,
+                           tab64, status);
+    else
+        hipLaunchKernelGGL(k_tables_prepare, dim3(grid), dim3(64), lds, s, E, dim, n, rank, factors,
+                           tab64, status);
     const int64_t items = 2 * E;
     const int grid2 = (int)(items < 65536 ? items : 65536);
     hipLaunchKernelGGL(k_tables_schur, dim3(grid2), dim3(64), 2 * nn * sizeof(double), s, E, n,
                        tab64, status);
-    hipLaunchKernelGGL(k_tables_finish, dim3(grid), dim3(64), 6 * nn * sizeof(double), s, E, dim, n,
-                       tab64, kinds, status);
+    if (lds4f <= kTables4LdsMax)
+        hipLaunchKernelGGL(k_tables_finish4, dim3(grid), dim3(256), lds4f, s, E, dim, n, tab64, kinds,
+                           status);
+    else
+        hipLaunchKernelGGL(k_tables_finish, dim3(grid), dim3(64), 6 * nn * sizeof(double), s, E, dim, n,
+                           tab64, kinds, status);
     return hipGetLastError();
 }
 

@@ -183,6 +183,21 @@ struct WaveTeam {
         for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
         return v;
     }
+    // index of the largest |v[i*stride]| for i in [lo, hi) (lowest index on ties)
+    __device__ int argmax_abs(const double* v, int stride, int lo, int hi) const {
+        double bv = -1.0;
+        int bi = lo;
+        for (int i = lo + (int)(threadIdx.x & 63); i < hi; i += 64) {
+            const double a = fabs(v[i * stride]);
+            if (a > bv) { bv = a; bi = i; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        return bi;
+    }
 };
 #endif
 
