@@ -413,6 +413,106 @@ KP_INLINE bool tridiag_eig(int k, double* d, double* e, double* Z) {
     return true;
 }
 
+// The same QL iteration with the eigenvector updates spread over a team:
+// the leader runs each sweep (the scalar recurrence, identical arithmetic)
+// and records its rotations in rot; then every thread applies the sweep's
+// rotations to its own rows of Z.  Results equal tridiag_eig's.
+// rot: 2 k doubles; qc: 8 ints of shared control state.
+template <class Team>
+KP_HD bool tridiag_eig_team(const Team& tm, int k, double* d, double* e, double* Z, double* rot, int* qc) {
+    for (int t = tm.tid(); t < k * k; t += tm.size()) Z[t] = (t / k == t % k) ? 1.0 : 0.0;
+    if (k == 1) {
+        tm.sync();
+        return true;
+    }
+    if (tm.leader()) {
+        e[k - 1] = 0.0;
+        qc[0] = 0;  // l
+        qc[1] = 0;  // iterations at this l
+    }
+    tm.sync();
+    const double eps = 2.220446049250313e-16;
+    while (true) {
+        if (tm.leader()) {
+            int l = qc[0], iter = qc[1];
+            int status = 0, mm_out = 0, ilow = 0;
+            while (true) {
+                if (l >= k) {
+                    status = 1;
+                    break;
+                }
+                int mm = l;
+                for (; mm < k - 1; ++mm) {
+                    const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
+                    if (fabs(e[mm]) <= eps * dd) break;
+                }
+                if (mm == l) {
+                    ++l;
+                    iter = 0;
+                    continue;
+                }
+                if (++iter > 60) {
+                    status = 2;
+                    break;
+                }
+                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                double r = hypot(g, 1.0);
+                g = d[mm] - d[l] + e[l] / (g + (g >= 0.0 ? fabs(r) : -fabs(r)));
+                double s = 1.0, c = 1.0, p = 0.0;
+                int i = mm - 1;
+                bool early = false;
+                for (; i >= l; --i) {
+                    const double f = s * e[i], b = c * e[i];
+                    r = hypot(f, g);
+                    e[i + 1] = r;
+                    if (r == 0.0) {
+                        d[i + 1] -= p;
+                        e[mm] = 0.0;
+                        early = true;
+                        break;
+                    }
+                    s = f / r;
+                    c = g / r;
+                    g = d[i + 1] - p;
+                    r = (d[i] - g) * s + 2.0 * c * b;
+                    p = s * r;
+                    d[i + 1] = g + p;
+                    g = c * r - b;
+                    rot[2 * i] = s;
+                    rot[2 * i + 1] = c;
+                }
+                if (!early) {
+                    d[l] -= p;
+                    e[l] = g;
+                    e[mm] = 0.0;
+                }
+                mm_out = mm;
+                ilow = early ? i + 1 : l;
+                break;
+            }
+            qc[0] = l;
+            qc[1] = iter;
+            qc[2] = status;
+            qc[3] = mm_out;
+            qc[4] = ilow;
+        }
+        tm.sync();
+        const int status = qc[2];
+        if (status != 0) return status == 1;
+        const int mm = qc[3], ilow = qc[4];
+        for (int q = tm.tid(); q < k; q += tm.size()) {
+            double* zr = Z + q * k;
+            for (int i = mm - 1; i >= ilow; --i) {
+                const double sn = rot[2 * i], cs = rot[2 * i + 1];
+                const double f = zr[i + 1];
+                zr[i + 1] = sn * zr[i] + cs * f;
+                zr[i] = cs * zr[i] - sn * f;
+            }
+        }
+        tm.sync();
+    }
+}
+
 // ==================================================== Lanczos (Alg. 2)
 // Top-r eigenpairs of G = R(A) R(A)^T by symmetric Lanczos with full
 // reorthogonalisation (classical Gram-Schmidt, applied twice).  Its Krylov
@@ -433,6 +533,8 @@ struct LanczosWork {
     double* sel;    // r * kmax selected eigenvectors of T
     double* theta;  // r
     int* ctrl;      // 8 ints: [0] converged flag, [1] steps, [4..4+r) selected Ritz indices
+    double* rot;    // 2 kmax: rotations of one QL sweep
+    int* qc;        // 8 ints: QL control state
 };
 
 template <class Team, class Op>
@@ -488,7 +590,10 @@ KP_HD int lanczos_top(const Team& tm, const Op& op, int m, int r, int kmax, doub
                     L.d[i] = L.alpha[i];
                     L.e[i] = (i + 1 < steps) ? L.beta[i] : 0.0;
                 }
-                bool ok = tridiag_eig(steps, L.d, L.e, L.Z);
+            }
+            tm.sync();
+            const bool ok = tridiag_eig_team(tm, steps, L.d, L.e, L.Z, L.rot, L.qc);
+            if (tm.leader()) {
                 // select the r largest Ritz values (descending)
                 int rr = r < steps ? r : steps;
                 bool conv = ok;
@@ -1335,6 +1440,7 @@ KP_INLINE long setup_work_doubles(int dim, int n, bool expl, int rank = 2) {
     t += 64;                              // small
     t += (kmax + 1) * m + m + (kmax + 2) + 2 * (kmax + 1) + 2 * kmax + kmax * kmax + 3 * kmax + 3;
     t += 8;                               // ctrl (as doubles)
+    t += 2 * kmax + 4;                    // rot, qc
     if (rank >= 3) t += (kmax + 16) * m + kmax * kmax + kmax + 8;  // Wm (+ block vectors), Vr, norms, order
     return (t + 31) / 32 * 32;
 }
@@ -1366,6 +1472,8 @@ KP_INLINE SetupWork carve_setup_work(double* base, int dim, int n, bool expl, in
     W.L.sel = p; p += 3 * kmax;
     W.L.theta = p; p += 3;
     W.L.ctrl = (int*)p; p += 8;
+    W.L.rot = p; p += 2 * kmax;
+    W.L.qc = (int*)p; p += 4;
     W.Wm = nullptr;
     W.Vr = nullptr;
     if (rank >= 3) {
@@ -1379,7 +1487,7 @@ KP_INLINE SetupWork carve_setup_work(double* base, int dim, int n, bool expl, in
 // and the operator scratch d, placed in fast shared memory: doubles needed
 KP_INLINE long setup_small_doubles(int n, bool expl) {
     const long kmax = lanczos_kmax(n, expl);
-    return (kmax + 2) + 2 * (kmax + 1) + 2 * kmax + kmax * kmax + 3 * kmax + 3 + 8 +
+    return (kmax + 2) + 2 * (kmax + 1) + 2 * kmax + kmax * kmax + 3 * kmax + 3 + 8 + 2 * kmax + 4 +
            (long)n * n + 64;
 }
 KP_INLINE void carve_small(double* p, int n, bool expl, SetupWork* W) {
@@ -1393,6 +1501,8 @@ KP_INLINE void carve_small(double* p, int n, bool expl, SetupWork* W) {
     W->L.sel = p; p += 3 * kmax;
     W->L.theta = p; p += 3;
     W->L.ctrl = (int*)p; p += 8;
+    W->L.rot = p; p += 2 * kmax;
+    W->L.qc = (int*)p; p += 4;
     W->d = p; p += (long)n * n;
     W->small = p;
 }

@@ -11,6 +11,13 @@ namespace kp {
 
 hipError_t launch_build_blocks(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
                                const double* params, double* out);
+// workspace slots of the setup kernels for E elements: a multiple of 4 (one
+// wave per element, four per workgroup), at most 2048
+constexpr size_t kSetupWavesLdsMax = 150 * 1024;
+inline int setup_slots(int64_t E) {
+    const int64_t g = E < 2048 ? E : 2048;
+    return (int)((g + 3) / 4 * 4);
+}
 hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int rank,
                         const Tables1D* tab, const double* params, const double* blocks,
                         const double* guess, double* factors, double* sigma, int32_t* status,

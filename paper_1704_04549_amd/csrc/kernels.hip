@@ -71,6 +71,52 @@ __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int ra
     }
 }
 
+// One wave per element (four elements per workgroup, independent waves, no
+// workgroup barrier inside the loop): each wave has its own workspace slot
+// and its own LDS small arrays; the workgroup shares the 1D tables.
+// Specialised on the dimension and on explicit / structured input, so that
+// each instance carries only its own path (registers are sized for the
+// longest path of an instance).
+template <bool kRefine, int DIM, bool EXPL>
+__global__ void __launch_bounds__(256) k_setup_waves(int64_t E, int dim_rt, int n, int rank,
+                                                     const Tables1D* tab, const double* params,
+                                                     const double* blocks, const double* guess,
+                                                     double* factors, double* sigma, int32_t* status,
+                                                     double* ws, int64_t ws_stride, const int32_t* skip,
+                                                     int32_t status_or, int64_t small_stride) {
+    __shared__ Tables1D T;
+    extern __shared__ double small[];
+    {
+        const double* src = (const double*)tab;
+        double* dst = (double*)&T;
+        for (int i = threadIdx.x; i < (int)(sizeof(Tables1D) / sizeof(double)); i += blockDim.x)
+            dst[i] = src[i];
+        __syncthreads();
+    }
+    (void)dim_rt;
+    constexpr int dim = DIM;
+    constexpr bool expl = EXPL;
+    WaveTeam tm;
+    const int wv = threadIdx.x >> 6;
+    const int64_t slot = (int64_t)blockIdx.x * 4 + wv;
+    SetupWork W = carve_setup_work(ws + slot * ws_stride, dim, n, expl, rank);
+    carve_small(small + wv * small_stride, n, expl, &W);
+    const long nn = (long)n * n;
+    const long nd = dim == 2 ? nn : nn * n;
+    const int nf = dim == 2 ? 2 * rank : 5;
+    const long gs = dim == 3 ? 2 : 1;
+    for (int64_t e = slot; e < E; e += (int64_t)gridDim.x * 4) {
+        if (skip && skip[e]) continue;
+        const double* blk = expl ? blocks + e * nd * nd : nullptr;
+        const double* g = guess ? guess + e * gs * nn : nullptr;
+        const double* g2 = (guess && dim == 3) ? g + nn : nullptr;
+        int st = setup_element<kRefine>(tm, DIM, n, rank, T, params + e * kRecLen, blk, g,
+                                        factors + e * nf * nn, sigma + e * 4, W, g2);
+        if ((threadIdx.x & 63) == 0) status[e] = st | status_or;
+        tm.sync();
+    }
+}
+
 // ---------------------------------------------------------- apply tables
 // Three kernels: prepare (one wave per element: pair rotation, inverses, C1
 // and C2), Schur (one wave per (element, C matrix), with a small LDS
@@ -413,10 +459,25 @@ hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int 
                         const Tables1D* tab, const double* params, const double* blocks,
                         const double* guess, double* factors, double* sigma, int32_t* status,
                         double* ws, int64_t ws_stride, const int32_t* skip, int32_t status_or) {
-    const size_t lds = setup_small_doubles(n, blocks != nullptr) * sizeof(double);
-    auto kern = rank >= 3 ? k_setup<true> : k_setup<false>;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, E, dim, n, rank, tab, params, blocks,
-                       guess, factors, sigma, status, ws, ws_stride, skip, status_or);
+    const size_t small = setup_small_doubles(n, blocks != nullptr);
+    if (rank >= 3) {
+        hipLaunchKernelGGL(k_setup<true>, dim3(grid), dim3(256), small * sizeof(double), s, E, dim, n, rank,
+                           tab, params, blocks, guess, factors, sigma, status, ws, ws_stride, skip, status_or);
+    } else if (4 * ((small + 31) / 32 * 32) * sizeof(double) + sizeof(Tables1D) > kSetupWavesLdsMax) {
+        // the four waves' small arrays do not fit: one workgroup per element
+        hipLaunchKernelGGL(k_setup<false>, dim3(grid), dim3(256), small * sizeof(double), s, E, dim, n, rank,
+                           tab, params, blocks, guess, factors, sigma, status, ws, ws_stride, skip, status_or);
+    } else {
+        // one wave per element: the grid's workspace slots (a multiple of 4,
+        // see setup_slots) serve grid / 4 workgroups
+        const int64_t small_stride = (small + 31) / 32 * 32;
+        const int g4 = grid / 4;
+        auto kern = dim == 3 ? (blocks ? k_setup_waves<false, 3, true> : k_setup_waves<false, 3, false>)
+                             : (blocks ? k_setup_waves<false, 2, true> : k_setup_waves<false, 2, false>);
+        hipLaunchKernelGGL(kern, dim3(g4), dim3(256), 4 * small_stride * sizeof(double), s, E, dim, n, rank,
+                           tab, params, blocks, guess, factors, sigma, status, ws, ws_stride, skip, status_or,
+                           small_stride);
+    }
     return hipGetLastError();
 }
 

@@ -148,7 +148,7 @@ kp_status kp_setup(kp_ctx c, const kp_batch* b, int32_t rank, int32_t mode, void
     hipSetDevice(c->device);
     const bool expl = b->blocks != nullptr;
     const int64_t wsd = setup_work_doubles(b->dim, b->n, expl, rank);
-    int grid = (int)(E < 2048 ? E : 2048);
+    const int grid = setup_slots(E);
     if ((st = ensure_ws(c, (size_t)wsd * grid * sizeof(double), &c->ws, &c->ws_bytes)) != KP_OK)
         return st;
     char* pc = (char*)precond;

@@ -183,6 +183,28 @@ struct WaveTeam {
         for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
         return v;
     }
+    // out[j] = sum_i Q[j*ldq + i] * v[i] for j < k (lanes over i, then the
+    // wave reduction); out is visible to the wave on return
+    __device__ void dots(const double* Q, long ldq, int k, const double* v, int len, double* out) const {
+        const int lane = (int)(threadIdx.x & 63);
+        for (int j = 0; j < k; ++j) {
+            double s = 0.0;
+            for (int i = lane; i < len; i += 64) s += Q[j * ldq + i] * v[i];
+            s = wave_sum(s);
+            if (lane == 0) out[j] = s;
+        }
+        sync();
+    }
+    // v[0..k) hold per-lane partials on entry and the wave sums on exit
+    __device__ void sum_many(double* v, int k) const {
+        for (int i = 0; i < k; ++i) v[i] = wave_sum(v[i]);
+    }
+    // the wave is a single group
+    __device__ int groups() const { return 1; }
+    __device__ int group() const { return 0; }
+    __device__ int lane() const { return (int)(threadIdx.x & 63); }
+    __device__ int group_size() const { return 64; }
+    __device__ double group_sum(double v) const { return wave_sum(v); }
     // index of the largest |v[i*stride]| for i in [lo, hi) (lowest index on ties)
     __device__ int argmax_abs(const double* v, int stride, int lo, int hi) const {
         double bv = -1.0;
