@@ -250,7 +250,10 @@ kp_status kp_mixed_apply(kp_ctx ctx, kp_mixed_plan plan, const void* precond, in
 
 /* Autotune the apply launch: for every (dim, n) in the batch, time its
  * elements applied by a whole workgroup each and by one wave each (four per
- * workgroup), keep the faster, and rebuild the plan's work list.  r and z
+ * workgroup), keep the faster, and rebuild the plan's work list.  The wave
+ * mode is tried only where four elements' three FP64 buffers fit in 150 KiB
+ * of LDS (every 2D n up to 40, 3D n up to 11), so the chosen work list serves
+ * every precision.  r and z
  * are used as scratch (z is overwritten).  modes_h (or NULL): triples
  * (dim, n, mode 0 workgroup / 1 wave), -1 after the last.  Synchronises. */
 kp_status kp_mixed_autotune(kp_ctx ctx, kp_mixed_plan plan, const void* precond, int32_t prec,

@@ -26,6 +26,16 @@ struct MixedElem {
 // one per wave, each processed by its wave alone.
 constexpr int kMixedItemWidth = 4;
 
+// Dynamic LDS of one apply launch: three element-sized buffers per workgroup
+// item, or per wave of a wave item.  A launch above the limit is refused; a
+// (dim, n) class takes the wave mode only if it fits at FP64, so one work list
+// serves every precision.
+constexpr size_t kMixedApplyLdsMax = 150 * 1024;
+inline size_t mixed_apply_lds(size_t elem_bytes, long block_nd, long wave_nd) {
+    const long need = block_nd > kMixedItemWidth * wave_nd ? block_nd : kMixedItemWidth * wave_nd;
+    return 3 * (size_t)need * elem_bytes;
+}
+
 hipError_t launch_mixed_setup(hipStream_t s, int grid, int64_t E, const MixedElem* el, const int32_t* order,
                               Tables1D* const* tabs, const double* params, double* factors, double* sigma,
                               int32_t* status, double* ws, int64_t ws_stride, size_t small_doubles);

@@ -176,9 +176,8 @@ hipError_t launch_mixed_apply(hipStream_t s, int prec, int grid, int n_items, in
                               const MixedElem* el, const void* tabs, const int8_t* kinds, const double* r,
                               double* z, long block_nd, long wave_nd) {
     if (n_items <= 0) return hipSuccess;
-    const long need = 3 * (block_nd > kMixedItemWidth * wave_nd ? block_nd : kMixedItemWidth * wave_nd);
-    const size_t es = prec == 0 ? sizeof(double) : sizeof(float);
-    const size_t lds = need * es;
+    const size_t lds = mixed_apply_lds(prec == 0 ? sizeof(double) : sizeof(float), block_nd, wave_nd);
+    if (lds > kMixedApplyLdsMax) return hipErrorInvalidValue;
     if (prec == 0)
         hipLaunchKernelGGL((k_mixed_apply<double, double, RoundNone>), dim3(grid), dim3(256), lds, s, n_items,
                            n_block, items, el, (const double*)tabs, kinds, r, z, block_nd, wave_nd, RoundNone());

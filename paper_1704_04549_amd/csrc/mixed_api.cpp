@@ -289,6 +289,8 @@ kp_status kp_mixed_autotune(kp_ctx c, kp_mixed_plan p, const void* precond, int3
                     members.push_back((int32_t)e);
                     nd = elem_nd(p->h_el[e]);
                 }
+            // the wave mode holds four elements per workgroup: only where they fit at FP64
+            if (md == 1 && mixed_apply_lds(sizeof(double), 0, nd) > kMixedApplyLdsMax) break;
             const int width = md == 0 ? 1 : kMixedItemWidth;
             const int nit = (int)((members.size() + width - 1) / width);
             items.assign((size_t)nit * kMixedItemWidth, -1);

@@ -110,6 +110,39 @@ def test_mixed_setup_apply_autotune_operator(ctx):
     plan.close()
 
 
+def test_mixed_autotune_large_3d(ctx):
+    """3D n = 12 and 16 elements: four of them per workgroup would not fit in
+    LDS at FP64, so the autotuner keeps those classes on whole workgroups; the
+    list tuned at FP32 then serves every precision."""
+    import torch
+
+    from paper_1704_04549_amd import kp
+    from tests.gpu_util import to_dev
+    dims = np.array([3, 2, 3, 3, 2, 3])
+    ns = np.array([16, 31, 12, 4, 9, 16])
+    recs = np.zeros((len(dims), synth.REC_LEN))
+    for e, (d, n) in enumerate(zip(dims, ns)):
+        recs[e] = synth.draw_params(1, int(d), 7000 + e, face=True)[0]
+    print(f"mixed large E={len(dims)}", flush=True)
+    _, fo = oracle_parts(dims, ns, recs)
+    plan = kp.MixedPlan(ctx, dims, ns, to_dev(recs))
+    pc, st = plan.setup()
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    off = plan.offsets
+    r = np.random.default_rng(4).standard_normal(plan.vec_len)
+    zref = np.concatenate([dense_solve(fo[e], r[off[e]:off[e + 1]]) for e in range(len(dims))])
+    rd = to_dev(r)
+    modes = plan.autotune(pc, "fp32", rd, torch.empty_like(rd))
+    print(f"  modes {modes}", flush=True)
+    assert modes[(3, 16)] == 0 and modes[(3, 12)] == 0
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5), ("bf16", 2e-2), ("bf16x3", 1e-4)):
+        z = plan.apply(pc, prec, rd).cpu().numpy()
+        print(f"  {prec}: {rel(z, zref):.2e}", flush=True)
+        assert rel(z, zref) <= tol, prec
+    plan.close()
+
+
 def test_mixed_fgmres_matches_oracle(ctx):
     from paper_1704_04549_amd import kp
     from tests.gpu_util import to_dev
