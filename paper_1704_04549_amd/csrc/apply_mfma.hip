@@ -38,7 +38,33 @@ constexpr int kTensor = 16 * kSA;
 
 __device__ __forceinline__ int xidx(int a, int b, int c) { return a * kSA + b * kSB + c; }
 
-__device__ __forceinline__ short bf16s(float v) { return (short)f32_to_bf16(v); }
+// f32 -> bf16, round to nearest even, on the hardware converter (gfx950
+// v_cvt_pk_bf16_f32); two at a time where the values come in pairs
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ short bf16s(float v) { return __builtin_bit_cast(short, (__bf16)v); }
+__device__ __forceinline__ unsigned bf16x2s(float a, float b) {
+    const floatx2 f = {a, b};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f, bf16x2));
+}
+__device__ __forceinline__ shortx4 bf16x4s(float a, float b, float c, float d) {
+    const unsigned lo = bf16x2s(a, b), hi = bf16x2s(c, d);
+    shortx4 r;
+    r[0] = (short)(lo & 0xffffu);
+    r[1] = (short)(lo >> 16);
+    r[2] = (short)(hi & 0xffffu);
+    r[3] = (short)(hi >> 16);
+    return r;
+}
+
+// a register tile held as a plain array (FP32, FP64) or as a vector (the BF16
+// forms, whose conversions otherwise keep a memory copy of the tile)
+template <class T>
+struct Arr4 {
+    T v[4];
+    __device__ __forceinline__ T& operator[](int i) { return v[i]; }
+    __device__ __forceinline__ const T& operator[](int i) const { return v[i]; }
+};
 
 // ----------------------------------------------------------- policies
 // A fragment: the lane's share of a 16 x 16 matrix A on the A side of the MFMA;
@@ -48,6 +74,7 @@ struct PolF32 {
     typedef float T;
     typedef float Tab;
     typedef floatx4 Acc;
+    typedef Arr4<float> Vec;  // one register tile: the lane's four values
     __device__ __forceinline__ static int orow(int g, int v) { return 4 * g + v; }
     struct Frag { float a[4]; };
     typedef float FragTab;
@@ -71,12 +98,31 @@ struct PolF32 {
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[kk], (float)b(4 * kk + g, c), acc, 0, 0, 0);
         return acc;
     }
+    // register-resident form: instruction kk takes k = orow(g, kk), so an
+    // output tile is directly the next product's operand.  Fragment: M[c][4g + kk].
+    __device__ __forceinline__ static Frag row_frag(const Tab* tab, const FragTab*, int m, int g, int c, int) {
+        const float4 v = *(const float4*)(tab + m * 256 + c * 16 + 4 * g);
+        Frag f;
+        f.a[0] = v.x; f.a[1] = v.y; f.a[2] = v.z; f.a[3] = v.w;
+        return f;
+    }
+    // TA false: D = M X (tile on the B side); true: D = X^T M^T (tile on the A side)
+    template <bool TA>
+    __device__ __forceinline__ static Acc mmr(const Frag& f, const Vec& x) {
+        Acc acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            acc = TA ? __builtin_amdgcn_mfma_f32_16x16x4f32(x[kk], f.a[kk], acc, 0, 0, 0)
+                     : __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[kk], x[kk], acc, 0, 0, 0);
+        return acc;
+    }
 };
 
 struct PolF64 {
     typedef double T;
     typedef double Tab;
     typedef doublex4 Acc;
+    typedef Arr4<double> Vec;  // one register tile: the lane's four values
     // the FP64 16x16x4 instruction interleaves its output rows
     __device__ __forceinline__ static int orow(int g, int v) { return g + 4 * v; }
     struct Frag { double a[4]; };
@@ -102,12 +148,26 @@ struct PolF64 {
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[kk], (double)b(4 * kk + g, c), acc, 0, 0, 0);
         return acc;
     }
+    // k = orow(g, kk) = g + 4 kk: the fragment order M[c][4kk + g] of the fragment tables
+    __device__ __forceinline__ static Frag row_frag(const Tab*, const FragTab* fr, int m, int, int, int l) {
+        return load_frag(fr, m, l);
+    }
+    template <bool TA>
+    __device__ __forceinline__ static Acc mmr(const Frag& f, const Vec& x) {
+        Acc acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            acc = TA ? __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk], f.a[kk], acc, 0, 0, 0)
+                     : __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[kk], x[kk], acc, 0, 0, 0);
+        return acc;
+    }
 };
 
 struct PolBF16 {
     typedef float T;
     typedef uint16_t Tab;
     typedef floatx4 Acc;
+    typedef floatx4 Vec;  // one register tile: the lane's four values
     __device__ __forceinline__ static int orow(int g, int v) { return 4 * g + v; }
     struct Frag { shortx4 a; };
     typedef uint16_t FragTab;
@@ -130,12 +190,25 @@ struct PolBF16 {
         Acc acc = {0.f, 0.f, 0.f, 0.f};
         return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.a, bb, acc, 0, 0, 0);
     }
+    __device__ __forceinline__ static Frag row_frag(const Tab* tab, const FragTab*, int m, int g, int c, int) {
+        Frag f;
+        f.a = *(const shortx4*)(tab + m * 256 + c * 16 + 4 * g);
+        return f;
+    }
+    template <bool TA>
+    __device__ __forceinline__ static Acc mmr(const Frag& f, const Vec& x) {
+        const shortx4 b = bf16x4s(x[0], x[1], x[2], x[3]);
+        Acc acc = {0.f, 0.f, 0.f, 0.f};
+        return TA ? __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b, f.a, acc, 0, 0, 0)
+                  : __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.a, b, acc, 0, 0, 0);
+    }
 };
 
 struct PolBF16X3 {
     typedef float T;
     typedef float Tab;  // hi + lo as float; split again exactly
     typedef floatx4 Acc;
+    typedef floatx4 Vec;  // one register tile: the lane's four values
     __device__ __forceinline__ static int orow(int g, int v) { return 4 * g + v; }
     struct Frag { shortx4 hi, lo; };
     typedef uint16_t FragTab;
@@ -148,9 +221,8 @@ struct PolBF16X3 {
         return f;
     }
     __device__ __forceinline__ static void split(float v, short* h, short* l) {
-        const uint16_t hb = f32_to_bf16(v);
-        *h = (short)hb;
-        *l = bf16s(v - bf16_to_f32(hb));
+        *h = bf16s(v);
+        *l = bf16s(v - bf16_to_f32((uint16_t)*h));
     }
     __device__ __forceinline__ static Frag load(const Tab* M, int g, int c) {
         Frag f;
@@ -175,6 +247,41 @@ struct PolBF16X3 {
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.lo, bh, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.hi, bl, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.hi, bh, acc, 0, 0, 0);
+        return acc;
+    }
+    __device__ __forceinline__ static Frag row_frag(const Tab* tab, const FragTab*, int m, int g, int c, int) {
+        const float4 v = *(const float4*)(tab + m * 256 + c * 16 + 4 * g);
+        const float e[4] = {v.x, v.y, v.z, v.w};
+        Frag f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            short h, lo;
+            split(e[i], &h, &lo);
+            f.hi[i] = h;
+            f.lo[i] = lo;
+        }
+        return f;
+    }
+    template <bool TA>
+    __device__ __forceinline__ static Acc mmr(const Frag& f, const Vec& x) {
+        shortx4 bh, bl;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            short h, lo;
+            split(x[i], &h, &lo);
+            bh[i] = h;
+            bl[i] = lo;
+        }
+        Acc acc = {0.f, 0.f, 0.f, 0.f};
+        if (TA) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bh, f.lo, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bl, f.hi, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bh, f.hi, acc, 0, 0, 0);
+        } else {
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.lo, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.hi, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.hi, bh, acc, 0, 0, 0);
+        }
         return acc;
     }
 };
@@ -385,6 +492,235 @@ __global__ void __launch_bounds__(256) k_apply16(int64_t E, int nrhs, const type
     }
 }
 
+// ------------------------------------------------- 3D, register-resident
+// One workgroup of four waves per (element, right-hand side).  The tensor
+// lives in registers: wave w holds the tiles t = 4w .. 4w+3 (slot s = t % 4)
+// of the "T" axis, and in tile t lane (g, c) holds the four values
+// whose "G" index is orow(g, v) and whose "C" index is c.  Writing a layout as
+// (G, C, T) = (axis, axis, axis):
+//   * M applied on the B side (D = M X) contracts the G axis, layout kept;
+//   * M applied on the A side (D = X^T M^T) contracts the G axis and swaps the
+//     roles: the old C axis becomes G, the contracted axis becomes C;
+//   * transpose_tg exchanges the G and T axes through LDS.
+// Route: load (a, c, b) -> L0 on A side (c, a, b) -> L2 (c) -> transpose
+// (b, a, c) -> L1 (b) -> Sylvester (T1 on b, T2 on c; each wave sweeps its
+// own four columns, the lower waves receive them through LDS) -> R0 (b) -> transpose
+// (c, a, b) -> R1 on A side (a, c, b) -> store.  Loads and stores of r and z
+// are 128-byte contiguous per 16 lanes.
+
+// transpose buffer: lane axis pitch 260, inner index rotated by the middle
+// index and the lane axis (bank-conflict free for 4-byte entries)
+constexpr int kTrA = 260;
+constexpr int kTrSize = 16 * kTrA;
+constexpr int kR3Work = kTrSize;  // entries: the transpose buffer, reused by the sweep
+__device__ __forceinline__ int tr_idx(int cl, int x, int y) { return cl * kTrA + x * 16 + ((y + x + cl) & 15); }
+
+// tile held in slot s by wave w: w + 4 s (consecutive Sylvester columns on
+// different waves, so that the step products of the sweep rotate over the
+// four SIMDs)
+__device__ __forceinline__ int tile_of(int s, int w) { return w + 4 * s; }
+
+template <class P>
+__device__ __forceinline__ void transpose_tg(typename P::Vec (&R)[4], typename P::T* M, int g, int c, int w) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) M[tr_idx(c, tile_of(s, w), P::orow(g, v))] = R[s][v];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) R[s][v] = M[tr_idx(c, P::orow(g, v), tile_of(s, w))];
+    __syncthreads();
+}
+
+template <class P, bool TA>
+__device__ __forceinline__ void contract_reg(const typename P::Frag& f, typename P::Vec (&R)[4]) {
+    typename P::Acc acc[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = P::template mmr<TA>(f, R[s]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) R[s][v] = (typename P::T)acc[s][v];
+}
+
+// T1 Y + Y T2^T = F per slice a on the layout (b, a, c): column j is the tile
+// j, held by wave j % 4 in slot j / 4.  The holder forms y_j; the other waves receive it through LDS (xb: 4 buffers of
+// 256 entries used in pairs, alternately, so that a buffer is rewritten only
+// after a barrier that follows every read of it).  T2s: T2 row-major in LDS.
+template <class P>
+__device__ __forceinline__ void sylvester_col(typename P::Vec (&R)[4], const typename P::Frag (&fN)[4],
+                                              const typename P::Frag& fT1, const int* kd,
+                                              const typename P::T* T2s, typename P::T* xb, int l, int w) {
+    typedef typename P::T T;
+    int ph = 0;
+    bool skip = false;
+#pragma clang loop unroll(full)
+    for (int j = 15; j >= 0; --j) {
+        if (skip) {
+            skip = false;
+            continue;
+        }
+        if (j >= 1 && kd[j] == 2) {
+            const int j1 = j - 1, o1 = j1 & 3, s1 = j1 >> 2, o2 = j & 3, s2 = j >> 2;
+            T* e0 = xb + ph * 512;
+            T* e1 = e0 + 256;
+            ph ^= 1;
+            if (w == o1)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) e0[v * 64 + l] = R[s1][v];
+            if (w == o2)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) e1[v * 64 + l] = R[s2][v];
+            __syncthreads();
+            const T p = T2s[j * 16 + j], q = T2s[j1 * 16 + j], sv = T2s[j * 16 + j1];
+            T* f0 = xb + ph * 512;
+            T* f1 = f0 + 256;
+            ph ^= 1;
+            if (w == o1) {
+                typename P::Vec h;
+                const typename P::Acc a1 = P::template mmr<false>(fT1, R[s1]);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) h[v] = (T)a1[v] + p * R[s1][v] - q * e1[v * 64 + l];
+                const typename P::Acc y = P::template mmr<false>(fN[s1], h);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    R[s1][v] = (T)y[v];
+                    f0[v * 64 + l] = R[s1][v];
+                }
+            }
+            if (w == o2) {
+                typename P::Vec h;
+                const typename P::Acc a2 = P::template mmr<false>(fT1, R[s2]);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) h[v] = (T)a2[v] + p * R[s2][v] - sv * e0[v * 64 + l];
+                const typename P::Acc y = P::template mmr<false>(fN[s2], h);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    R[s2][v] = (T)y[v];
+                    f1[v * 64 + l] = R[s2][v];
+                }
+            }
+            __syncthreads();
+            typename P::Vec y1, y2;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                y1[v] = w == o1 ? R[s1][v] : f0[v * 64 + l];
+                y2[v] = w == o2 ? R[s2][v] : f1[v * 64 + l];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int t = 4 * s + w;
+                if (t < j1) {
+                    const T ta = T2s[t * 16 + j1], tb = T2s[t * 16 + j];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) R[s][v] -= ta * y1[v] + tb * y2[v];
+                }
+            }
+            skip = true;
+        } else {
+            const int o = j & 3, sj = j >> 2;
+            T* e = xb + ph * 512;
+            ph ^= 1;
+            if (w == o) {
+                const typename P::Acc y = P::template mmr<false>(fN[sj], R[sj]);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    R[sj][v] = (T)y[v];
+                    e[v * 64 + l] = R[sj][v];
+                }
+            }
+            __syncthreads();
+            typename P::Vec y;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) y[v] = w == o ? R[sj][v] : e[v * 64 + l];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int t = 4 * s + w;
+                if (t < j) {
+                    const T tc = T2s[t * 16 + j];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) R[s][v] -= tc * y[v];
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <class P, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) k_apply16r3(int64_t E, int nrhs, const typename P::Tab* tabs,
+                                                   int64_t tab_stride, const typename P::FragTab* frags,
+                                                   const int8_t* kinds, const double* r, double* z) {
+    typedef typename P::T T;
+    typedef typename P::Frag Frag;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* M = (T*)smem;         // transpose buffer; the Sylvester buffers alias it
+    T* T2s = M + kR3Work;    // T2, row-major
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, g = l >> 4, c = l & 15;
+    const int64_t work = E * nrhs;
+    for (int64_t it = blockIdx.x; it < work; it += gridDim.x) {
+        const int64_t e = it / nrhs;
+        const typename P::Tab* tab = tabs + e * tab_stride;
+        const typename P::FragTab* fr = frags + e * tab_stride * P::kFragStride;
+        // every global load of the item first: r in the layout (a, c, b),
+        // the fragments of L0..L2, R0, R1, T1 and of the wave's own N_j
+        typename P::Vec R[4];
+        {
+            const double* rw = r + it * 4096;
+            double rb[4][4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) rb[s][v] = rw[P::orow(g, v) * 256 + tile_of(s, w) * 16 + c];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) R[s][v] = (T)rb[s][v];
+        }
+        const Frag fL0 = P::row_frag(tab, fr, 0, g, c, l), fL1 = P::row_frag(tab, fr, 1, g, c, l),
+                   fL2 = P::row_frag(tab, fr, 2, g, c, l), fR0 = P::row_frag(tab, fr, 3, g, c, l),
+                   fR1 = P::row_frag(tab, fr, 4, g, c, l), fT1 = P::row_frag(tab, fr, 5, g, c, l);
+        Frag fN[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) fN[s] = P::row_frag(tab, fr, 7 + tile_of(s, w), g, c, l);
+        const T t2v = (T)P::tab(tab + 6 * 256, tid);
+        int kd[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) kd[j] = kinds[e * kMaxN + j];
+        T2s[tid] = t2v;  // read after the barriers of the first transpose
+
+        contract_reg<P, true>(fL0, R);   // L0 on a: (a, c, b) -> (c, a, b)
+        contract_reg<P, false>(fL2, R);  // L2 on c
+        transpose_tg<P>(R, M, g, c, w);  // (b, a, c)
+        contract_reg<P, false>(fL1, R);  // L1 on b
+        sylvester_col<P>(R, fN, fT1, kd, T2s, M, l, w);
+        contract_reg<P, false>(fR0, R);  // R0 on b
+        transpose_tg<P>(R, M, g, c, w);  // (c, a, b)
+        contract_reg<P, true>(fR1, R);   // R1 on c: (c, a, b) -> (a, c, b)
+
+        double* zw = z + it * 4096;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) zw[P::orow(g, v) * 256 + tile_of(s, w) * 16 + c] = (double)R[s][v];
+    }
+}
+
+// WPE: waves per SIMD the register allocation is held to (FP32, BF16: 4 with
+// 128 registers; split BF16: 3; FP64: 2)
+template <class P, int WPE>
+static hipError_t launch16r3(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
+                             const void* frags, const int8_t* kinds, const double* r, double* z) {
+    const int64_t work = E * nrhs;
+    const int grid = (int)(work < kApply16Grid ? work : kApply16Grid);
+    const size_t lds = (kR3Work + 256) * sizeof(typename P::T);
+    hipLaunchKernelGGL((k_apply16r3<P, WPE>), dim3(grid), dim3(256), lds, st, E, nrhs, (const typename P::Tab*)tabs,
+                       tab_stride, (const typename P::FragTab*)frags, kinds, r, z);
+    return hipGetLastError();
+}
+
 template <class P, int DIM>
 static hipError_t launch16(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
                            const void* frags, const int8_t* kinds, const double* r, double* z) {
@@ -404,10 +740,10 @@ hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs,
                           const double* r, double* z) {
     if (dim == 3) {
         switch (prec) {
-            case 0: return launch16<PolF64, 3>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
-            case 1: return launch16<PolF32, 3>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
-            case 2: return launch16<PolBF16, 3>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
-            default: return launch16<PolBF16X3, 3>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
+            case 0: return launch16r3<PolF64, 2>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
+            case 1: return launch16r3<PolF32, 4>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
+            case 2: return launch16r3<PolBF16, 4>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
+            default: return launch16r3<PolBF16X3, 3>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
         }
     }
     switch (prec) {
