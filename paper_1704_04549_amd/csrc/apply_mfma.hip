@@ -649,56 +649,73 @@ __device__ __forceinline__ void sylvester_col(typename P::Vec (&R)[4], const typ
     __syncthreads();
 }
 
+// Everything one item reads from HBM, held in registers: r (as loaded), the
+// fragments of L0, L1, L2, R0, R1, T1 and of the wave's own N_j, the thread's
+// entry of T2 and the block kinds of T2.
+template <class P>
+struct Item3 {
+    double rb[4][4];
+    typename P::Frag fL0, fL1, fL2, fR0, fR1, fT1;
+    typename P::Frag fN[4];
+    typename P::T t2v;
+    int kd[16];
+};
+
+template <class P>
+__device__ __forceinline__ void load_item3(Item3<P>& x, int64_t it, int nrhs, const typename P::Tab* tabs,
+                                           int64_t tab_stride, const typename P::FragTab* frags,
+                                           const int8_t* kinds, const double* r, int g, int c, int l, int w,
+                                           int tid) {
+    const int64_t e = it / nrhs;
+    const typename P::Tab* tab = tabs + e * tab_stride;
+    const typename P::FragTab* fr = frags + e * tab_stride * P::kFragStride;
+    const double* rw = r + it * 4096;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x.rb[s][v] = rw[P::orow(g, v) * 256 + tile_of(s, w) * 16 + c];
+    x.fL0 = P::row_frag(tab, fr, 0, g, c, l);
+    x.fL1 = P::row_frag(tab, fr, 1, g, c, l);
+    x.fL2 = P::row_frag(tab, fr, 2, g, c, l);
+    x.fR0 = P::row_frag(tab, fr, 3, g, c, l);
+    x.fR1 = P::row_frag(tab, fr, 4, g, c, l);
+    x.fT1 = P::row_frag(tab, fr, 5, g, c, l);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) x.fN[s] = P::row_frag(tab, fr, 7 + tile_of(s, w), g, c, l);
+    x.t2v = (typename P::T)P::tab(tab + 6 * 256, tid);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x.kd[j] = kinds[e * kMaxN + j];
+}
+
 template <class P, int WPE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) k_apply16r3(int64_t E, int nrhs, const typename P::Tab* tabs,
                                                    int64_t tab_stride, const typename P::FragTab* frags,
                                                    const int8_t* kinds, const double* r, double* z) {
     typedef typename P::T T;
-    typedef typename P::Frag Frag;
     extern __shared__ __align__(16) unsigned char smem[];
     T* M = (T*)smem;         // transpose buffer; the Sylvester buffers alias it
     T* T2s = M + kR3Work;    // T2, row-major
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, g = l >> 4, c = l & 15;
     const int64_t work = E * nrhs;
     for (int64_t it = blockIdx.x; it < work; it += gridDim.x) {
-        const int64_t e = it / nrhs;
-        const typename P::Tab* tab = tabs + e * tab_stride;
-        const typename P::FragTab* fr = frags + e * tab_stride * P::kFragStride;
-        // every global load of the item first: r in the layout (a, c, b),
-        // the fragments of L0..L2, R0, R1, T1 and of the wave's own N_j
+        // every global load of the item first
+        Item3<P> x;
+        load_item3<P>(x, it, nrhs, tabs, tab_stride, frags, kinds, r, g, c, l, w, tid);
         typename P::Vec R[4];
-        {
-            const double* rw = r + it * 4096;
-            double rb[4][4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) rb[s][v] = rw[P::orow(g, v) * 256 + tile_of(s, w) * 16 + c];
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) R[s][v] = (T)rb[s][v];
-        }
-        const Frag fL0 = P::row_frag(tab, fr, 0, g, c, l), fL1 = P::row_frag(tab, fr, 1, g, c, l),
-                   fL2 = P::row_frag(tab, fr, 2, g, c, l), fR0 = P::row_frag(tab, fr, 3, g, c, l),
-                   fR1 = P::row_frag(tab, fr, 4, g, c, l), fT1 = P::row_frag(tab, fr, 5, g, c, l);
-        Frag fN[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) fN[s] = P::row_frag(tab, fr, 7 + tile_of(s, w), g, c, l);
-        const T t2v = (T)P::tab(tab + 6 * 256, tid);
-        int kd[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) kd[j] = kinds[e * kMaxN + j];
-        T2s[tid] = t2v;  // read after the barriers of the first transpose
+            for (int v = 0; v < 4; ++v) R[s][v] = (T)x.rb[s][v];
+        T2s[tid] = x.t2v;  // read after the barriers of the first transpose
 
-        contract_reg<P, true>(fL0, R);   // L0 on a: (a, c, b) -> (c, a, b)
-        contract_reg<P, false>(fL2, R);  // L2 on c
-        transpose_tg<P>(R, M, g, c, w);  // (b, a, c)
-        contract_reg<P, false>(fL1, R);  // L1 on b
-        sylvester_col<P>(R, fN, fT1, kd, T2s, M, l, w);
-        contract_reg<P, false>(fR0, R);  // R0 on b
-        transpose_tg<P>(R, M, g, c, w);  // (c, a, b)
-        contract_reg<P, true>(fR1, R);   // R1 on c: (c, a, b) -> (a, c, b)
+        contract_reg<P, true>(x.fL0, R);   // L0 on a: (a, c, b) -> (c, a, b)
+        contract_reg<P, false>(x.fL2, R);  // L2 on c
+        transpose_tg<P>(R, M, g, c, w);    // (b, a, c)
+        contract_reg<P, false>(x.fL1, R);  // L1 on b
+        sylvester_col<P>(R, x.fN, x.fT1, x.kd, T2s, M, l, w);
+        contract_reg<P, false>(x.fR0, R);  // R0 on b
+        transpose_tg<P>(R, M, g, c, w);    // (c, a, b)
+        contract_reg<P, true>(x.fR1, R);   // R1 on c: (c, a, b) -> (a, c, b)
 
         double* zw = z + it * 4096;
 #pragma unroll
@@ -709,7 +726,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8
 }
 
 // WPE: waves per SIMD the register allocation is held to (FP32, BF16: 4 with
-// 128 registers; split BF16: 3; FP64: 2)
+// 128 registers; split BF16: 3; FP64: 2).  One workgroup per item: a
+// persistent grid that prefetches the next item into registers measured
+// slower (it needs half the occupancy).
 template <class P, int WPE>
 static hipError_t launch16r3(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
                              const void* frags, const int8_t* kinds, const double* r, double* z) {
