@@ -1,22 +1,25 @@
 // Apply of the Kronecker-sum inverse for n = 16 on the matrix cores (Alg. 6 / Alg. 8).
 //
-// One workgroup of four waves per (element, slice group).  The element's data
-// is a 16 x 16 x 16 tensor X[a][b][c] held in LDS (updated in place) with
-// padded pitches (c: 1, b: 17, a: 273) so
-// that every access pattern below (contiguous in c, strided by b or by a) hits
-// distinct banks.  In 3D a, b, c are the x, y, z axes of one right-hand side;
-// in 2D a runs over up to 16 right-hand sides and b, c are the x, y axes.
+// Two kernels, one workgroup of four waves per work item:
 //
-// Every contraction out = M (x)_axis X is a 16 x 16 x 256 matrix product done
-// as 16 tiles of 16 x 16 x 16 on the MFMA units (M on the A side, the tensor
-// on the B side, the two untouched axes spanning the columns).  The
-// quasi-triangular Sylvester solve T1 Y + Y T2^T = F runs over the columns j
-// of the last axis from 15 to 0; each step is the 16 x 16 x 16 product
-// N_j [F[:, :, j]] batched over the slices a (plus T1 [.] products for the
-// 2 x 2 blocks of T2), and a rank-1 update of the remaining columns.  The four
-// waves split the 16 column tiles of every contraction; in the Sylvester sweep
-// each wave forms the (small) step product itself and updates every fourth
-// remaining column.
+// k_apply16 (2D; a work item is an element and a group of up to 16
+// right-hand sides).  The data is a 16 x 16 x 16 tensor X[a][b][c] held in
+// LDS (updated in place) with padded pitches (c: 1, b: 17, a: 273) so that
+// every access pattern below hits distinct banks; a runs over the right-hand
+// sides and b, c are the x, y axes.  Every contraction out = M (x)_axis X is a
+// 16 x 16 x 256 matrix product done as 16 tiles of 16 x 16 x 16 (M on the A
+// side, the tensor read from LDS on the B side).  The quasi-triangular
+// Sylvester solve T1 Y + Y T2^T = F runs over the columns j of the last axis
+// from 15 to 0; each step is the product N_j [F[:, :, j]] batched over the
+// slices a (plus T1 [.] products for the 2 x 2 blocks of T2) and a rank-1
+// update of the remaining columns.  The fragments come from the
+// fragment-ordered tables.
+//
+// k_apply16r3 (3D; a work item is an element and one right-hand side).  The
+// tensor lives in registers (see the description above the kernel): MFMA
+// outputs are fed straight back as operands, the axes are routed by choosing
+// the operand side, and two LDS transposes move the third axis.  Its
+// fragments are read from the row-major tables.
 //
 // Precision policies: FP32 (v_mfma_f32_16x16x4f32), FP64
 // (v_mfma_f64_16x16x4f64), BF16 (bf16 operands, v_mfma_f32_16x16x16bf16, FP32
@@ -100,7 +103,7 @@ struct PolF32 {
     }
     // register-resident form: instruction kk takes k = orow(g, kk), so an
     // output tile is directly the next product's operand.  Fragment: M[c][4g + kk].
-    __device__ __forceinline__ static Frag row_frag(const Tab* tab, const FragTab*, int m, int g, int c, int) {
+    __device__ __forceinline__ static Frag row_frag(const Tab* tab, int m, int g, int c) {
         const float4 v = *(const float4*)(tab + m * 256 + c * 16 + 4 * g);
         Frag f;
         f.a[0] = v.x; f.a[1] = v.y; f.a[2] = v.z; f.a[3] = v.w;
@@ -148,9 +151,12 @@ struct PolF64 {
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[kk], (double)b(4 * kk + g, c), acc, 0, 0, 0);
         return acc;
     }
-    // k = orow(g, kk) = g + 4 kk: the fragment order M[c][4kk + g] of the fragment tables
-    __device__ __forceinline__ static Frag row_frag(const Tab*, const FragTab* fr, int m, int, int, int l) {
-        return load_frag(fr, m, l);
+    // k = orow(g, kk) = g + 4 kk: M[c][g + 4 kk], four strided entries of row c
+    __device__ __forceinline__ static Frag row_frag(const Tab* tab, int m, int g, int c) {
+        Frag f;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) f.a[kk] = tab[m * 256 + c * 16 + g + 4 * kk];
+        return f;
     }
     template <bool TA>
     __device__ __forceinline__ static Acc mmr(const Frag& f, const Vec& x) {
@@ -190,7 +196,7 @@ struct PolBF16 {
         Acc acc = {0.f, 0.f, 0.f, 0.f};
         return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.a, bb, acc, 0, 0, 0);
     }
-    __device__ __forceinline__ static Frag row_frag(const Tab* tab, const FragTab*, int m, int g, int c, int) {
+    __device__ __forceinline__ static Frag row_frag(const Tab* tab, int m, int g, int c) {
         Frag f;
         f.a = *(const shortx4*)(tab + m * 256 + c * 16 + 4 * g);
         return f;
@@ -249,7 +255,7 @@ struct PolBF16X3 {
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.hi, bh, acc, 0, 0, 0);
         return acc;
     }
-    __device__ __forceinline__ static Frag row_frag(const Tab* tab, const FragTab*, int m, int g, int c, int) {
+    __device__ __forceinline__ static Frag row_frag(const Tab* tab, int m, int g, int c) {
         const float4 v = *(const float4*)(tab + m * 256 + c * 16 + 4 * g);
         const float e[4] = {v.x, v.y, v.z, v.w};
         Frag f;
@@ -663,34 +669,32 @@ struct Item3 {
 
 template <class P>
 __device__ __forceinline__ void load_item3(Item3<P>& x, int64_t it, int nrhs, const typename P::Tab* tabs,
-                                           int64_t tab_stride, const typename P::FragTab* frags,
-                                           const int8_t* kinds, const double* r, int g, int c, int l, int w,
-                                           int tid) {
+                                           int64_t tab_stride, const int8_t* kinds, const double* r, int g,
+                                           int c, int w, int tid) {
     const int64_t e = it / nrhs;
     const typename P::Tab* tab = tabs + e * tab_stride;
-    const typename P::FragTab* fr = frags + e * tab_stride * P::kFragStride;
     const double* rw = r + it * 4096;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int v = 0; v < 4; ++v) x.rb[s][v] = rw[P::orow(g, v) * 256 + tile_of(s, w) * 16 + c];
-    x.fL0 = P::row_frag(tab, fr, 0, g, c, l);
-    x.fL1 = P::row_frag(tab, fr, 1, g, c, l);
-    x.fL2 = P::row_frag(tab, fr, 2, g, c, l);
-    x.fR0 = P::row_frag(tab, fr, 3, g, c, l);
-    x.fR1 = P::row_frag(tab, fr, 4, g, c, l);
-    x.fT1 = P::row_frag(tab, fr, 5, g, c, l);
+    x.fL0 = P::row_frag(tab, 0, g, c);
+    x.fL1 = P::row_frag(tab, 1, g, c);
+    x.fL2 = P::row_frag(tab, 2, g, c);
+    x.fR0 = P::row_frag(tab, 3, g, c);
+    x.fR1 = P::row_frag(tab, 4, g, c);
+    x.fT1 = P::row_frag(tab, 5, g, c);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) x.fN[s] = P::row_frag(tab, fr, 7 + tile_of(s, w), g, c, l);
+    for (int s = 0; s < 4; ++s) x.fN[s] = P::row_frag(tab, 7 + tile_of(s, w), g, c);
     x.t2v = (typename P::T)P::tab(tab + 6 * 256, tid);
 #pragma unroll
     for (int j = 0; j < 16; ++j) x.kd[j] = kinds[e * kMaxN + j];
 }
 
 template <class P, int WPE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) k_apply16r3(int64_t E, int nrhs, const typename P::Tab* tabs,
-                                                   int64_t tab_stride, const typename P::FragTab* frags,
-                                                   const int8_t* kinds, const double* r, double* z) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) k_apply16r3(
+    int64_t E, int nrhs, const typename P::Tab* tabs, int64_t tab_stride, const int8_t* kinds, const double* r,
+    double* z) {
     typedef typename P::T T;
     extern __shared__ __align__(16) unsigned char smem[];
     T* M = (T*)smem;         // transpose buffer; the Sylvester buffers alias it
@@ -700,7 +704,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8
     for (int64_t it = blockIdx.x; it < work; it += gridDim.x) {
         // every global load of the item first
         Item3<P> x;
-        load_item3<P>(x, it, nrhs, tabs, tab_stride, frags, kinds, r, g, c, l, w, tid);
+        load_item3<P>(x, it, nrhs, tabs, tab_stride, kinds, r, g, c, w, tid);
         typename P::Vec R[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
@@ -731,12 +735,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8
 // slower (it needs half the occupancy).
 template <class P, int WPE>
 static hipError_t launch16r3(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
-                             const void* frags, const int8_t* kinds, const double* r, double* z) {
+                             const int8_t* kinds, const double* r, double* z) {
     const int64_t work = E * nrhs;
     const int grid = (int)(work < kApply16Grid ? work : kApply16Grid);
     const size_t lds = (kR3Work + 256) * sizeof(typename P::T);
     hipLaunchKernelGGL((k_apply16r3<P, WPE>), dim3(grid), dim3(256), lds, st, E, nrhs, (const typename P::Tab*)tabs,
-                       tab_stride, (const typename P::FragTab*)frags, kinds, r, z);
+                       tab_stride, kinds, r, z);
     return hipGetLastError();
 }
 
@@ -759,10 +763,10 @@ hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs,
                           const double* r, double* z) {
     if (dim == 3) {
         switch (prec) {
-            case 0: return launch16r3<PolF64, 2>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
-            case 1: return launch16r3<PolF32, 4>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
-            case 2: return launch16r3<PolBF16, 4>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
-            default: return launch16r3<PolBF16X3, 3>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
+            case 0: return launch16r3<PolF64, 2>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 1: return launch16r3<PolF32, 4>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 2: return launch16r3<PolBF16, 4>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            default: return launch16r3<PolBF16X3, 3>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
         }
     }
     switch (prec) {

@@ -110,7 +110,7 @@ static kp_status finish_tables(kp_ctx c, const kp_batch* b, int rank, char* pc, 
     KP_HIP(launch_cast_tables(c->stream, E * L.ne, (const double*)(pc + L.t64), (float*)(pc + L.t32),
                               (uint16_t*)(pc + L.thi), (uint16_t*)(pc + L.tlo),
                               (float*)(pc + L.t2)));
-    if (b->n == 16)
+    if (b->n == 16 && b->dim == 2)
         KP_HIP(launch_frag_tables(c->stream, E, (const double*)(pc + L.t64), (double*)(pc + L.f64f),
                                   (float*)(pc + L.f32f), (uint16_t*)(pc + L.fbf),
                                   (uint16_t*)(pc + L.fbf3)));
