@@ -145,13 +145,101 @@ __global__ void __launch_bounds__(64) k_tables_prepare(int64_t E, int dim, int n
     }
 }
 
+// Gauss-Jordan inverses of four n x n matrices (n <= 16) in one wave: the
+// 16-lane group q = lane / 16 inverts its own matrix, lane i of the group
+// holding row i of [A | I] in registers.  Partial pivoting by the largest
+// |entry| of the column among the rows not yet used as pivots (ties: the
+// lowest row); the pivot row is scaled by the reciprocal of the pivot and
+// broadcast through the group's LDS slot (32 doubles), and every other row
+// subtracts its multiple, the same arithmetic per entry as invert().  The row
+// that was the pivot of step k ends as row k of the inverse.  Aq / Aiq: the
+// lane's group's input and output (row-major, may be the same buffer; Aq null:
+// the group idles).  Returns false on the lanes of a group whose matrix has a
+// zero pivot column.
+__device__ bool invert4(int n, const double* Aq, double* Aiq, double* slot) {
+    const int lane = (int)(threadIdx.x & 63), q = lane >> 4, i = lane & 15;
+    const bool grp = Aq != nullptr;
+    const bool act = grp && i < n;
+    double a[16], b[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        a[j] = (act && j < n) ? Aq[i * n + j] : 0.0;
+        b[j] = (act && i == j) ? 1.0 : 0.0;
+    }
+    double* sl = slot + q * 32;
+    bool used = false, ok = true;
+    int stepk = -1;
+    WaveTeam wt;
+    wt.sync();  // every read of Aq precedes any write of Aiq
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k >= n) break;
+        double v = (act && !used) ? fabs(a[k]) : -1.0;
+        int p = i;
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(v, off, 16);
+            const int op = __shfl_xor(p, off, 16);
+            if (ov > v || (ov == v && op < p)) {
+                v = ov;
+                p = op;
+            }
+        }
+        const bool sing = !(v > 0.0);
+        if (sing) ok = false;
+        const bool piv = act && !sing && i == p;
+        if (piv) {
+            const double inv = 1.0 / a[k];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                a[j] *= inv;
+                b[j] *= inv;
+                sl[j] = a[j];
+                sl[16 + j] = b[j];
+            }
+            used = true;
+            stepk = k;
+        }
+        wt.sync();
+        if (act && !sing && !piv) {
+            const double m = a[k];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                a[j] -= m * sl[j];
+                b[j] -= m * sl[16 + j];
+            }
+        }
+        wt.sync();
+    }
+    if (act && stepk >= 0)
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (j < n) Aiq[stepk * n + j] = b[j];
+    wt.sync();
+    return ok || !grp;
+}
+
+// ||M||_1 (largest column sum of |entries|) of the lane's group's n x n
+// matrix (n <= 16), on every lane of the group
+__device__ double norm1_group(int n, const double* M) {
+    const int i = (int)(threadIdx.x & 15);
+    double c = 0.0;
+    if (M != nullptr && i < n)
+        for (int r = 0; r < n; ++r) c += fabs(M[r * n + i]);
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) c = fmax(c, __shfl_xor(c, off, 16));
+    return c;
+}
+
 // Four-wave variants of prepare and finish (256 threads per element): the
 // independent pieces of the work run on separate waves, each with its own
-// LDS scratch, and give the same results as the one-wave kernels (every
-// matrix is formed by the same arithmetic; the angle search compares the
-// same scores with the same tie rule).
-//   prepare: wave w scores the rotation angles k = w and w + 4; waves 0..2
-//            form the inverses; waves 0, 1 form C1, C2.
+// LDS scratch, with the arithmetic of the one-wave kernels (the angle search
+// compares the same scores with the same tie rule).  For n <= 16 the
+// inversions run four at a time per wave (invert4: the same operations per
+// entry; its pivot order can differ from invert()'s only on exact ties).
+//   prepare: wave w scores the rotation angles k = w and w + 4; the inverses
+//            are formed by wave 0 (n <= 16) or waves 0..2; waves 0, 1 form
+//            C1, C2.
 //   finish:  waves 0, 1 form the two L = Q^T inverse tables; wave w forms
 //            the N_j with j = w mod 4 (a 2 x 2 block of T2 stays on one wave).
 __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int n, int rank,
@@ -163,18 +251,22 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
     __shared__ int ipiv[4][kMaxN];
     __shared__ double scores[8];
     __shared__ int fail[4];
+    __shared__ double gslot[4][4 * 32];
     BlockTeam bt{red};
     WaveTeam wt;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long nn = (long)n * n;
     const int nf = dim == 2 ? 2 * rank : 5;
     const long ne = tab_entries(n);
+    // n <= 16: four matrices per wave are inverted at once (invert4), else one
+    const bool grp4 = n <= 16;
+    const int wsz = grp4 ? 4 : 3;          // scratch matrices per wave
     double* F = lds;                       // nf n^2
     double* R6 = F + nf * nn;              // left 1
     double* R7 = R6 + nn;                  // left 2 (inverted)
     double* R8 = R7 + nn;                  // right 1 (inverted)
     double* R9 = R8 + nn;                  // right 2
-    double* Wv = R9 + nn + wv * 3 * nn;    // this wave's scratch: 3 n^2
+    double* Wv = R9 + nn + wv * wsz * nn;  // this wave's scratch
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         for (long t = threadIdx.x; t < nf * nn; t += blockDim.x) F[t] = factors[e * nf * nn + t];
         if (threadIdx.x < 4) fail[threadIdx.x] = 0;
@@ -210,7 +302,36 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
         __syncthreads();
         // angle search: kappa_1 of the two factors to invert for k = wv, wv + 4
         const double pi = 3.14159265358979323846;
-        for (int k = wv; k < 8; k += 4) {
+        if (grp4) {
+            // group 2h + m: angle wv + 4h, matrix m (0: rotated left 2, 1: rotated right 1)
+            for (int h = 0; h < 2; ++h) {
+                const int k = wv + 4 * h;
+                const double c = cos(pi * k / 8.0), sn = sin(pi * k / 8.0);
+                double* M0 = Wv + (2 * h) * nn;
+                double* M1 = M0 + nn;
+                for (long t = lane; t < nn; t += 64) {
+                    M0[t] = -sn * R6[t] + c * R7[t];
+                    M1[t] = c * R9[t] + sn * R8[t];
+                }
+            }
+            wt.sync();
+            double* Mq = Wv + (lane >> 4) * nn;
+            const double nm = norm1_group(n, Mq);
+            const bool ok = invert4(n, Mq, Mq, gslot[wv]);
+            const double ni = norm1_group(n, Mq);
+            const double term = ok ? nm * ni : 1e300;
+            const double t0 = __shfl(term, 0, 64), t1 = __shfl(term, 16, 64);
+            const double t2 = __shfl(term, 32, 64), t3 = __shfl(term, 48, 64);
+            double sc0 = 1.0 * t0 * t1, sc1 = 1.0 * t2 * t3;
+            if (!(sc0 == sc0)) sc0 = 1e300;
+            if (!(sc1 == sc1)) sc1 = 1e300;
+            if (lane == 0) {
+                scores[wv] = sc0;
+                scores[wv + 4] = sc1;
+            }
+            wt.sync();
+        }
+        for (int k = wv; k < 8 && !grp4; k += 4) {
             const double c = cos(pi * k / 8.0), sn = sin(pi * k / 8.0);
             double* W0 = Wv;
             double* W1 = Wv + nn;
@@ -251,7 +372,20 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
         // 3D L0 = inv(A1), L1 = inv(B2'), L2 = inv(C1')
         const double* srcs[3] = {dim == 2 ? R7 : F, dim == 2 ? R8 : R7, R8};
         const int nq = dim == 3 ? 3 : 2;
-        if (wv < nq) {
+        if (grp4 && wv == 0) {
+            // wave 0 inverts all of them, group q the q-th, in its scratch
+            for (int q = 0; q < nq; ++q)
+                for (long t = lane; t < nn; t += 64) Wv[q * nn + t] = srcs[q][t];
+            wt.sync();
+            const int q = lane >> 4;
+            double* Mq = q < nq ? Wv + q * nn : nullptr;
+            const bool ok = invert4(n, Mq, Mq, gslot[0]);
+            if (!ok && (lane & 15) == 0) fail[q] = 1;
+            for (int qq = 0; qq < nq; ++qq)
+                for (long t = lane; t < nn; t += 64) tab[qq * nn + t] = Wv[qq * nn + t];
+            wt.sync();
+        }
+        if (!grp4 && wv < nq) {
             double* W0 = Wv;
             double* W2 = Wv + 2 * nn;
             for (long t = lane; t < nn; t += 64) W0[t] = srcs[wv][t];
@@ -266,10 +400,11 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
         __syncthreads();
         // C1 = inv(Y) G_y, C2 = inv(Z) G_z (2D: Y = A2', Z = B1'; 3D: Y = B2', Z = C1')
         if (wv < 2) {
-            const int src_wave = dim == 2 ? wv : wv + 1;  // the wave that holds inv(Y) / inv(Z)
-            const double* inv = lds + nf * nn + 4 * nn + src_wave * 3 * nn;
+            const int src_wave = dim == 2 ? wv : wv + 1;  // the wave (grp4: wave 0's group) holding inv(Y) / inv(Z)
+            const double* inv = grp4 ? lds + nf * nn + 4 * nn + src_wave * nn
+                                     : lds + nf * nn + 4 * nn + src_wave * 3 * nn;
             const double* G = wv == 0 ? R6 : R9;
-            double* out = Wv + nn;
+            double* out = grp4 ? Wv + 3 * nn : Wv + nn;  // clear of every inverse
             mm(wt, n, inv, G, out);
             for (long t = lane; t < nn; t += 64) N[wv * nn + t] = out[t];
             wt.sync();
@@ -287,13 +422,15 @@ __global__ void __launch_bounds__(256) k_tables_finish4(int64_t E, int dim, int 
     __shared__ double sh[4][kMaxN + 8];
     __shared__ int ipiv[4][kMaxN];
     __shared__ int fail[4];
+    __shared__ double gslot[4][4 * 32];
     BlockTeam bt{red};
     WaveTeam wt;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long nn = (long)n * n;
     const long ne = tab_entries(n);
+    const bool grp4 = n <= 16;  // the wave's four N_j inverted at once (invert4)
     double* T1 = lds;
-    double* Wv = lds + nn + wv * 4 * nn;  // W0, W1, W4, W5
+    double* Wv = lds + nn + wv * (grp4 ? 5 : 4) * nn;  // grp4: 4 inputs, M; else W0, W1, W4, W5
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         double* tab = tab64 + e * ne;
         double* N = tab + 7 * nn;
@@ -326,7 +463,41 @@ __global__ void __launch_bounds__(256) k_tables_finish4(int64_t E, int dim, int 
             wt.sync();
         }
         // N_j, j = wv mod 4
-        for (int j = wv; j < n; j += 4) {
+        if (grp4) {
+            // group q: j = wv + 4 q; the input is T1 + t_j I, or M^2 - q s I
+            // for a 2 x 2 block (M = T1 + p I), inverted in place
+            double* In = Wv;
+            double* Mt = Wv + 4 * nn;
+            for (int q = 0; q < 4; ++q) {
+                const int j = wv + 4 * q;
+                if (j >= n || kd[j] == 1) continue;
+                double* X = In + q * nn;
+                if (kd[j] == 0) {
+                    const double tj = T2[j * n + j];
+                    for (long t = lane; t < nn; t += 64) X[t] = T1[t] + ((t / n == t % n) ? tj : 0.0);
+                } else {
+                    const double p = T2[j * n + j], qv = T2[(j - 1) * n + j], sv = T2[j * n + j - 1];
+                    for (long t = lane; t < nn; t += 64) Mt[t] = T1[t] + ((t / n == t % n) ? p : 0.0);
+                    wt.sync();
+                    mm(wt, n, Mt, Mt, X);
+                    for (long t = lane; t < nn; t += 64) X[t] = X[t] - ((t / n == t % n) ? qv * sv : 0.0);
+                }
+                wt.sync();
+            }
+            const int q = lane >> 4, jq = wv + 4 * q;
+            double* Xq = (jq < n && kd[jq] != 1) ? In + q * nn : nullptr;
+            if (!invert4(n, Xq, Xq, gslot[wv]) && (lane & 15) == 0) fail[wv] = 1;
+            for (int qq = 0; qq < 4; ++qq) {
+                const int j = wv + 4 * qq;
+                if (j >= n || kd[j] == 1) continue;
+                for (long t = lane; t < nn; t += 64) {
+                    N[(long)j * nn + t] = In[qq * nn + t];
+                    if (kd[j] == 2) N[(long)(j - 1) * nn + t] = In[qq * nn + t];
+                }
+            }
+            wt.sync();
+        }
+        for (int j = wv; j < n && !grp4; j += 4) {
             const int k = kd[j];
             if (k == 1) continue;  // formed with its partner j + 1
             if (k == 0) {
@@ -491,8 +662,8 @@ hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank
     const size_t lds = (nf + 10) * nn * sizeof(double);
     const int grid = (int)(E < 65536 ? E : 65536);
     // four-wave kernels where their scratch fits in LDS, else one wave per element
-    const size_t lds4p = (nf + 4 + 12) * nn * sizeof(double);
-    const size_t lds4f = 17 * nn * sizeof(double);
+    const size_t lds4p = (nf + 4 + (n <= 16 ? 16 : 12)) * nn * sizeof(double);
+    const size_t lds4f = (n <= 16 ? 21 : 17) * nn * sizeof(double);
     if (lds4p <= kTables4LdsMax)
         hipLaunchKernelGGL(k_tables_prepare4, dim3(grid), dim3(256), lds4p, s, E, dim, n, rank, factors,
                            tab64, status);
