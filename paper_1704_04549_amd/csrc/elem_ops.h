@@ -221,14 +221,28 @@ struct OpStruct3 {
         }
         t1 = tm.sum(t1);
         t2 = tm.sum(t2) + c * nrm2;
+        // s_a = sum_q m[a][q] d[q], spread over the team: C interleaved chunks
+        // of q per a (partials in y), then the chunk sums in order into d[a]
+        int C = tm.size() / n;
+        if (C > n) C = n;
+        if (C < 1) C = 1;
+        for (int t = tm.tid(); t < n * C; t += tm.size()) {
+            const int a = t / C, ch = t % C;
+            double s = 0.0;
+            for (int q = ch; q < nn; q += C) s += m[a * nn + q] * d[q];
+            y[t] = s;
+        }
+        tm.sync();
+        for (int a = tm.tid(); a < n; a += tm.size()) {
+            double s = 0.0;
+            for (int ch = 0; ch < C; ++ch) s += y[a * C + ch];
+            d[a] = s;
+        }
+        tm.sync();
         for (int t = tm.tid(); t < nn; t += tm.size()) {
             const int a = t / n, a2 = t % n;
             double v = X[t] * t1;
-            if (a == a2) {
-                double s = 0.0;
-                for (int q = 0; q < nn; ++q) s += m[a * nn + q] * d[q];
-                v += s + w[a] * t2;
-            }
+            if (a == a2) v += d[a] + w[a] * t2;
             y[t] = v;
         }
         tm.sync();
@@ -564,7 +578,15 @@ KP_HD int lanczos_top(const Team& tm, const Op& op, int m, int r, int kmax, doub
             tm.dots(Q, m, k + 1, L.w, m, L.h);
             for (int i = tm.tid(); i < m; i += tm.size()) {
                 double s = L.w[i];
-                for (int j = 0; j <= k; ++j) s -= L.h[j] * Q[(long)j * m + i];
+                int j = 0;
+                for (; j + 8 <= k + 1; j += 8) {  // eight basis loads in flight, the same order
+                    double qv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) qv[u] = Q[(long)(j + u) * m + i];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) s -= L.h[j + u] * qv[u];
+                }
+                for (; j <= k; ++j) s -= L.h[j] * Q[(long)j * m + i];
                 L.w[i] = s;
             }
             aco += L.h[k];

@@ -134,16 +134,29 @@ struct BlockTeam {
         return bi;
     }
     // out[j] = sum_i Q[j*ldq + i] * v[i] for j < k; one wave per dot product,
-    // fixed summation order; out is visible to the whole team on return
+    // fixed summation order; out is visible to the whole team on return.  A
+    // wave forms 8 of its dot products at a time (their loads in flight
+    // together, their reductions interleaved).
     __device__ void dots(const double* Q, long ldq, int k, const double* v, int len,
                          double* out) const {
         const int nw = (int)(blockDim.x >> 6);
         const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-        for (int j = w; j < k; j += nw) {
-            double s = 0.0;
-            for (int i = lane; i < len; i += 64) s += Q[j * ldq + i] * v[i];
-            s = wave_sum(s);
-            if (lane == 0) out[j] = s;
+        for (int j0 = w; j0 < k; j0 += 8 * nw) {
+            double s[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s[u] = 0.0;
+            for (int i = lane; i < len; i += 64) {
+                const double vi = v[i];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (j0 + u * nw < k) s[u] += Q[(j0 + u * nw) * ldq + i] * vi;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s[u] = wave_sum(s[u]);
+            if (lane == 0)
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (j0 + u * nw < k) out[j0 + u * nw] = s[u];
         }
         __syncthreads();
     }
@@ -184,14 +197,27 @@ struct WaveTeam {
         return v;
     }
     // out[j] = sum_i Q[j*ldq + i] * v[i] for j < k (lanes over i, then the
-    // wave reduction); out is visible to the wave on return
+    // wave reduction); out is visible to the wave on return.  Eight dot
+    // products at a time: their loads in flight together, their reductions
+    // interleaved (the summation order of each is unchanged).
     __device__ void dots(const double* Q, long ldq, int k, const double* v, int len, double* out) const {
         const int lane = (int)(threadIdx.x & 63);
-        for (int j = 0; j < k; ++j) {
-            double s = 0.0;
-            for (int i = lane; i < len; i += 64) s += Q[j * ldq + i] * v[i];
-            s = wave_sum(s);
-            if (lane == 0) out[j] = s;
+        for (int j0 = 0; j0 < k; j0 += 8) {
+            double s[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s[u] = 0.0;
+            for (int i = lane; i < len; i += 64) {
+                const double vi = v[i];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (j0 + u < k) s[u] += Q[(j0 + u) * ldq + i] * vi;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s[u] = wave_sum(s[u]);
+            if (lane == 0)
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (j0 + u < k) out[j0 + u] = s[u];
         }
         sync();
     }
