@@ -186,6 +186,80 @@ struct OpStruct3 {
     const double *m, *X, *Y, *Z, *w;
     double* d;      // [n^2] scratch
     double nrm2;    // ||Y (x) W + W (x) Z||_F^2
+    // Gram form (set by precompute): with M = m as an n x n^2 matrix,
+    // ww_q = w_b w_c and dg_q = Y_bb w_c + w_b Z_cc (q = b n + c),
+    // G = M M^T, mv = [M ww, M dg, dg.ww, ww.ww]; then G R(A)^T x costs O(n^2)
+    const double* G = nullptr;
+    const double* mv = nullptr;
+
+    // forms G (into gbuf, n^2) and mv (into vbuf, 2n + 2) on the teams that
+    // can; returns whether the Gram form is in use
+    template <class Team>
+    KP_HD bool precompute(const Team& tm, double* gbuf, double* vbuf) {
+        const int nn = n * n;
+        const double* w_ = w;
+        const double* Y_ = Y;
+        const double* Z_ = Z;
+        const int n_ = n;
+        auto bf = [=](int q, int j) -> double {
+            const int b = q / n_, cc = q % n_;
+            return j == 0 ? w_[b] * w_[cc] : Y_[b * n_ + b] * w_[cc] + w_[b] * Z_[cc * n_ + cc];
+        };
+        if (!tm.gram16(m, n, nn, bf, gbuf, vbuf)) return false;
+        double dgww = 0.0, ww2 = 0.0;
+        for (int q = tm.tid(); q < nn; q += tm.size()) {
+            const double wq = bf(q, 0), dq = bf(q, 1);
+            dgww += dq * wq;
+            ww2 += wq * wq;
+        }
+        dgww = tm.sum(dgww);
+        ww2 = tm.sum(ww2);
+        if (tm.leader()) {
+            vbuf[2 * n] = dgww;
+            vbuf[2 * n + 1] = ww2;
+        }
+        tm.sync();
+        G = gbuf;
+        mv = vbuf;
+        return true;
+    }
+
+    // G R(A)^T x in the Gram form: with x_d = diag(x), p1 = <X, x>, c = w.x_d,
+    //   t1 = (M ww).x_d + p1 ww.ww + c dg.ww,  t2 = (M dg).x_d + p1 dg.ww + c nrm2,
+    //   y = t1 X + diag(G x_d + p1 M ww + c M dg + t2 w)
+    template <class Team>
+    KP_HD void apply_gram(const Team& tm, const double* x, double* y) const {
+        const int nn = n * n;
+        double p1 = 0.0, c = 0.0, u1 = 0.0, u2 = 0.0;
+        for (int t = tm.tid(); t < nn; t += tm.size()) {
+            p1 += X[t] * x[t];
+            const int a = t / n;
+            if (a == t % n) {
+                const double xa = x[t];
+                c += w[a] * xa;
+                u1 += mv[a] * xa;
+                u2 += mv[n + a] * xa;
+            }
+        }
+        p1 = tm.sum(p1);
+        c = tm.sum(c);
+        u1 = tm.sum(u1);
+        u2 = tm.sum(u2);
+        const double dgww = mv[2 * n], ww2 = mv[2 * n + 1];
+        const double t1 = u1 + p1 * ww2 + c * dgww;
+        const double t2 = u2 + p1 * dgww + c * nrm2;
+        for (int t = tm.tid(); t < nn; t += tm.size()) {
+            const int a = t / n, a2 = t % n;
+            double v = X[t] * t1;
+            if (a == a2) {
+                double s = 0.0;
+                for (int b = 0; b < n; ++b) s += G[a * n + b] * x[b * n + b];
+                v += s + p1 * mv[a] + c * mv[n + a] + w[a] * t2;
+            }
+            y[t] = v;
+        }
+        tm.sync();
+    }
 
     template <class Team>
     KP_HD void transpose(const Team& tm, const double* x, double* g, double* c_out) const {
@@ -208,6 +282,10 @@ struct OpStruct3 {
 
     template <class Team>
     KP_HD void apply(const Team& tm, const double* x, double* y) const {
+        if (G) {
+            apply_gram(tm, x, y);
+            return;
+        }
         const int nn = n * n;
         double c;
         transpose(tm, x, d, &c);
@@ -538,6 +616,7 @@ KP_HD bool tridiag_eig_team(const Team& tm, int k, double* d, double* e, double*
 struct LanczosWork {
     double* Q;      // (kmax+1) x m basis; Q[0..m) holds the start vector on entry
     double* w;      // m
+    double* qv;     // m: a copy of the newest basis vector in fast memory, or null
     double* h;      // kmax + 2
     double* alpha;  // kmax + 1
     double* beta;   // kmax + 1
@@ -565,13 +644,16 @@ KP_HD int lanczos_top(const Team& tm, const Op& op, int m, int r, int kmax, doub
         for (int i = tm.tid(); i < m; i += tm.size()) Q[i] = 1.0;
         nrm = sqrt((double)m);
     }
-    for (int i = tm.tid(); i < m; i += tm.size()) Q[i] /= nrm;
+    for (int i = tm.tid(); i < m; i += tm.size()) {
+        Q[i] /= nrm;
+        if (L.qv) L.qv[i] = Q[i];
+    }
     tm.sync();
     double scale = 0.0;
     int steps = 0;
     bool converged = false;
     for (int k = 0; k < kmax; ++k) {
-        const double* qk = Q + (long)k * m;
+        const double* qk = L.qv ? L.qv : Q + (long)k * m;
         op.apply(tm, qk, L.w);
         double aco = 0.0;
         for (int pass = 0; pass < 2; ++pass) {
@@ -654,7 +736,11 @@ KP_HD int lanczos_top(const Team& tm, const Op& op, int m, int r, int kmax, doub
         }
         if (b == 0.0 || steps == m) break;
         double* qn = Q + (long)(k + 1) * m;
-        for (int i = tm.tid(); i < m; i += tm.size()) qn[i] = L.w[i] / b;
+        for (int i = tm.tid(); i < m; i += tm.size()) {
+            const double v = L.w[i] / b;
+            qn[i] = v;
+            if (L.qv) L.qv[i] = v;
+        }
         tm.sync();
     }
     // Ritz vectors u_j = Q sel_j
@@ -1485,6 +1571,7 @@ KP_INLINE SetupWork carve_setup_work(double* base, int dim, int n, bool expl, in
     W.small = p; p += 64;
     W.L.Q = p; p += (kmax + 1) * m;
     W.L.w = p; p += m;
+    W.L.qv = nullptr;
     W.L.h = p; p += kmax + 2;
     W.L.alpha = p; p += kmax + 1;
     W.L.beta = p; p += kmax + 1;
@@ -1510,10 +1597,14 @@ KP_INLINE SetupWork carve_setup_work(double* base, int dim, int n, bool expl, in
 KP_INLINE long setup_small_doubles(int n, bool expl) {
     const long kmax = lanczos_kmax(n, expl);
     return (kmax + 2) + 2 * (kmax + 1) + 2 * kmax + kmax * kmax + 3 * kmax + 3 + 8 + 2 * kmax + 4 +
-           (long)n * n + 64;
+           3 * (long)n * n + 64;
 }
+// the small, often-touched parts of the setup work (in LDS on the GPU): the
+// Lanczos scalars and tridiagonal, its work vector and newest basis vector
 KP_INLINE void carve_small(double* p, int n, bool expl, SetupWork* W) {
     const long kmax = lanczos_kmax(n, expl);
+    W->L.w = p; p += (long)n * n;
+    W->L.qv = p; p += (long)n * n;
     W->L.h = p; p += kmax + 2;
     W->L.alpha = p; p += kmax + 1;
     W->L.beta = p; p += kmax + 1;
@@ -1888,6 +1979,7 @@ KP_HD int setup_element(const Team& tm, int dim, int n, int rank, const Tables1D
     } else {
         OpStruct3 op{n, W.mass, W.Xax, W.Xax + nn, W.Xax + 2 * nn, T.w, W.d,
                      struct3_nrm2(n, W.Xax + nn, W.Xax + 2 * nn, T.w)};
+        op.precompute(tm, W.d, W.small);  // the mass tensor is then read once
         lanczos_start(tm, W.L.Q, nn, guess);
         const int conv = lanczos_top(tm, op, nn, 1, kmax, 1e-14, W.L, W.U);
         status |= conv ? 0 : 1;

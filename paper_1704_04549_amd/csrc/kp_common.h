@@ -31,6 +31,9 @@ struct HostTeam {
     int tid() const { return 0; }
     int size() const { return 1; }
     void sync() const {}
+    // matrix-core Gram products: not on this team (see WaveTeam::gram16)
+    template <class BF>
+    bool gram16(const double*, int, int, BF, double*, double*) const { return false; }
     double sum(double v) const { return v; }
     double max(double v) const { return v; }
     // reduce k partial sums in place (v[0..k)); identity on one thread
@@ -75,6 +78,8 @@ struct BlockTeam {
     __device__ int tid() const { return (int)threadIdx.x; }
     __device__ int size() const { return (int)blockDim.x; }
     __device__ void sync() const { __syncthreads(); }
+    template <class BF>
+    __device__ bool gram16(const double*, int, int, BF, double*, double*) const { return false; }
     __device__ bool leader() const { return threadIdx.x == 0; }
     __device__ int groups() const { return (int)(blockDim.x >> 6); }
     __device__ int group() const { return (int)(threadIdx.x >> 6); }
@@ -189,6 +194,34 @@ struct WaveTeam {
     __device__ void sync() const {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
+    }
+    // G = M M^T (rows x rows, row-major) and mv[j * rows + i] = (M V)[i][j]
+    // for j = 0, 1, where M is rows x len row-major (rows <= 16, len a
+    // multiple of 4) and V[q][j] = bf(q, j), on the FP64 matrix cores: per
+    // 16x16x4 product the lane (g, c) loads M[c][q0 + g] once and feeds it as
+    // both operands of M M^T.  G and mv are visible to the wave on return.
+    // Returns false (nothing written) when the shape does not fit.
+    template <class BF>
+    __device__ bool gram16(const double* M, int rows, int len, BF bf, double* G, double* mv) const {
+        if (rows > 16 || (len & 3)) return false;
+        typedef double dx4 __attribute__((ext_vector_type(4)));
+        const int lane = (int)(threadIdx.x & 63), g = lane >> 4, c = lane & 15;
+        dx4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+        for (int q0 = 0; q0 < len; q0 += 4) {
+            const double a = c < rows ? M[(long)c * len + q0 + g] : 0.0;
+            const double b = c < 2 ? bf(q0 + g, c) : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, acc, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc2, 0, 0, 0);
+        }
+        // the lane holds D[g + 4 v][c]
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = g + 4 * v;
+            if (r < rows && c < rows) G[r * rows + c] = acc[v];
+            if (r < rows && c < 2) mv[c * rows + r] = acc2[v];
+        }
+        sync();
+        return true;
     }
     __device__ bool leader() const { return (threadIdx.x & 63) == 0; }
     __device__ double sum(double v) const { return wave_sum(v); }
