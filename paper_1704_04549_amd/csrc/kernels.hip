@@ -559,6 +559,31 @@ __global__ void __launch_bounds__(64) k_tables_schur(int64_t E, int n, double* t
     }
 }
 
+// the same with four work items per wave, one per 16-lane team, each with
+// its own LDS (H, Q, small scratch): the reflector loops span at most n
+// lanes, so a whole wave per item left three quarters of it idle
+__global__ void __launch_bounds__(64) k_tables_schur16(int64_t E, int n, double* tab64, int32_t* status) {
+    extern __shared__ double lds[];
+    GroupTeam16 tm;
+    const long nn = (long)n * n;
+    const long ne = tab_entries(n);
+    const int gq = (int)(threadIdx.x >> 4);
+    double* H = lds + gq * (2 * nn + kMaxN + 8);
+    double* Q = H + nn;
+    double* sh = Q + nn;
+    for (int64_t w0 = (int64_t)blockIdx.x * 4; w0 < 2 * E; w0 += (int64_t)gridDim.x * 4) {
+        const int64_t w = w0 + gq;
+        if (w < 2 * E) {
+            const int64_t e = w >> 1;
+            const int i = (int)(w & 1);
+            double* tab = tab64 + e * ne;
+            const int st = tables_schur(tm, n, tab + (7 + i) * nn, tab + (5 + i) * nn, tab + (3 + i) * nn, H, Q, sh);
+            if (tm.leader() && st) atomicOr(&status[e], st);
+        }
+        tm.sync();
+    }
+}
+
 __global__ void __launch_bounds__(64) k_tables_finish(int64_t E, int dim, int n, double* tab64,
                                                       int8_t* kinds, int32_t* status) {
     extern __shared__ double lds[];  // 6 n^2 work doubles
@@ -672,9 +697,16 @@ hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank
         hipLaunchKernelGGL(k_tables_prepare, dim3(grid), dim3(64), lds, s, E, dim, n, rank, factors,
                            tab64, status);
     const int64_t items = 2 * E;
-    const int grid2 = (int)(items < 65536 ? items : 65536);
-    hipLaunchKernelGGL(k_tables_schur, dim3(grid2), dim3(64), 2 * nn * sizeof(double), s, E, n,
-                       tab64, status);
+    const size_t lds16 = 4 * (2 * nn + kMaxN + 8) * sizeof(double);
+    if (lds16 <= 64 * 1024) {
+        const int64_t wg = (items + 3) / 4;
+        const int grid16 = (int)(wg < 65536 ? wg : 65536);
+        hipLaunchKernelGGL(k_tables_schur16, dim3(grid16), dim3(64), lds16, s, E, n, tab64, status);
+    } else {
+        const int grid2 = (int)(items < 65536 ? items : 65536);
+        hipLaunchKernelGGL(k_tables_schur, dim3(grid2), dim3(64), 2 * nn * sizeof(double), s, E, n,
+                           tab64, status);
+    }
     if (lds4f <= kTables4LdsMax)
         hipLaunchKernelGGL(k_tables_finish4, dim3(grid), dim3(256), lds4f, s, E, dim, n, tab64, kinds,
                            status);

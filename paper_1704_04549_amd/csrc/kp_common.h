@@ -188,6 +188,28 @@ struct BlockTeam {
 // of its workgroup: sync is a wave-scope fence plus a wave barrier (no
 // workgroup barrier), reductions are wave shuffles.  Routines that use only
 // tid / size / sync / sum / max run unchanged on it.
+// Sixteen lanes of a wave as a team: a wave runs four such teams on
+// independent problems.  Control flow is uniform within a team (it may
+// differ between the four); sync is the wave's fence, reductions stay within
+// the team's lanes.
+struct GroupTeam16 {
+    __device__ int tid() const { return (int)(threadIdx.x & 15); }
+    __device__ int size() const { return 16; }
+    __device__ void sync() const {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    __device__ bool leader() const { return (threadIdx.x & 15) == 0; }
+    __device__ double sum(double v) const {
+        for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+        return v;
+    }
+    __device__ double max(double v) const {
+        for (int off = 8; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 16));
+        return v;
+    }
+};
+
 struct WaveTeam {
     __device__ int tid() const { return (int)(threadIdx.x & 63); }
     __device__ int size() const { return 64; }
