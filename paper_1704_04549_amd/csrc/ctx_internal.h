@@ -22,6 +22,10 @@ struct kp_ctx_s {
     // FGMRES / operator scratch
     void* ks = nullptr;
     size_t ks_bytes = 0;
+    // the matrix-free operator's per-element structure (mass tensor and axis
+    // matrices), formed once per FGMRES solve
+    void* strc = nullptr;
+    size_t strc_bytes = 0;
     // matrix-core apply for n = 16 (KP_APPLY_GENERIC=1 in the environment selects
     // the generic per-element kernel instead, for comparison)
     bool use_mfma16 = true;

@@ -62,6 +62,7 @@ kp_status kp_destroy(kp_ctx c) {
         if (c->d_tables[n]) hipFree(c->d_tables[n]);
     if (c->ws) hipFree(c->ws);
     if (c->ks) hipFree(c->ks);
+    if (c->strc) hipFree(c->strc);
     if (c->mw) hipFree(c->mw);
     if (c->pinned) hipHostFree(c->pinned);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
@@ -311,7 +312,18 @@ kp_status kp_operator_apply(kp_ctx c, const kp_batch* b, const double* x, double
     if (nd > 4096) return KP_ERR_UNSUPPORTED;
     const Tables1D* T;
     if ((st = get_tables(c, b->n, &T)) != KP_OK) return st;
-    KP_HIP(launch_operator(c->stream, E, b->dim, b->n, T, b->params, b->nbr, b->blocks, x, y));
+    KP_HIP(launch_operator(c->stream, E, b->dim, b->n, T, b->params, b->nbr, b->blocks, nullptr, x, y));
+    return KP_OK;
+}
+
+// the operator with its element structure formed once (into c->strc) and
+// read by every application of the solve
+static kp_status operator_cached(kp_ctx c, const kp_batch* b, const double* x, double* y) {
+    const Tables1D* T;
+    kp_status st = get_tables(c, b->n, &T);
+    if (st != KP_OK) return st;
+    KP_HIP(launch_operator(c->stream, b->num_elems, b->dim, b->n, T, b->params, b->nbr, b->blocks,
+                           (const double*)c->strc, x, y));
     return KP_OK;
 }
 
@@ -512,6 +524,16 @@ kp_status kp_fgmres(kp_ctx c, const kp_batch* b, int32_t pc_kind, int32_t rank, 
     const int nd = b->dim == 2 ? b->n * b->n : b->n * b->n * b->n;
     const int64_t N = b->num_elems * nd;
     VecFn op = [&](const double* in, double* out) { return kp_operator_apply(c, b, in, out); };
+    if (!b->blocks && nd <= 4096 && b->num_elems > 0) {
+        // matrix-free: form every element's structure once for the solve
+        const Tables1D* T;
+        if ((st = get_tables(c, b->n, &T)) != KP_OK) return st;
+        const size_t per = (size_t)nd + 3 * (size_t)b->n * b->n;
+        if ((st = ensure_ws(c, per * b->num_elems * sizeof(double), &c->strc, &c->strc_bytes)) != KP_OK)
+            return st;
+        KP_HIP(launch_structure(c->stream, b->num_elems, b->dim, b->n, T, b->params, (double*)c->strc));
+        op = [&](const double* in, double* out) { return operator_cached(c, b, in, out); };
+    }
     VecFn pc = [&](const double* in, double* out) {
         return fg_precond(c, b, pc_kind, rank, pc_data, pc_aux, pc_prec, in, out, N);
     };

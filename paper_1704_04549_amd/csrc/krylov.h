@@ -10,9 +10,13 @@ namespace kp {
 
 constexpr int kVecBlocks = 1024;  // grid of the vector kernels (and partial-sum rows)
 
+// strc: the elements' structure (mass n^d, then Xax 3 n^2, per element) from
+// launch_structure, or null to form it from the records in every call
 hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
                            const double* params, const int32_t* nbr, const double* blocks,
-                           const double* x, double* y);
+                           const double* strc, const double* x, double* y);
+hipError_t launch_structure(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                            const double* params, double* strc);
 hipError_t launch_mdot(hipStream_t s, const double* V, int64_t ldv, int k, const double* w,
                        int64_t N, double* partial, double* out, int accumulate);
 hipError_t launch_mgs_update(hipStream_t s, const double* V, int64_t ldv, int k, const double* h,

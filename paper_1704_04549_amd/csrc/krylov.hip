@@ -18,8 +18,8 @@ namespace kp {
 // One workgroup per element.  LDS: x_e, mass, X_ax, one face trace.
 __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, const Tables1D* tab,
                                                   const double* params, const int32_t* nbr,
-                                                  const double* blocks, const double* x,
-                                                  double* y) {
+                                                  const double* blocks, const double* strc,
+                                                  const double* x, double* y) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
     __shared__ Tables1D T;
@@ -34,14 +34,26 @@ __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, con
     const int nn = n * n;
     const int nd = dim == 2 ? nn : nn * n;
     const int nf = nd / n;  // face size n^(d-1)
+    // LDS: x of the element, the axis matrices, a face trace; the mass tensor
+    // too when it is formed here (with strc each thread reads its own entries
+    // of it from HBM, which keeps the LDS footprint and so the occupancy down)
     double* xe = lds;
-    double* mass = xe + nd;
-    double* Xax = mass + nd;
+    double* Xax = xe + nd;
     double* tr = Xax + 3 * nn;
+    double* mass_l = tr + nf;
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const double* rec = params + e * kRecLen;
         for (int t = threadIdx.x; t < nd; t += blockDim.x) xe[t] = x[e * nd + t];
-        record_structure(tm, rec, T, dim, mass, Xax);  // ends with a barrier
+        const double* mass;
+        if (strc) {
+            const double* se = strc + e * (int64_t)(nd + 3 * nn);
+            for (int t = threadIdx.x; t < 3 * nn; t += blockDim.x) Xax[t] = se[nd + t];
+            mass = se;
+            __syncthreads();
+        } else {
+            record_structure(tm, rec, T, dim, mass_l, Xax);  // ends with a barrier
+            mass = mass_l;
+        }
         double acc[16];
         const int per = (nd + blockDim.x - 1) / blockDim.x;
         for (int q = 0; q < per && q < 16; ++q) {
@@ -143,12 +155,22 @@ __global__ void __launch_bounds__(256) k_mdot_partial(const double* V, int64_t l
 }
 
 // out[i] = sum_b partial[b * k + i] (fixed order), optionally accumulated
-__global__ void k_mdot_reduce(const double* partial, int nblocks, int k, double* out, int accumulate) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= k) return;
+// one workgroup per output: thread t sums the partials b = t, t + 256, ... in
+// order, then a fixed-order reduction over the workgroup (deterministic)
+__global__ void __launch_bounds__(256) k_mdot_reduce(const double* partial, int nblocks, int k, double* out,
+                                                     int accumulate) {
+    __shared__ double red[4];
+    const int i = blockIdx.x;
     double a = 0.0;
-    for (int b = 0; b < nblocks; ++b) a += partial[(int64_t)b * k + i];
-    out[i] = accumulate ? out[i] + a : a;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) a += partial[(int64_t)b * k + i];
+    a = wave_sum(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        out[i] = accumulate ? out[i] + t : t;
+    }
 }
 
 // w -= sum_i h[i] V_i
@@ -183,14 +205,45 @@ __global__ void k_axpby(double* dst, const double* src, double a, const double* 
 // ------------------------------------------------------------ launchers
 hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
                            const double* params, const int32_t* nbr, const double* blocks,
-                           const double* x, double* y) {
+                           const double* strc, const double* x, double* y) {
     const int nn = n * n;
     const int nd = dim == 2 ? nn : nn * n;
     if (nd > 16 * 256) return hipErrorInvalidValue;
-    size_t lds = (2 * nd + 3 * nn + nd / n) * sizeof(double);
+    const double* sc = blocks ? nullptr : strc;
+    size_t lds = ((sc ? 1 : 2) * nd + 3 * nn + nd / n) * sizeof(double);
     int grid = (int)(E < 65536 ? E : 65536);
     hipLaunchKernelGGL(k_operator, dim3(grid), dim3(256), lds, s, E, dim, n, tab, params, nbr, blocks,
-                       x, y);
+                       sc, x, y);
+    return hipGetLastError();
+}
+
+// the matrix-free elements' structure: per element the mass tensor (n^d) and
+// the three axis matrices (3 n^2) of record_structure, contiguous
+__global__ void __launch_bounds__(256) k_structure(int64_t E, int dim, int n, const Tables1D* tab,
+                                                   const double* params, double* strc) {
+    __shared__ double red[4 * kMaxReduce];
+    __shared__ Tables1D T;
+    BlockTeam tm{red};
+    {
+        const double* src = (const double*)tab;
+        double* dst = (double*)&T;
+        for (int i = threadIdx.x; i < (int)(sizeof(Tables1D) / sizeof(double)); i += blockDim.x)
+            dst[i] = src[i];
+        __syncthreads();
+    }
+    const int nn = n * n;
+    const int nd = dim == 2 ? nn : nn * n;
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        double* se = strc + e * (int64_t)(nd + 3 * nn);
+        record_structure(tm, params + e * kRecLen, T, dim, se, se + nd);
+    }
+}
+
+hipError_t launch_structure(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                            const double* params, double* strc) {
+    if (E <= 0) return hipSuccess;
+    const int grid = (int)(E < 65536 ? E : 65536);
+    hipLaunchKernelGGL(k_structure, dim3(grid), dim3(256), 0, s, E, dim, n, tab, params, strc);
     return hipGetLastError();
 }
 
@@ -205,8 +258,8 @@ hipError_t launch_mdot(hipStream_t s, const double* V, int64_t ldv, int k, const
                        int64_t N, double* partial, double* out, int accumulate) {
     const int g = vec_grid(N);
     hipLaunchKernelGGL(k_mdot_partial, dim3(g), dim3(256), 0, s, V, ldv, k, w, N, partial);
-    hipLaunchKernelGGL(k_mdot_reduce, dim3((k + 63) / 64), dim3(64), 0, s, partial, g, k, out,
-                       accumulate);
+    if (k > 0)
+        hipLaunchKernelGGL(k_mdot_reduce, dim3(k), dim3(256), 0, s, partial, g, k, out, accumulate);
     return hipGetLastError();
 }
 
