@@ -39,9 +39,15 @@ hipError_t launch_fallback_mask(hipStream_t s, int64_t E, const int32_t* accept,
 // prepare and finish run on four waves per element when their scratch fits
 constexpr size_t kTables4LdsMax = 144 * 1024;
 // apply tables from the factors (three kernels: prepare, Schur, finish)
+struct MixedElem;
 hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank,
                               const double* factors, double* tab64, int8_t* kinds,
                               int32_t* status);
+// the same (rank 2) for the count elements list[0, count) of one (dim, n)
+// class of a mixed batch, at the factor and table offsets of their descriptors
+hipError_t launch_form_tables_list(hipStream_t s, int64_t count, const int32_t* list, const MixedElem* el,
+                                   int dim, int n, const double* factors, double* tab64, int8_t* kinds,
+                                   int32_t* status);
 // rank-3 2D apply (inner flexible GMRES per element); LDS budget and restart length
 constexpr size_t kRank3LdsMax = 150 * 1024;
 int rank3_restart(int n);

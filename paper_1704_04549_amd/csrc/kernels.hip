@@ -6,6 +6,7 @@
 
 #include "elem_ops.h"
 #include "kernels.h"
+#include "mixed.h"
 
 namespace kp {
 
@@ -118,13 +119,25 @@ __global__ void __launch_bounds__(256) k_setup_waves(int64_t E, int dim_rt, int 
 }
 
 // ---------------------------------------------------------- apply tables
+// Where element q of a table launch lives: contiguous (list null: element q,
+// factors at q fstride, tables at q tstride doubles) or, for a class of a
+// mixed batch, element list[q] with the offsets of its descriptor.
+struct TabAddr {
+    const int32_t* list;
+    const MixedElem* el;
+    int64_t fstride, tstride;
+    __device__ int64_t elem(int64_t q) const { return list ? (int64_t)list[q] : q; }
+    __device__ int64_t fac(int64_t e) const { return list ? el[e].fac_off : e * fstride; }
+    __device__ int64_t tab(int64_t e) const { return list ? el[e].tab_off : e * tstride; }
+};
+
 // Three kernels: prepare (one wave per element: pair rotation, inverses, C1
 // and C2), Schur (one wave per (element, C matrix), with a small LDS
 // footprint so that many run per CU) and finish (one wave per element: L
 // tables, kinds, N_j).  Intermediates live in the element's own table slots.
 __global__ void __launch_bounds__(64) k_tables_prepare(int64_t E, int dim, int n, int rank,
                                                        const double* factors, double* tab64,
-                                                       int32_t* status) {
+                                                       int32_t* status, TabAddr ad) {
     extern __shared__ double lds[];
     __shared__ double red[kMaxReduce];
     __shared__ double sh[kMaxN + 8];
@@ -132,13 +145,13 @@ __global__ void __launch_bounds__(64) k_tables_prepare(int64_t E, int dim, int n
     BlockTeam tm{red};
     const long nn = (long)n * n;
     const int nf = dim == 2 ? 2 * rank : 5;
-    const long ne = tab_entries(n);
     double* F = lds;              // nf n^2
     double* work = F + nf * nn;   // 10 n^2
-    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
-        for (long t = threadIdx.x; t < nf * nn; t += blockDim.x) F[t] = factors[e * nf * nn + t];
+    for (int64_t q = blockIdx.x; q < E; q += gridDim.x) {
+        const int64_t e = ad.elem(q);
+        for (long t = threadIdx.x; t < nf * nn; t += blockDim.x) F[t] = factors[ad.fac(e) + t];
         __syncthreads();
-        double* tab = tab64 + e * ne;
+        double* tab = tab64 + ad.tab(e);
         const int st = tables_prepare(tm, dim, n, rank, F, tab, tab + 7 * nn, work, ipiv, sh);
         if (threadIdx.x == 0) status[e] |= st;
         __syncthreads();
@@ -245,7 +258,7 @@ __device__ double norm1_group(int n, const double* M) {
 //            the N_j with j = w mod 4 (a 2 x 2 block of T2 stays on one wave).
 __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int n, int rank,
                                                          const double* factors, double* tab64,
-                                                         int32_t* status) {
+                                                         int32_t* status, TabAddr ad) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
     __shared__ double sh[4][kMaxN + 8];
@@ -258,7 +271,6 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long nn = (long)n * n;
     const int nf = dim == 2 ? 2 * rank : 5;
-    const long ne = tab_entries(n);
     // n <= 16: four matrices per wave are inverted at once (invert4), else one
     const bool grp4 = n <= 16;
     const int wsz = grp4 ? 4 : 3;          // scratch matrices per wave
@@ -268,11 +280,12 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
     double* R8 = R7 + nn;                  // right 1 (inverted)
     double* R9 = R8 + nn;                  // right 2
     double* Wv = R9 + nn + wv * wsz * nn;  // this wave's scratch
-    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
-        for (long t = threadIdx.x; t < nf * nn; t += blockDim.x) F[t] = factors[e * nf * nn + t];
+    for (int64_t q = blockIdx.x; q < E; q += gridDim.x) {
+        const int64_t e = ad.elem(q);
+        for (long t = threadIdx.x; t < nf * nn; t += blockDim.x) F[t] = factors[ad.fac(e) + t];
         if (threadIdx.x < 4) fail[threadIdx.x] = 0;
         __syncthreads();
-        double* tab = tab64 + e * ne;
+        double* tab = tab64 + ad.tab(e);
         double* N = tab + 7 * nn;
         if (dim == 2 && rank == 1) {
             // no pair to rotate: the one-team path (its work fits in R6.. onward)
@@ -417,7 +430,7 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
 }
 
 __global__ void __launch_bounds__(256) k_tables_finish4(int64_t E, int dim, int n, double* tab64,
-                                                        int8_t* kinds, int32_t* status) {
+                                                        int8_t* kinds, int32_t* status, TabAddr ad) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
     __shared__ double sh[4][kMaxN + 8];
@@ -428,12 +441,12 @@ __global__ void __launch_bounds__(256) k_tables_finish4(int64_t E, int dim, int 
     WaveTeam wt;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long nn = (long)n * n;
-    const long ne = tab_entries(n);
     const bool grp4 = n <= 16;  // the wave's four N_j inverted at once (invert4)
     double* T1 = lds;
     double* Wv = lds + nn + wv * (grp4 ? 5 : 4) * nn;  // grp4: 4 inputs, M; else W0, W1, W4, W5
-    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
-        double* tab = tab64 + e * ne;
+    for (int64_t q = blockIdx.x; q < E; q += gridDim.x) {
+        const int64_t e = ad.elem(q);
+        double* tab = tab64 + ad.tab(e);
         double* N = tab + 7 * nn;
         const double* T2 = tab + 6 * nn;
         int8_t* kd = kinds + e * kMaxN;
@@ -539,19 +552,18 @@ __global__ void __launch_bounds__(256) k_tables_finish4(int64_t E, int dim, int 
 // work item w = 2 e + i: real Schur form of C_(i+1), held in N slot i, into
 // the T_(i+1) and R_i slots
 __global__ void __launch_bounds__(64) k_tables_schur(int64_t E, int n, double* tab64,
-                                                     int32_t* status) {
+                                                     int32_t* status, TabAddr ad) {
     extern __shared__ double lds[];
     __shared__ double red[kMaxReduce];
     __shared__ double sh[kMaxN + 8];
     BlockTeam tm{red};
     const long nn = (long)n * n;
-    const long ne = tab_entries(n);
     double* H = lds;
     double* Q = lds + nn;
     for (int64_t w = blockIdx.x; w < 2 * E; w += gridDim.x) {
-        const int64_t e = w >> 1;
+        const int64_t e = ad.elem(w >> 1);
         const int i = (int)(w & 1);
-        double* tab = tab64 + e * ne;
+        double* tab = tab64 + ad.tab(e);
         const int st = tables_schur(tm, n, tab + (7 + i) * nn, tab + (5 + i) * nn,
                                     tab + (3 + i) * nn, H, Q, sh);
         if (threadIdx.x == 0 && st) atomicOr(&status[e], st);
@@ -562,11 +574,11 @@ __global__ void __launch_bounds__(64) k_tables_schur(int64_t E, int n, double* t
 // the same with four work items per wave, one per 16-lane team, each with
 // its own LDS (H, Q, small scratch): the reflector loops span at most n
 // lanes, so a whole wave per item left three quarters of it idle
-__global__ void __launch_bounds__(64) k_tables_schur16(int64_t E, int n, double* tab64, int32_t* status) {
+__global__ void __launch_bounds__(64) k_tables_schur16(int64_t E, int n, double* tab64, int32_t* status,
+                                                       TabAddr ad) {
     extern __shared__ double lds[];
     GroupTeam16 tm;
     const long nn = (long)n * n;
-    const long ne = tab_entries(n);
     const int gq = (int)(threadIdx.x >> 4);
     double* H = lds + gq * (2 * nn + kMaxN + 8);
     double* Q = H + nn;
@@ -574,9 +586,9 @@ __global__ void __launch_bounds__(64) k_tables_schur16(int64_t E, int n, double*
     for (int64_t w0 = (int64_t)blockIdx.x * 4; w0 < 2 * E; w0 += (int64_t)gridDim.x * 4) {
         const int64_t w = w0 + gq;
         if (w < 2 * E) {
-            const int64_t e = w >> 1;
+            const int64_t e = ad.elem(w >> 1);
             const int i = (int)(w & 1);
-            double* tab = tab64 + e * ne;
+            double* tab = tab64 + ad.tab(e);
             const int st = tables_schur(tm, n, tab + (7 + i) * nn, tab + (5 + i) * nn, tab + (3 + i) * nn, H, Q, sh);
             if (tm.leader() && st) atomicOr(&status[e], st);
         }
@@ -585,16 +597,16 @@ __global__ void __launch_bounds__(64) k_tables_schur16(int64_t E, int n, double*
 }
 
 __global__ void __launch_bounds__(64) k_tables_finish(int64_t E, int dim, int n, double* tab64,
-                                                      int8_t* kinds, int32_t* status) {
+                                                      int8_t* kinds, int32_t* status, TabAddr ad) {
     extern __shared__ double lds[];  // 6 n^2 work doubles
     __shared__ double red[kMaxReduce];
     __shared__ double sh[kMaxN + 8];
     __shared__ int ipiv[kMaxN];
     BlockTeam tm{red};
     const long nn = (long)n * n;
-    const long ne = tab_entries(n);
-    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
-        double* tab = tab64 + e * ne;
+    for (int64_t q = blockIdx.x; q < E; q += gridDim.x) {
+        const int64_t e = ad.elem(q);
+        double* tab = tab64 + ad.tab(e);
         const int st = tables_finish(tm, dim, n, tab, tab + 7 * nn, kinds + e * kMaxN, lds, ipiv, sh);
         if (threadIdx.x == 0) status[e] |= st;
         __syncthreads();
@@ -678,9 +690,8 @@ hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int 
     return hipGetLastError();
 }
 
-hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank,
-                              const double* factors, double* tab64, int8_t* kinds,
-                              int32_t* status) {
+static hipError_t form_tables(hipStream_t s, int64_t E, int dim, int n, int rank, const double* factors,
+                              double* tab64, int8_t* kinds, int32_t* status, TabAddr ad) {
     if (E <= 0) return hipSuccess;
     const long nn = (long)n * n;
     const int nf = dim == 2 ? 2 * rank : 5;
@@ -692,28 +703,42 @@ hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank
     const size_t lds4f = (n <= 16 ? 21 : 17) * nn * sizeof(double);
     if (lds4p <= kTables4LdsMax)
         hipLaunchKernelGGL(k_tables_prepare4, dim3(grid), dim3(256), lds4p, s, E, dim, n, rank, factors,
-                           tab64, status);
+                           tab64, status, ad);
     else
         hipLaunchKernelGGL(k_tables_prepare, dim3(grid), dim3(64), lds, s, E, dim, n, rank, factors,
-                           tab64, status);
+                           tab64, status, ad);
     const int64_t items = 2 * E;
     const size_t lds16 = 4 * (2 * nn + kMaxN + 8) * sizeof(double);
     if (lds16 <= 64 * 1024) {
         const int64_t wg = (items + 3) / 4;
         const int grid16 = (int)(wg < 65536 ? wg : 65536);
-        hipLaunchKernelGGL(k_tables_schur16, dim3(grid16), dim3(64), lds16, s, E, n, tab64, status);
+        hipLaunchKernelGGL(k_tables_schur16, dim3(grid16), dim3(64), lds16, s, E, n, tab64, status, ad);
     } else {
         const int grid2 = (int)(items < 65536 ? items : 65536);
         hipLaunchKernelGGL(k_tables_schur, dim3(grid2), dim3(64), 2 * nn * sizeof(double), s, E, n,
-                           tab64, status);
+                           tab64, status, ad);
     }
     if (lds4f <= kTables4LdsMax)
         hipLaunchKernelGGL(k_tables_finish4, dim3(grid), dim3(256), lds4f, s, E, dim, n, tab64, kinds,
-                           status);
+                           status, ad);
     else
         hipLaunchKernelGGL(k_tables_finish, dim3(grid), dim3(64), 6 * nn * sizeof(double), s, E, dim, n,
-                           tab64, kinds, status);
+                           tab64, kinds, status, ad);
     return hipGetLastError();
+}
+
+hipError_t launch_form_tables(hipStream_t s, int64_t E, int dim, int n, int rank,
+                              const double* factors, double* tab64, int8_t* kinds,
+                              int32_t* status) {
+    const long nn = (long)n * n;
+    const TabAddr ad{nullptr, nullptr, (dim == 2 ? 2 * rank : 5) * nn, tab_entries(n)};
+    return form_tables(s, E, dim, n, rank, factors, tab64, kinds, status, ad);
+}
+
+hipError_t launch_form_tables_list(hipStream_t s, int64_t count, const int32_t* list, const MixedElem* el,
+                                   int dim, int n, const double* factors, double* tab64, int8_t* kinds,
+                                   int32_t* status) {
+    return form_tables(s, count, dim, n, 2, factors, tab64, kinds, status, TabAddr{list, el, 0, 0});
 }
 
 // fragment-ordered copies of the n = 16 tables for the matrix-core apply:

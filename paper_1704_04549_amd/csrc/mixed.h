@@ -11,6 +11,7 @@
 #include <stdint.h>
 
 #include "elem_ops.h"
+#include "kernels.h"
 
 namespace kp {
 
@@ -39,8 +40,13 @@ inline size_t mixed_apply_lds(size_t elem_bytes, long block_nd, long wave_nd) {
 hipError_t launch_mixed_setup(hipStream_t s, int grid, int64_t E, const MixedElem* el, const int32_t* order,
                               Tables1D* const* tabs, const double* params, double* factors, double* sigma,
                               int32_t* status, double* ws, int64_t ws_stride, size_t small_doubles);
-hipError_t launch_mixed_tables(hipStream_t s, int64_t E, const MixedElem* el, int max_n, int nf_max,
-                               const double* factors, double* tab64, int8_t* kinds, int32_t* status);
+// the wave form: order lists its elements only; grid4 workgroups serve
+// 4 * grid4 workspace slots of ws_stride doubles; small_stride: the LDS part
+// of one wave (doubles)
+hipError_t launch_mixed_setup_waves(hipStream_t s, int grid4, int64_t E, const MixedElem* el,
+                                    const int32_t* order, Tables1D* const* tabs, const double* params,
+                                    double* factors, double* sigma, int32_t* status, double* ws,
+                                    int64_t ws_stride, int64_t small_stride);
 hipError_t launch_mixed_apply(hipStream_t s, int prec, int grid, int n_items, int n_block, const int32_t* items,
                               const MixedElem* el, const void* tabs, const int8_t* kinds, const double* r,
                               double* z, long block_nd, long wave_nd);

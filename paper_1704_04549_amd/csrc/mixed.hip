@@ -49,77 +49,39 @@ hipError_t launch_mixed_setup(hipStream_t s, int grid, int64_t E, const MixedEle
     return hipGetLastError();
 }
 
-// --------------------------------------------------------- apply tables
-__global__ void __launch_bounds__(64) k_mixed_prepare(int64_t E, const MixedElem* el, const double* factors,
-                                                      double* tab64, int32_t* status) {
-    extern __shared__ double lds[];
-    __shared__ double red[kMaxReduce];
-    __shared__ double sh[kMaxN + 8];
-    __shared__ int ipiv[kMaxN];
-    BlockTeam tm{red};
-    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+// One wave per element (four per workgroup, each with its own LDS part and
+// workspace slot), for the classes whose LDS part fits four times; the 1D
+// tables are read through the element's own table pointer (a workgroup can
+// hold elements of different n).
+__global__ void __launch_bounds__(256) k_mixed_setup_waves(int64_t E, const MixedElem* el, const int32_t* order,
+                                                           Tables1D* const* tabs, const double* params,
+                                                           double* factors, double* sigma, int32_t* status,
+                                                           double* ws, int64_t ws_stride, int64_t small_stride) {
+    extern __shared__ double small[];
+    WaveTeam tm;
+    const int wv = (int)(threadIdx.x >> 6);
+    const int64_t slot = (int64_t)blockIdx.x * 4 + wv;
+    for (int64_t q = slot; q < E; q += (int64_t)gridDim.x * 4) {
+        const int64_t e = order[q];
         const MixedElem d = el[e];
-        const long nn = (long)d.n * d.n;
-        const int nf = d.dim == 2 ? 4 : 5;
-        double* F = lds;
-        double* work = F + nf * nn;
-        for (long t = threadIdx.x; t < nf * nn; t += blockDim.x) F[t] = factors[d.fac_off + t];
-        __syncthreads();
-        double* tab = tab64 + d.tab_off;
-        const int st = tables_prepare(tm, d.dim, d.n, 2, F, tab, tab + 7 * nn, work, ipiv, sh);
-        if (threadIdx.x == 0) status[e] |= st;
-        __syncthreads();
+        const Tables1D& T = *tabs[d.n];
+        SetupWork W = carve_setup_work(ws + slot * ws_stride, d.dim, d.n, false, 2);
+        carve_small(small + wv * small_stride, d.n, false, &W);
+        const int st = setup_element<false>(tm, d.dim, d.n, 2, T, params + e * kRecLen, nullptr, nullptr,
+                                            factors + d.fac_off, sigma + e * 4, W);
+        if ((threadIdx.x & 63) == 0) status[e] = st;
+        tm.sync();
     }
 }
 
-__global__ void __launch_bounds__(64) k_mixed_schur(int64_t E, const MixedElem* el, double* tab64,
-                                                    int32_t* status) {
-    extern __shared__ double lds[];
-    __shared__ double red[kMaxReduce];
-    __shared__ double sh[kMaxN + 8];
-    BlockTeam tm{red};
-    for (int64_t w = blockIdx.x; w < 2 * E; w += gridDim.x) {
-        const int64_t e = w >> 1;
-        const int i = (int)(w & 1);
-        const MixedElem d = el[e];
-        const long nn = (long)d.n * d.n;
-        double* tab = tab64 + d.tab_off;
-        const int st = tables_schur(tm, d.n, tab + (7 + i) * nn, tab + (5 + i) * nn, tab + (3 + i) * nn, lds,
-                                    lds + nn, sh);
-        if (threadIdx.x == 0 && st) atomicOr(&status[e], st);
-        __syncthreads();
-    }
-}
-
-__global__ void __launch_bounds__(64) k_mixed_finish(int64_t E, const MixedElem* el, double* tab64,
-                                                     int8_t* kinds, int32_t* status) {
-    extern __shared__ double lds[];
-    __shared__ double red[kMaxReduce];
-    __shared__ double sh[kMaxN + 8];
-    __shared__ int ipiv[kMaxN];
-    BlockTeam tm{red};
-    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
-        const MixedElem d = el[e];
-        const long nn = (long)d.n * d.n;
-        double* tab = tab64 + d.tab_off;
-        const int st = tables_finish(tm, d.dim, d.n, tab, tab + 7 * nn, kinds + e * kMaxN, lds, ipiv, sh);
-        if (threadIdx.x == 0) status[e] |= st;
-        __syncthreads();
-    }
-}
-
-hipError_t launch_mixed_tables(hipStream_t s, int64_t E, const MixedElem* el, int max_n, int nf_max,
-                               const double* factors, double* tab64, int8_t* kinds, int32_t* status) {
+hipError_t launch_mixed_setup_waves(hipStream_t s, int grid4, int64_t E, const MixedElem* el,
+                                    const int32_t* order, Tables1D* const* tabs, const double* params,
+                                    double* factors, double* sigma, int32_t* status, double* ws,
+                                    int64_t ws_stride, int64_t small_stride) {
     if (E <= 0) return hipSuccess;
-    const long nn = (long)max_n * max_n;
-    const int grid = (int)(E < 65536 ? E : 65536);
-    hipLaunchKernelGGL(k_mixed_prepare, dim3(grid), dim3(64), (nf_max + 10) * nn * sizeof(double), s, E, el,
-                       factors, tab64, status);
-    const int64_t items = 2 * E;
-    const int grid2 = (int)(items < 65536 ? items : 65536);
-    hipLaunchKernelGGL(k_mixed_schur, dim3(grid2), dim3(64), 2 * nn * sizeof(double), s, E, el, tab64, status);
-    hipLaunchKernelGGL(k_mixed_finish, dim3(grid), dim3(64), 6 * nn * sizeof(double), s, E, el, tab64, kinds,
-                       status);
+    if (4 * small_stride * sizeof(double) > kSetupWavesLdsMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mixed_setup_waves, dim3(grid4), dim3(256), 4 * small_stride * sizeof(double), s, E, el,
+                       order, tabs, params, factors, sigma, status, ws, ws_stride, small_stride);
     return hipGetLastError();
 }
 

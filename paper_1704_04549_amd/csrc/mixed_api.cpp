@@ -32,7 +32,17 @@ struct kp_mixed_plan_s {
     int64_t fac_total = 0, tab_total = 0;
     int max_n = 2, max_nd = 4;
     int64_t ws_stride = 0;
-    size_t small_doubles = 0;
+    // setup: order[0, n_setup_block) one workgroup per element (LDS part of
+    // small_doubles), the rest one wave per element (LDS part small_wave each)
+    size_t small_doubles = 0, small_wave = 0;
+    int64_t n_setup_block = 0;
+    // elements grouped by (dim, n) class for the table kernels
+    struct Class {
+        int dim, n;
+        int64_t start, count;
+    };
+    std::vector<Class> classes;
+    int32_t* d_cls = nullptr;
     // apply work list and its launch shape
     std::map<std::pair<int, int>, int> mode;  // (dim, n) -> 0 workgroup, 1 wave
     int32_t* d_items = nullptr;
@@ -138,7 +148,6 @@ kp_status kp_mixed_plan_create(kp_ctx c, int64_t num_elems, const int32_t* dim_n
         p->max_n = std::max(p->max_n, n);
         p->max_nd = (int)std::max<long>(p->max_nd, elem_nd(d));
         wsd = std::max(wsd, setup_work_doubles(dim, n, false, 2));
-        smd = std::max(smd, (size_t)setup_small_doubles(n, false));
         present[n] = true;
         p->mode[{dim, n}] = 0;
     }
@@ -146,7 +155,22 @@ kp_status kp_mixed_plan_create(kp_ctx c, int64_t num_elems, const int32_t* dim_n
     p->fac_total = fo;
     p->tab_total = to;
     p->ws_stride = wsd;
+    // a class is set up one wave per element when four waves' LDS parts fit
+    auto wave_setup = [](int n) {
+        const size_t sm = (setup_small_doubles(n, false) + 31) / 32 * 32;
+        return 4 * sm * sizeof(double) <= kSetupWavesLdsMax;
+    };
+    size_t smw = 0;
+    for (int64_t e = 0; e < num_elems; ++e) {
+        const int n = p->h_el[e].n;
+        const size_t sm = setup_small_doubles(n, false);
+        if (wave_setup(n))
+            smw = std::max(smw, (sm + 31) / 32 * 32);
+        else
+            smd = std::max(smd, sm);
+    }
     p->small_doubles = smd;
+    p->small_wave = smw;
     size_t off = 0;
     p->sigma = off; off = al256(off + num_elems * 4 * sizeof(double));
     p->factors = off; off = al256(off + fo * sizeof(double));
@@ -164,9 +188,13 @@ kp_status kp_mixed_plan_create(kp_ctx c, int64_t num_elems, const int32_t* dim_n
     for (int64_t e = 0; e < num_elems; ++e) order[e] = (int32_t)e;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         const MixedElem &x = p->h_el[a], &y = p->h_el[b];
+        const bool wx = wave_setup(x.n), wy = wave_setup(y.n);
+        if (wx != wy) return wy;  // workgroup-mode elements first
         if (elem_nd(x) != elem_nd(y)) return elem_nd(x) > elem_nd(y);
         return x.n > y.n;
     });
+    for (int64_t e = 0; e < num_elems; ++e)
+        if (!wave_setup(p->h_el[e].n)) ++p->n_setup_block;
     Tables1D* tabs[kMaxN + 1] = {};
     for (int n = 2; n <= kMaxN; ++n)
         if (present[n]) {
@@ -178,14 +206,28 @@ kp_status kp_mixed_plan_create(kp_ctx c, int64_t num_elems, const int32_t* dim_n
             }
             tabs[n] = (Tables1D*)t;
         }
+    std::vector<int32_t> cls(num_elems);
+    for (int64_t e = 0; e < num_elems; ++e) cls[e] = (int32_t)e;
+    std::stable_sort(cls.begin(), cls.end(), [&](int32_t a, int32_t b) {
+        const MixedElem &x = p->h_el[a], &y = p->h_el[b];
+        return x.dim != y.dim ? x.dim < y.dim : x.n < y.n;
+    });
+    for (int64_t i = 0; i < num_elems; ++i) {
+        const MixedElem& d = p->h_el[cls[i]];
+        if (p->classes.empty() || p->classes.back().dim != d.dim || p->classes.back().n != d.n)
+            p->classes.push_back({d.dim, d.n, i, 0});
+        ++p->classes.back().count;
+    }
     if (num_elems > 0) {
         if (hipMalloc((void**)&p->d_el, num_elems * sizeof(MixedElem)) != hipSuccess ||
-            hipMalloc((void**)&p->d_order, num_elems * sizeof(int32_t)) != hipSuccess) {
+            hipMalloc((void**)&p->d_order, num_elems * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void**)&p->d_cls, num_elems * sizeof(int32_t)) != hipSuccess) {
             kp_mixed_plan_destroy(p);
             return KP_ERR_ALLOC;
         }
         hipMemcpy(p->d_el, p->h_el.data(), num_elems * sizeof(MixedElem), hipMemcpyHostToDevice);
         hipMemcpy(p->d_order, order.data(), num_elems * sizeof(int32_t), hipMemcpyHostToDevice);
+        hipMemcpy(p->d_cls, cls.data(), num_elems * sizeof(int32_t), hipMemcpyHostToDevice);
     }
     if (hipMalloc((void**)&p->d_tabs, sizeof(tabs)) != hipSuccess) {
         kp_mixed_plan_destroy(p);
@@ -207,6 +249,7 @@ kp_status kp_mixed_plan_destroy(kp_mixed_plan p) {
     hipDeviceSynchronize();
     if (p->d_el) hipFree(p->d_el);
     if (p->d_order) hipFree(p->d_order);
+    if (p->d_cls) hipFree(p->d_cls);
     if (p->d_tabs) hipFree(p->d_tabs);
     if (p->d_items) hipFree(p->d_items);
     delete p;
@@ -225,18 +268,28 @@ kp_status kp_mixed_setup(kp_ctx c, kp_mixed_plan p, const double* params, void* 
     if (p->E == 0) return KP_OK;
     if (!params || !precond) return KP_ERR_ARG;
     hipSetDevice(c->device);
-    const int grid = (int)(p->E < 2048 ? p->E : 2048);
-    kp_status st = ensure_ws(c, (size_t)p->ws_stride * grid * sizeof(double), &c->ws, &c->ws_bytes);
+    // the two launches run one after the other on the stream and share the
+    // workspace: at most 2048 slots each
+    const int64_t eb = p->n_setup_block, ew = p->E - eb;
+    const int grid = (int)(eb < 2048 ? eb : 2048);
+    const int grid4 = (int)((std::min<int64_t>(ew, 2048) + 3) / 4);
+    const int64_t slots = std::max<int64_t>(grid, 4 * (int64_t)grid4);
+    kp_status st = ensure_ws(c, (size_t)p->ws_stride * slots * sizeof(double), &c->ws, &c->ws_bytes);
     if (st != KP_OK) return st;
     char* pc = (char*)precond;
-    MX_HIP(launch_mixed_setup(c->stream, grid, p->E, p->d_el, p->d_order, p->d_tabs, params,
+    MX_HIP(launch_mixed_setup(c->stream, grid, eb, p->d_el, p->d_order, p->d_tabs, params,
                               (double*)(pc + p->factors), (double*)(pc + p->sigma), (int32_t*)(pc + p->status),
                               (double*)c->ws, p->ws_stride, p->small_doubles));
-    int nf_max = 4;
-    for (auto& kv : p->mode)
-        if (kv.first.first == 3) nf_max = 5;
-    MX_HIP(launch_mixed_tables(c->stream, p->E, p->d_el, p->max_n, nf_max, (const double*)(pc + p->factors),
-                               (double*)(pc + p->t64), (int8_t*)(pc + p->kinds), (int32_t*)(pc + p->status)));
+    MX_HIP(launch_mixed_setup_waves(c->stream, grid4, ew, p->d_el, p->d_order + eb, p->d_tabs, params,
+                                    (double*)(pc + p->factors), (double*)(pc + p->sigma),
+                                    (int32_t*)(pc + p->status), (double*)c->ws, p->ws_stride,
+                                    (int64_t)p->small_wave));
+    // the tables one (dim, n) class at a time, each in the launch shape of
+    // a uniform batch of that class
+    for (const auto& k : p->classes)
+        MX_HIP(launch_form_tables_list(c->stream, k.count, p->d_cls + k.start, p->d_el, k.dim, k.n,
+                                       (const double*)(pc + p->factors), (double*)(pc + p->t64),
+                                       (int8_t*)(pc + p->kinds), (int32_t*)(pc + p->status)));
     MX_HIP(launch_cast_tables(c->stream, p->tab_total, (const double*)(pc + p->t64), (float*)(pc + p->t32),
                               (uint16_t*)(pc + p->thi), (uint16_t*)(pc + p->tlo), (float*)(pc + p->t2)));
     if (elem_status)

@@ -30,7 +30,7 @@ def ctx():
 def mixed_case(seed):
     """Classes of (dim, n) with several elements each, shuffled; every element
     closed by its own upwind faces (block-diagonal system)."""
-    classes = [(2, 4, 5), (2, 7, 3), (2, 12, 4), (2, 16, 3), (2, 23, 2), (2, 31, 2), (3, 3, 4), (3, 5, 3),
+    classes = [(2, 4, 5), (2, 7, 3), (2, 12, 4), (2, 16, 3), (2, 23, 2), (2, 29, 2), (2, 31, 2), (3, 3, 4), (3, 5, 3),
                (3, 8, 3)]
     dims, ns = [], []
     for d, n, k in classes:
