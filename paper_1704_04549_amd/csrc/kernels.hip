@@ -147,8 +147,8 @@ __global__ void __launch_bounds__(64) k_tables_prepare(int64_t E, int dim, int n
     const int nf = dim == 2 ? 2 * rank : 5;
     double* F = lds;              // nf n^2
     double* work = F + nf * nn;   // 10 n^2
-    for (int64_t q = blockIdx.x; q < E; q += gridDim.x) {
-        const int64_t e = ad.elem(q);
+    for (int64_t it = blockIdx.x; it < E; it += gridDim.x) {
+        const int64_t e = ad.elem(it);
         for (long t = threadIdx.x; t < nf * nn; t += blockDim.x) F[t] = factors[ad.fac(e) + t];
         __syncthreads();
         double* tab = tab64 + ad.tab(e);
@@ -158,42 +158,48 @@ __global__ void __launch_bounds__(64) k_tables_prepare(int64_t E, int dim, int n
     }
 }
 
-// Gauss-Jordan inverses of four n x n matrices (n <= 16) in one wave: the
-// 16-lane group q = lane / 16 inverts its own matrix, lane i of the group
-// holding row i of [A | I] in registers.  Partial pivoting by the largest
-// |entry| of the column among the rows not yet used as pivots (ties: the
-// lowest row); the pivot row is scaled by the reciprocal of the pivot and
-// broadcast through the group's LDS slot (32 doubles), and every other row
-// subtracts its multiple, the same arithmetic per entry as invert().  The row
-// that was the pivot of step k ends as row k of the inverse.  Aq / Aiq: the
-// lane's group's input and output (row-major, may be the same buffer; Aq null:
-// the group idles).  Returns false on the lanes of a group whose matrix has a
-// zero pivot column.
-__device__ bool invert4(int n, const double* Aq, double* Aiq, double* slot) {
-    const int lane = (int)(threadIdx.x & 63), q = lane >> 4, i = lane & 15;
+// Gauss-Jordan inverses of 64 / G matrices of order n <= G in one wave (G =
+// 16: four, G = 32: two): the G-lane group q = lane / G inverts its own
+// matrix, lane i of the group holding row i of [A | I] in registers.  Partial
+// pivoting by the largest |entry| of the column among the rows not yet used as
+// pivots (ties: the lowest row); the pivot row is scaled by the reciprocal of
+// the pivot and broadcast through the group's LDS slot (2 G doubles), and every
+// other row subtracts its multiple, the same arithmetic per entry as invert().
+// The row that was the pivot of step k ends as row k of the inverse.  Aq /
+// Aiq: the lane's group's input and output (row-major, may be the same
+// buffer; Aq null: the group idles); slot: 128 doubles per wave.  Returns
+// false on the lanes of a group whose matrix has a zero pivot column.
+template <int G>
+__device__ bool invert_grp(int n, const double* Aq, double* Aiq, double* slot) {
+    const int lane = (int)(threadIdx.x & 63), q = lane / G, i = lane % G;
     const bool grp = Aq != nullptr;
     const bool act = grp && i < n;
-    double a[16], b[16];
+    double a[G], b[G];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < G; ++j) {
         a[j] = (act && j < n) ? Aq[i * n + j] : 0.0;
         b[j] = (act && i == j) ? 1.0 : 0.0;
     }
-    double* sl = slot + q * 32;
+    double* sl = slot + q * 2 * G;
     bool used = false, ok = true;
     int stepk = -1;
     WaveTeam wt;
     wt.sync();  // every read of Aq precedes any write of Aiq
-    // the step loop stays rolled: unrolled, the sixteen steps made the
-    // finish kernel slower (measured 0.63 against 0.44 ms for 4096 elements)
+    // the step loop stays rolled: unrolled, the sixteen steps of G = 16 made
+    // the finish kernel slower (measured 0.63 against 0.44 ms for 4096
+    // elements); a[k] is picked by selects, not by a dynamic register index
 #pragma unroll 1
     for (int k = 0; k < n; ++k) {
-        double v = (act && !used) ? fabs(a[k]) : -1.0;
+        double ak = 0.0;
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (j == k) ak = a[j];
+        double v = (act && !used) ? fabs(ak) : -1.0;
         int p = i;
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-            const double ov = __shfl_xor(v, off, 16);
-            const int op = __shfl_xor(p, off, 16);
+        for (int off = G / 2; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(v, off, G);
+            const int op = __shfl_xor(p, off, G);
             if (ov > v || (ov == v && op < p)) {
                 v = ov;
                 p = op;
@@ -203,59 +209,65 @@ __device__ bool invert4(int n, const double* Aq, double* Aiq, double* slot) {
         if (sing) ok = false;
         const bool piv = act && !sing && i == p;
         if (piv) {
-            const double inv = 1.0 / a[k];
+            const double inv = 1.0 / ak;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
+            for (int j = 0; j < G; ++j) {
                 a[j] *= inv;
                 b[j] *= inv;
                 sl[j] = a[j];
-                sl[16 + j] = b[j];
+                sl[G + j] = b[j];
             }
             used = true;
             stepk = k;
         }
         wt.sync();
         if (act && !sing && !piv) {
-            const double m = a[k];
+            const double m = ak;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
+            for (int j = 0; j < G; ++j) {
                 a[j] -= m * sl[j];
-                b[j] -= m * sl[16 + j];
+                b[j] -= m * sl[G + j];
             }
         }
         wt.sync();
     }
     if (act && stepk >= 0)
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
+        for (int j = 0; j < G; ++j)
             if (j < n) Aiq[stepk * n + j] = b[j];
     wt.sync();
     return ok || !grp;
 }
+__device__ bool invert4(int n, const double* Aq, double* Aiq, double* slot) {
+    return invert_grp<16>(n, Aq, Aiq, slot);
+}
 
-// ||M||_1 (largest column sum of |entries|) of the lane's group's n x n
-// matrix (n <= 16), on every lane of the group
+// ||M||_1 (largest column sum of |entries|) of the lane's G-lane group's
+// n x n matrix (n <= G), on every lane of the group
+template <int G = 16>
 __device__ double norm1_group(int n, const double* M) {
-    const int i = (int)(threadIdx.x & 15);
+    const int i = (int)(threadIdx.x % G);
     double c = 0.0;
     if (M != nullptr && i < n)
         for (int r = 0; r < n; ++r) c += fabs(M[r * n + i]);
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) c = fmax(c, __shfl_xor(c, off, 16));
+    for (int off = G / 2; off > 0; off >>= 1) c = fmax(c, __shfl_xor(c, off, G));
     return c;
 }
 
 // Four-wave variants of prepare and finish (256 threads per element): the
 // independent pieces of the work run on separate waves, each with its own
 // LDS scratch, with the arithmetic of the one-wave kernels (the angle search
-// compares the same scores with the same tie rule).  For n <= 16 the
-// inversions run four at a time per wave (invert4: the same operations per
-// entry; its pivot order can differ from invert()'s only on exact ties).
+// compares the same scores with the same tie rule).  The inversions
+// run in registers, four at a time per wave for n <= 16 and two for n > 16
+// (invert_grp: the same operations per entry; its pivot order can differ from
+// invert()'s only on exact ties).
 //   prepare: wave w scores the rotation angles k = w and w + 4; the inverses
 //            are formed by wave 0 (n <= 16) or waves 0..2; waves 0, 1 form
 //            C1, C2.
 //   finish:  waves 0, 1 form the two L = Q^T inverse tables; wave w forms
 //            the N_j with j = w mod 4 (a 2 x 2 block of T2 stays on one wave).
+template <bool kGrp4>
 __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int n, int rank,
                                                          const double* factors, double* tab64,
                                                          int32_t* status, TabAddr ad) {
@@ -271,17 +283,17 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long nn = (long)n * n;
     const int nf = dim == 2 ? 2 * rank : 5;
-    // n <= 16: four matrices per wave are inverted at once (invert4), else one
-    const bool grp4 = n <= 16;
-    const int wsz = grp4 ? 4 : 3;          // scratch matrices per wave
+    // n <= 16: four matrices per wave are inverted at once (invert4), else two
+    constexpr bool grp4 = kGrp4;
+    const int wsz = grp4 ? 4 : 2;          // scratch matrices per wave
     double* F = lds;                       // nf n^2
     double* R6 = F + nf * nn;              // left 1
     double* R7 = R6 + nn;                  // left 2 (inverted)
     double* R8 = R7 + nn;                  // right 1 (inverted)
     double* R9 = R8 + nn;                  // right 2
     double* Wv = R9 + nn + wv * wsz * nn;  // this wave's scratch
-    for (int64_t q = blockIdx.x; q < E; q += gridDim.x) {
-        const int64_t e = ad.elem(q);
+    for (int64_t it = blockIdx.x; it < E; it += gridDim.x) {
+        const int64_t e = ad.elem(it);
         for (long t = threadIdx.x; t < nf * nn; t += blockDim.x) F[t] = factors[ad.fac(e) + t];
         if (threadIdx.x < 4) fail[threadIdx.x] = 0;
         __syncthreads();
@@ -346,23 +358,22 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
             wt.sync();
         }
         for (int k = wv; k < 8 && !grp4; k += 4) {
+            // 32-lane group m inverts matrix m (0: rotated left 2, 1: rotated right 1)
             const double c = cos(pi * k / 8.0), sn = sin(pi * k / 8.0);
             double* W0 = Wv;
             double* W1 = Wv + nn;
-            double* W2 = Wv + 2 * nn;
             for (long t = lane; t < nn; t += 64) {
                 W0[t] = -sn * R6[t] + c * R7[t];
                 W1[t] = c * R9[t] + sn * R8[t];
             }
             wt.sync();
-            double score = 1.0;
-            for (int q = 0; q < 2; ++q) {
-                double* M = q == 0 ? W0 : W1;
-                const double nm = norm1(wt, n, M, sh[wv]);
-                const bool ok = invert(wt, n, M, W2, ipiv[wv], sh[wv] + 8);
-                const double ni = norm1(wt, n, W2, sh[wv]);
-                score *= ok ? nm * ni : 1e300;
-            }
+            double* Mq = Wv + (lane >> 5) * nn;
+            const double nm = norm1_group<32>(n, Mq);
+            const bool ok = invert_grp<32>(n, Mq, Mq, gslot[wv]);
+            const double ni = norm1_group<32>(n, Mq);
+            const double term = ok ? nm * ni : 1e300;
+            const double t0 = __shfl(term, 0, 64), t1 = __shfl(term, 32, 64);
+            double score = 1.0 * t0 * t1;
             if (!(score == score)) score = 1e300;
             if (lane == 0) scores[k] = score;
             wt.sync();
@@ -400,15 +411,13 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
             wt.sync();
         }
         if (!grp4 && wv < nq) {
+            // wave q inverts the q-th in place (its lanes 32..63 idle)
             double* W0 = Wv;
-            double* W2 = Wv + 2 * nn;
             for (long t = lane; t < nn; t += 64) W0[t] = srcs[wv][t];
             wt.sync();
-            if (!invert(wt, n, W0, W2, ipiv[wv], sh[wv] + 8) && lane == 0) fail[wv] = 1;
+            if (!invert_grp<32>(n, lane < 32 ? W0 : nullptr, W0, gslot[wv]) && lane == 0) fail[wv] = 1;
             double* dst = tab + wv * nn;
-            for (long t = lane; t < nn; t += 64) dst[t] = W2[t];
-            // keep the inverse in the wave's scratch for C below
-            for (long t = lane; t < nn; t += 64) W0[t] = W2[t];
+            for (long t = lane; t < nn; t += 64) dst[t] = W0[t];
             wt.sync();
         }
         __syncthreads();
@@ -416,7 +425,7 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
         if (wv < 2) {
             const int src_wave = dim == 2 ? wv : wv + 1;  // the wave (grp4: wave 0's group) holding inv(Y) / inv(Z)
             const double* inv = grp4 ? lds + nf * nn + 4 * nn + src_wave * nn
-                                     : lds + nf * nn + 4 * nn + src_wave * 3 * nn;
+                                     : lds + nf * nn + 4 * nn + src_wave * wsz * nn;
             const double* G = wv == 0 ? R6 : R9;
             double* out = grp4 ? Wv + 3 * nn : Wv + nn;  // clear of every inverse
             mm(wt, n, inv, G, out);
@@ -429,23 +438,23 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
     }
 }
 
+template <bool kGrp4>
 __global__ void __launch_bounds__(256) k_tables_finish4(int64_t E, int dim, int n, double* tab64,
                                                         int8_t* kinds, int32_t* status, TabAddr ad) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
-    __shared__ double sh[4][kMaxN + 8];
-    __shared__ int ipiv[4][kMaxN];
     __shared__ int fail[4];
     __shared__ double gslot[4][4 * 32];
     BlockTeam bt{red};
     WaveTeam wt;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long nn = (long)n * n;
-    const bool grp4 = n <= 16;  // the wave's four N_j inverted at once (invert4)
+    constexpr bool grp4 = kGrp4;  // n <= 16: the wave's four N_j inverted at once (invert4)
     double* T1 = lds;
-    double* Wv = lds + nn + wv * (grp4 ? 5 : 4) * nn;  // grp4: 4 inputs, M; else W0, W1, W4, W5
-    for (int64_t q = blockIdx.x; q < E; q += gridDim.x) {
-        const int64_t e = ad.elem(q);
+    double* Wv = lds + nn + wv * (grp4 ? 5 : 3) * nn;  // grp4: 4 inputs, M; else W0, W1, W4
+                                                       // (L tables), two inputs and M (N_j)
+    for (int64_t it = blockIdx.x; it < E; it += gridDim.x) {
+        const int64_t e = ad.elem(it);
         double* tab = tab64 + ad.tab(e);
         double* N = tab + 7 * nn;
         const double* T2 = tab + 6 * nn;
@@ -462,7 +471,6 @@ __global__ void __launch_bounds__(256) k_tables_finish4(int64_t E, int dim, int 
         double* W0 = Wv;
         double* W1 = Wv + nn;
         double* W4 = Wv + 2 * nn;
-        double* W5 = Wv + 3 * nn;
         // L = Q^T inverse: 2D L0, L1; 3D L1, L2 (waves 0 and 1)
         if (wv < 2) {
             double* Lq = dim == 2 ? tab + wv * nn : tab + (wv + 1) * nn;
@@ -511,30 +519,38 @@ __global__ void __launch_bounds__(256) k_tables_finish4(int64_t E, int dim, int 
             }
             wt.sync();
         }
-        for (int j = wv; j < n && !grp4; j += 4) {
-            const int k = kd[j];
-            if (k == 1) continue;  // formed with its partner j + 1
-            if (k == 0) {
-                const double tj = T2[j * n + j];
-                for (long t = lane; t < nn; t += 64) W0[t] = T1[t] + ((t / n == t % n) ? tj : 0.0);
-                wt.sync();
-                if (!invert(wt, n, W0, W1, ipiv[wv], sh[wv] + 8) && lane == 0) fail[wv] = 1;
-                for (long t = lane; t < nn; t += 64) N[(long)j * nn + t] = W1[t];
-                wt.sync();
-            } else {
-                const double p = T2[j * n + j], q = T2[(j - 1) * n + j], sv = T2[j * n + j - 1];
-                for (long t = lane; t < nn; t += 64) W4[t] = T1[t] + ((t / n == t % n) ? p : 0.0);
-                wt.sync();
-                mm(wt, n, W4, W4, W5);
-                for (long t = lane; t < nn; t += 64) W0[t] = W5[t] - ((t / n == t % n) ? q * sv : 0.0);
-                wt.sync();
-                if (!invert(wt, n, W0, W1, ipiv[wv], sh[wv] + 8) && lane == 0) fail[wv] = 1;
-                for (long t = lane; t < nn; t += 64) {
-                    N[(long)j * nn + t] = W1[t];
-                    N[(long)(j - 1) * nn + t] = W1[t];
+        // n > 16: the same, two N_j at a time (j = wv + 8 h + 4 q for the
+        // 32-lane group q); scratch: the two inputs and M
+        for (int h = 0; !grp4 && wv + 8 * h < n; ++h) {
+            double* Mt = Wv + 2 * nn;
+            for (int q = 0; q < 2; ++q) {
+                const int j = wv + 8 * h + 4 * q;
+                if (j >= n || kd[j] == 1) continue;
+                double* X = Wv + q * nn;
+                if (kd[j] == 0) {
+                    const double tj = T2[j * n + j];
+                    for (long t = lane; t < nn; t += 64) X[t] = T1[t] + ((t / n == t % n) ? tj : 0.0);
+                } else {
+                    const double p = T2[j * n + j], qv = T2[(j - 1) * n + j], sv = T2[j * n + j - 1];
+                    for (long t = lane; t < nn; t += 64) Mt[t] = T1[t] + ((t / n == t % n) ? p : 0.0);
+                    wt.sync();
+                    mm(wt, n, Mt, Mt, X);
+                    for (long t = lane; t < nn; t += 64) X[t] = X[t] - ((t / n == t % n) ? qv * sv : 0.0);
                 }
                 wt.sync();
             }
+            const int q = lane >> 5, jq = wv + 8 * h + 4 * q;
+            double* Xq = (jq < n && kd[jq] != 1) ? Wv + q * nn : nullptr;
+            if (!invert_grp<32>(n, Xq, Xq, gslot[wv]) && (lane & 31) == 0) fail[wv] = 1;
+            for (int qq = 0; qq < 2; ++qq) {
+                const int j = wv + 8 * h + 4 * qq;
+                if (j >= n || kd[j] == 1) continue;
+                for (long t = lane; t < nn; t += 64) {
+                    N[(long)j * nn + t] = Wv[qq * nn + t];
+                    if (kd[j] == 2) N[(long)(j - 1) * nn + t] = Wv[qq * nn + t];
+                }
+            }
+            wt.sync();
         }
         __syncthreads();
         // non-finite check (a NaN fails the comparison)
@@ -604,8 +620,8 @@ __global__ void __launch_bounds__(64) k_tables_finish(int64_t E, int dim, int n,
     __shared__ int ipiv[kMaxN];
     BlockTeam tm{red};
     const long nn = (long)n * n;
-    for (int64_t q = blockIdx.x; q < E; q += gridDim.x) {
-        const int64_t e = ad.elem(q);
+    for (int64_t it = blockIdx.x; it < E; it += gridDim.x) {
+        const int64_t e = ad.elem(it);
         double* tab = tab64 + ad.tab(e);
         const int st = tables_finish(tm, dim, n, tab, tab + 7 * nn, kinds + e * kMaxN, lds, ipiv, sh);
         if (threadIdx.x == 0) status[e] |= st;
@@ -699,10 +715,11 @@ static hipError_t form_tables(hipStream_t s, int64_t E, int dim, int n, int rank
     const size_t lds = (nf + 10) * nn * sizeof(double);
     const int grid = (int)(E < 65536 ? E : 65536);
     // four-wave kernels where their scratch fits in LDS, else one wave per element
-    const size_t lds4p = (nf + 4 + (n <= 16 ? 16 : 12)) * nn * sizeof(double);
-    const size_t lds4f = (n <= 16 ? 21 : 17) * nn * sizeof(double);
+    const size_t lds4p = (nf + 4 + (n <= 16 ? 16 : 8)) * nn * sizeof(double);
+    const size_t lds4f = (n <= 16 ? 21 : 13) * nn * sizeof(double);
     if (lds4p <= kTables4LdsMax)
-        hipLaunchKernelGGL(k_tables_prepare4, dim3(grid), dim3(256), lds4p, s, E, dim, n, rank, factors,
+        hipLaunchKernelGGL(n <= 16 ? k_tables_prepare4<true> : k_tables_prepare4<false>, dim3(grid), dim3(256),
+                           lds4p, s, E, dim, n, rank, factors,
                            tab64, status, ad);
     else
         hipLaunchKernelGGL(k_tables_prepare, dim3(grid), dim3(64), lds, s, E, dim, n, rank, factors,
@@ -719,7 +736,8 @@ static hipError_t form_tables(hipStream_t s, int64_t E, int dim, int n, int rank
                            tab64, status, ad);
     }
     if (lds4f <= kTables4LdsMax)
-        hipLaunchKernelGGL(k_tables_finish4, dim3(grid), dim3(256), lds4f, s, E, dim, n, tab64, kinds,
+        hipLaunchKernelGGL(n <= 16 ? k_tables_finish4<true> : k_tables_finish4<false>, dim3(grid), dim3(256),
+                           lds4f, s, E, dim, n, tab64, kinds,
                            status, ad);
     else
         hipLaunchKernelGGL(k_tables_finish, dim3(grid), dim3(64), 6 * nn * sizeof(double), s, E, dim, n,
