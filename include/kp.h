@@ -116,8 +116,13 @@ kp_status kp_set_stream(kp_ctx ctx, void* stream);
  *     replayed every restart cycle; the same kernels in the same order as
  *     without graphs.  A step that cannot be captured runs without graphs.
  *   KP_OPT_APPLY_MFMA16 (default 1): the matrix-core apply for n = 16; 0
- *     selects the generic per-element kernel. */
-typedef enum { KP_OPT_FGMRES_GRAPHS = 1, KP_OPT_APPLY_MFMA16 = 2 } kp_option;
+ *     selects the generic per-element kernel.
+ *   KP_OPT_FGMRES_Z32 (default 1): kp_fgmres keeps the preconditioned basis
+ *     Z in FP32 when the preconditioner is the rank-2 KSVD apply in FP32,
+ *     BF16 or split BF16 (kp_apply_z32); its outputs are FP32 numbers, so
+ *     the solve is the same as with an FP64 basis, with half the basis
+ *     bytes; 0 keeps Z in FP64. */
+typedef enum { KP_OPT_FGMRES_GRAPHS = 1, KP_OPT_APPLY_MFMA16 = 2, KP_OPT_FGMRES_Z32 = 3 } kp_option;
 kp_status kp_set_option(kp_ctx ctx, int32_t option, int64_t value);
 const char* kp_status_string(kp_status s);
 
@@ -186,6 +191,15 @@ kp_status kp_get_factors(kp_ctx ctx, const kp_batch* b, int32_t rank, const void
 kp_status kp_apply(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* precond,
                    int32_t prec, int32_t nrhs, const double* r, double* z);
 
+/* kp_apply with z stored in FP32: z [E][nrhs][n^d] float.  For rank 2 and
+ * prec FP32, BF16 or split BF16, whose apply ends in FP32 arithmetic: every
+ * stored value equals the one kp_apply writes as FP64 (the FP32 number it
+ * holds), with half the output bytes.  Rank 3 and prec FP64 return
+ * KP_ERR_UNSUPPORTED (their outputs are FP64 numbers); other arguments as in
+ * kp_apply. */
+kp_status kp_apply_z32(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* precond,
+                       int32_t prec, int32_t nrhs, const double* r, float* z);
+
 /* Exact block Jacobi.  Factor every explicit block by LU with partial
  * pivoting: lu [E][N][N] column-major per element (entry (i,j) at j*N + i;
  * unit lower triangle below the diagonal, U on and above), piv [E][N] (row
@@ -210,7 +224,8 @@ kp_status kp_operator_apply(kp_ctx ctx, const kp_batch* b, const double* x, doub
  * KP_ERR_NOCONV; x holds the last iterate).  Synchronises once per Arnoldi
  * step.  iters_h, relres_h: host scalars (final true relative residual);
  * hist_h: host array of hist_len per-step relative residual estimates, or
- * NULL.  Workspace: (2*restart + 3) * E * n^d doubles, owned by ctx. */
+ * NULL.  Workspace: (2*restart + 3) * E * n^d doubles (the basis Z in FP32
+ * under KP_OPT_FGMRES_Z32: restart/2 fewer), owned by ctx. */
 kp_status kp_fgmres(kp_ctx ctx, const kp_batch* b, int32_t pc_kind, int32_t rank,
                     const void* pc_data, const void* pc_aux, int32_t pc_prec, const double* rhs,
                     double* x, int32_t restart, double rtol, int32_t maxit, int32_t* iters_h,

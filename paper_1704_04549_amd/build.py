@@ -51,7 +51,8 @@ def build(verbose: bool = False) -> str:
         jobs.append([HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", path, "-o", obj])
     for src in CPP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        jobs.append([HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj])
+        # host code (the C ABI); hipcc compiles it as HIP, so it targets gfx950 too
+        jobs.append([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj])
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
         list(ex.map(_run, jobs))
     objs = [j[-1] for j in jobs]

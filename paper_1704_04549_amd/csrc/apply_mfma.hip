@@ -398,11 +398,11 @@ __device__ __forceinline__ void sylvester(const typename P::FragTab* Nf, const t
 // DIM 3: work item = (element, rhs); DIM 2: work item = (element, group of up
 // to 16 right-hand sides), the slices a being the right-hand sides.
 // LDS: the tensor (in place), T2, and the fragments of N_0..N_15.
-template <class P, int DIM>
+template <class P, int DIM, class Z = double>
 __global__ void __launch_bounds__(256) k_apply16(int64_t E, int nrhs, const typename P::Tab* tabs,
                                                  int64_t tab_stride,
                                                  const typename P::FragTab* frags,
-                                                 const int8_t* kinds, const double* r, double* z) {
+                                                 const int8_t* kinds, const double* r, Z* z) {
     typedef typename P::T T;
     typedef typename P::FragTab FT;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -478,20 +478,18 @@ __global__ void __launch_bounds__(256) k_apply16(int64_t E, int nrhs, const type
         contract<P, 1>(fL[3], X, g, c, wv);
         contract<P, 2>(fL[4], X, g, c, wv);
         if (DIM == 3) {
-            double2* zw = (double2*)(z + w * 4096);
+            Z* zw = z + w * 4096;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int t = 2 * (tid + 256 * i);
-                double2 v;
-                v.x = (double)X[xidx(t >> 8, (t >> 4) & 15, t & 15)];
-                v.y = (double)X[xidx(t >> 8, (t >> 4) & 15, (t & 15) + 1)];
-                zw[tid + 256 * i] = v;
+                zw[t] = (Z)X[xidx(t >> 8, (t >> 4) & 15, t & 15)];
+                zw[t + 1] = (Z)X[xidx(t >> 8, (t >> 4) & 15, (t & 15) + 1)];
             }
         } else {
             const int s0 = grp * 16;
             for (int t = tid; t < 4096; t += 256) {
                 const int a = t >> 8, s = s0 + a;
-                if (s < nrhs) z[(e * nrhs + s) * 256 + (t & 255)] = (double)X[xidx(a, (t >> 4) & 15, t & 15)];
+                if (s < nrhs) z[(e * nrhs + s) * 256 + (t & 255)] = (Z)X[xidx(a, (t >> 4) & 15, t & 15)];
             }
         }
         __syncthreads();
@@ -691,10 +689,12 @@ __device__ __forceinline__ void load_item3(Item3<P>& x, int64_t it, int nrhs, co
     for (int j = 0; j < 16; ++j) x.kd[j] = kinds[e * kMaxN + j];
 }
 
-template <class P, int WPE>
+// Z: the type z is stored in (float only where the arithmetic is FP32, so that
+// the stored values are exactly those of the double store)
+template <class P, int WPE, class Z = double>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) k_apply16r3(
     int64_t E, int nrhs, const typename P::Tab* tabs, int64_t tab_stride, const int8_t* kinds, const double* r,
-    double* z) {
+    Z* z) {
     typedef typename P::T T;
     extern __shared__ __align__(16) unsigned char smem[];
     T* M = (T*)smem;         // transpose buffer; the Sylvester buffers alias it
@@ -721,11 +721,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8
         transpose_tg<P>(R, M, g, c, w);    // (c, a, b)
         contract_reg<P, true>(x.fR1, R);   // R1 on c: (c, a, b) -> (a, c, b)
 
-        double* zw = z + it * 4096;
+        Z* zw = z + it * 4096;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) zw[P::orow(g, v) * 256 + tile_of(s, w) * 16 + c] = (double)R[s][v];
+            for (int v = 0; v < 4; ++v) zw[P::orow(g, v) * 256 + tile_of(s, w) * 16 + c] = (Z)R[s][v];
     }
 }
 
@@ -733,26 +733,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8
 // 128 registers; split BF16: 3; FP64: 2).  One workgroup per item: a
 // persistent grid that prefetches the next item into registers measured
 // slower (it needs half the occupancy).
-template <class P, int WPE>
+template <class P, int WPE, class Z>
 static hipError_t launch16r3(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
-                             const int8_t* kinds, const double* r, double* z) {
+                             const int8_t* kinds, const double* r, Z* z) {
     const int64_t work = E * nrhs;
     const int grid = (int)(work < kApply16Grid ? work : kApply16Grid);
     const size_t lds = (kR3Work + 256) * sizeof(typename P::T);
-    hipLaunchKernelGGL((k_apply16r3<P, WPE>), dim3(grid), dim3(256), lds, st, E, nrhs, (const typename P::Tab*)tabs,
-                       tab_stride, kinds, r, z);
+    hipLaunchKernelGGL((k_apply16r3<P, WPE, Z>), dim3(grid), dim3(256), lds, st, E, nrhs,
+                       (const typename P::Tab*)tabs, tab_stride, kinds, r, z);
     return hipGetLastError();
 }
 
-template <class P, int DIM>
+template <class P, int DIM, class Z>
 static hipError_t launch16(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
-                           const void* frags, const int8_t* kinds, const double* r, double* z) {
+                           const void* frags, const int8_t* kinds, const double* r, Z* z) {
     const int groups = DIM == 3 ? nrhs : (nrhs + 15) / 16;
     const int64_t work = E * groups;
     const int grid = (int)(work < kApply16Grid ? work : kApply16Grid);
     const size_t lds = (kTensor + 256) * sizeof(typename P::T) +
                        16 * 64 * 4 * P::kFragStride * sizeof(typename P::FragTab);
-    hipLaunchKernelGGL((k_apply16<P, DIM>), dim3(grid), dim3(256), lds, st, E, nrhs,
+    hipLaunchKernelGGL((k_apply16<P, DIM, Z>), dim3(grid), dim3(256), lds, st, E, nrhs,
                        (const typename P::Tab*)tabs, tab_stride, (const typename P::FragTab*)frags,
                        kinds, r, z);
     return hipGetLastError();
@@ -771,6 +771,24 @@ hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs,
     }
     switch (prec) {
         case 0: return launch16<PolF64, 2>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
+        case 1: return launch16<PolF32, 2>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
+        case 2: return launch16<PolBF16, 2>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
+        default: return launch16<PolBF16X3, 2>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
+    }
+}
+
+hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
+                          int64_t tab_stride, const void* frags, const int8_t* kinds,
+                          const double* r, float* z) {
+    if (prec == 0) return hipErrorInvalidValue;  // FP64 arithmetic: z stays FP64
+    if (dim == 3) {
+        switch (prec) {
+            case 1: return launch16r3<PolF32, 4>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 2: return launch16r3<PolBF16, 4>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            default: return launch16r3<PolBF16X3, 3>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+        }
+    }
+    switch (prec) {
         case 1: return launch16<PolF32, 2>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
         case 2: return launch16<PolBF16, 2>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);
         default: return launch16<PolBF16X3, 2>(s, E, nrhs, tabs, tab_stride, frags, kinds, r, z);

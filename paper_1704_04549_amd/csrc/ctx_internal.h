@@ -37,6 +37,7 @@ struct kp_ctx_s {
     // FGMRES steps as HIP graphs: a private stream for capture (default
     // priority) and pinned host memory for the projections
     bool use_graphs = false;
+    bool fgmres_z32 = true;  // FP32 basis Z where the preconditioner's outputs are FP32 numbers
     hipStream_t cap_stream = nullptr;
     double* pinned = nullptr;
     size_t pinned_doubles = 0;
@@ -94,6 +95,13 @@ static inline kp_status check_batch(const kp_batch* b, bool need_params = true) 
 
 // a device-vector map (operator or preconditioner) for the FGMRES driver
 typedef std::function<kp_status(const double*, double*)> VecFn;
+// the preconditioned basis Z kept in FP32: the preconditioner writes z_j in
+// FP32 and the operator reads it (used where the preconditioner's outputs are
+// FP32 numbers, so that the basis holds exactly what an FP64 one would)
+struct Z32Fns {
+    std::function<kp_status(const double*, float*)> pc;
+    std::function<kp_status(const float*, double*)> op;
+};
 kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, const double* rhs, double* x,
                       int32_t restart, double rtol, int32_t maxit, int32_t* iters_h, double* relres_h,
-                      double* hist_h, int32_t hist_len);
+                      double* hist_h, int32_t hist_len, const Z32Fns* z32 = nullptr);

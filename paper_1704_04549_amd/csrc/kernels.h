@@ -68,5 +68,13 @@ hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs,
 hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
                                 const void* tabs, int64_t tab_stride, const int8_t* kinds,
                                 const double* r, double* z);
+// the same two with z stored in FP32 (prec FP32, BF16, split BF16 only: their
+// results are FP32 numbers, stored exactly; prec FP64 is refused)
+hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
+                          int64_t tab_stride, const void* frags, const int8_t* kinds,
+                          const double* r, float* z);
+hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
+                                const void* tabs, int64_t tab_stride, const int8_t* kinds,
+                                const double* r, float* z);
 
 }  // namespace kp

@@ -648,11 +648,11 @@ __global__ void k_cast_tables(int64_t count, const double* t64, float* t32, uint
 
 // --------------------------------------------------------- generic apply
 // One workgroup per (element, rhs); tensor in LDS, tables read from global.
-template <typename T, typename TT, class Rnd>
+template <typename T, typename TT, class Rnd, class Z = double>
 __global__ void __launch_bounds__(256) k_apply_generic(int64_t E, int dim, int n, int nrhs,
                                                        const TT* tabs, int64_t tab_stride,
                                                        const int8_t* kinds, const double* r,
-                                                       double* z, Rnd rnd) {
+                                                       Z* z, Rnd rnd) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
     BlockTeam tm{red};
@@ -665,7 +665,7 @@ __global__ void __launch_bounds__(256) k_apply_generic(int64_t E, int dim, int n
         for (long t = threadIdx.x; t < nd; t += blockDim.x) X[t] = (T)r[w * nd + t];
         __syncthreads();
         apply_tensor(tm, dim, n, tabs + e * tab_stride, kinds + e * kMaxN, X, Y, H, rnd);
-        for (long t = threadIdx.x; t < nd; t += blockDim.x) z[w * nd + t] = (double)X[t];
+        for (long t = threadIdx.x; t < nd; t += blockDim.x) z[w * nd + t] = (Z)X[t];
         __syncthreads();
     }
 }
@@ -805,32 +805,45 @@ hipError_t launch_cast_tables(hipStream_t s, int64_t count, const double* t64, f
     return hipGetLastError();
 }
 
-hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
-                                const void* tabs, int64_t tab_stride, const int8_t* kinds,
-                                const double* r, double* z) {
+template <class Z>
+static hipError_t apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs, const void* tabs,
+                                int64_t tab_stride, const int8_t* kinds, const double* r, Z* z) {
     const long nd = dim == 2 ? n * n : n * n * n;
     int64_t work = E * nrhs;
     int grid = (int)(work < 65536 ? work : 65536);
     if (prec == 0) {
         size_t lds = 4 * nd * sizeof(double);
-        hipLaunchKernelGGL((k_apply_generic<double, double, RoundNone>), dim3(grid), dim3(256), lds, s,
+        hipLaunchKernelGGL((k_apply_generic<double, double, RoundNone, Z>), dim3(grid), dim3(256), lds, s,
                            E, dim, n, nrhs, (const double*)tabs, tab_stride, kinds, r, z, RoundNone());
     } else if (prec == 1) {
         size_t lds = 4 * nd * sizeof(float);
-        hipLaunchKernelGGL((k_apply_generic<float, float, RoundNone>), dim3(grid), dim3(256), lds, s,
+        hipLaunchKernelGGL((k_apply_generic<float, float, RoundNone, Z>), dim3(grid), dim3(256), lds, s,
                            E, dim, n, nrhs, (const float*)tabs, tab_stride, kinds, r, z, RoundNone());
     } else if (prec == 2) {
         size_t lds = 4 * nd * sizeof(float);
-        hipLaunchKernelGGL((k_apply_generic<float, uint16_t, RoundBf16>), dim3(grid), dim3(256), lds,
+        hipLaunchKernelGGL((k_apply_generic<float, uint16_t, RoundBf16, Z>), dim3(grid), dim3(256), lds,
                            s, E, dim, n, nrhs, (const uint16_t*)tabs, tab_stride, kinds, r, z,
                            RoundBf16());
     } else {
         size_t lds = 4 * nd * sizeof(float);
-        hipLaunchKernelGGL((k_apply_generic<float, float, RoundBf16x2>), dim3(grid), dim3(256), lds,
+        hipLaunchKernelGGL((k_apply_generic<float, float, RoundBf16x2, Z>), dim3(grid), dim3(256), lds,
                            s, E, dim, n, nrhs, (const float*)tabs, tab_stride, kinds, r, z,
                            RoundBf16x2());
     }
     return hipGetLastError();
+}
+
+hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
+                                const void* tabs, int64_t tab_stride, const int8_t* kinds,
+                                const double* r, double* z) {
+    return apply_generic(s, prec, E, dim, n, nrhs, tabs, tab_stride, kinds, r, z);
+}
+
+hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
+                                const void* tabs, int64_t tab_stride, const int8_t* kinds,
+                                const double* r, float* z) {
+    if (prec == 0) return hipErrorInvalidValue;  // FP64 arithmetic: z stays FP64
+    return apply_generic(s, prec, E, dim, n, nrhs, tabs, tab_stride, kinds, r, z);
 }
 
 }  // namespace kp

@@ -75,6 +75,7 @@ kp_status kp_set_option(kp_ctx c, int32_t option, int64_t value) {
     switch (option) {
         case KP_OPT_FGMRES_GRAPHS: c->use_graphs = value != 0; return KP_OK;
         case KP_OPT_APPLY_MFMA16: c->use_mfma16 = value != 0; return KP_OK;
+        case KP_OPT_FGMRES_Z32: c->fgmres_z32 = value != 0; return KP_OK;
     }
     return KP_ERR_ARG;
 }
@@ -234,14 +235,20 @@ kp_status kp_get_factors(kp_ctx c, const kp_batch* b, int32_t rank, const void* 
     return KP_OK;
 }
 
-kp_status kp_apply(kp_ctx c, const kp_batch* b, int32_t rank, const void* precond, int32_t prec,
-                   int32_t nrhs, const double* r, double* z) {
+}  // extern "C"
+
+// z = P^{-1} r, z FP64 (Z = double) or FP32 (Z = float; rank 2, prec not FP64)
+template <class Z>
+static kp_status apply_impl(kp_ctx c, const kp_batch* b, int32_t rank, const void* precond, int32_t prec,
+                            int32_t nrhs, const double* r, Z* z) {
+    constexpr bool z32 = sizeof(Z) == 4;
     if (!c) return KP_ERR_ARG;
     kp_status st = check_batch(b, false);
     if (st != KP_OK) return st;
     PcLayout L;
     if (!pc_layout(b->dim, b->n, rank, b->num_elems, &L)) return KP_ERR_ARG;
     if (prec < KP_FP64 || prec > KP_BF16X3 || nrhs < 1) return KP_ERR_ARG;
+    if (z32 && (prec == KP_FP64 || rank != 2)) return KP_ERR_UNSUPPORTED;
     const int64_t E = b->num_elems;
     if (E == 0) return KP_OK;
     if (!precond || !r || !z) return KP_ERR_ARG;
@@ -251,9 +258,10 @@ kp_status kp_apply(kp_ctx c, const kp_batch* b, int32_t rank, const void* precon
                        : prec == KP_BF16 ? (const void*)(pc + L.thi)
                                          : (const void*)(pc + L.t2);
     if (rank == 3) {
-        // 2D only (pc_layout rejects rank 3 in 3D)
-        KP_HIP(launch_apply_rank3(c->stream, prec, E, b->n, nrhs, (const double*)(pc + L.factors),
-                                  tabs, L.ne, (const int8_t*)(pc + L.kinds), r, z));
+        // 2D only (pc_layout rejects rank 3 in 3D); FP64 z only (checked above)
+        if constexpr (!z32)
+            KP_HIP(launch_apply_rank3(c->stream, prec, E, b->n, nrhs, (const double*)(pc + L.factors),
+                                      tabs, L.ne, (const int8_t*)(pc + L.kinds), r, z));
     } else if (b->n == 16 && c->use_mfma16) {
         const void* frags = prec == KP_FP64   ? (const void*)(pc + L.f64f)
                             : prec == KP_FP32 ? (const void*)(pc + L.f32f)
@@ -266,6 +274,18 @@ kp_status kp_apply(kp_ctx c, const kp_batch* b, int32_t rank, const void* precon
                                     (const int8_t*)(pc + L.kinds), r, z));
     }
     return KP_OK;
+}
+
+extern "C" {
+
+kp_status kp_apply(kp_ctx c, const kp_batch* b, int32_t rank, const void* precond, int32_t prec,
+                   int32_t nrhs, const double* r, double* z) {
+    return apply_impl(c, b, rank, precond, prec, nrhs, r, z);
+}
+
+kp_status kp_apply_z32(kp_ctx c, const kp_batch* b, int32_t rank, const void* precond, int32_t prec,
+                       int32_t nrhs, const double* r, float* z) {
+    return apply_impl(c, b, rank, precond, prec, nrhs, r, z);
 }
 
 kp_status kp_blockjacobi_exact(kp_ctx c, const kp_batch* b, double* lu, int32_t* piv,
@@ -318,14 +338,21 @@ kp_status kp_operator_apply(kp_ctx c, const kp_batch* b, const double* x, double
 
 // the operator with its element structure formed once (into c->strc) and
 // read by every application of the solve
-static kp_status operator_cached(kp_ctx c, const kp_batch* b, const double* x, double* y) {
+}  // extern "C"
+
+// (cached false: formed in every call, as kp_operator_apply does); x FP64 or
+// FP32
+template <class X>
+static kp_status operator_run(kp_ctx c, const kp_batch* b, bool cached, const X* x, double* y) {
     const Tables1D* T;
     kp_status st = get_tables(c, b->n, &T);
     if (st != KP_OK) return st;
     KP_HIP(launch_operator(c->stream, b->num_elems, b->dim, b->n, T, b->params, b->nbr, b->blocks,
-                           (const double*)c->strc, x, y));
+                           cached ? (const double*)c->strc : nullptr, x, y));
     return KP_OK;
 }
+
+extern "C" {
 
 // apply the selected preconditioner: z = M v
 static kp_status fg_precond(kp_ctx c, const kp_batch* b, int pc_kind, int rank, const void* pc_data,
@@ -344,20 +371,23 @@ static kp_status fg_precond(kp_ctx c, const kp_batch* b, int pc_kind, int rank, 
 // kp_fgmres and kp_mixed_fgmres.
 kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, const double* rhs, double* x,
                       int32_t restart, double rtol, int32_t maxit, int32_t* iters_h, double* relres_h,
-                      double* hist_h, int32_t hist_len) {
+                      double* hist_h, int32_t hist_len, const Z32Fns* z32) {
     kp_status st;
     const int m = restart;
     if (iters_h) *iters_h = 0;
     if (relres_h) *relres_h = 0.0;
     if (N == 0) return KP_OK;
-    // workspace: V (m+1) N, Z m N, w N, r N, partial, h (2 (m+2)), y (m)
+    // workspace: V (m+1) N, Z m N (FP64, or FP32 with z32), w N, r N,
+    // partial, h (2 (m+2)), y (m)
     const size_t vec = (size_t)N;
     const size_t part = (size_t)kVecBlocks * (m + 2);
-    const size_t need = ((2 * (size_t)m + 3) * vec + part + 3 * (size_t)(m + 2)) * sizeof(double);
+    const size_t zd = z32 ? ((size_t)m * vec + 1) / 2 : (size_t)m * vec;  // Z in doubles
+    const size_t need = ((m + 3) * vec + zd + part + 3 * (size_t)(m + 2)) * sizeof(double);
     if ((st = ensure_ws(c, need, &c->ks, &c->ks_bytes)) != KP_OK) return st;
     double* V = (double*)c->ks;
     double* Z = V + (m + 1) * vec;
-    double* w = Z + m * vec;
+    float* Z32 = (float*)Z;
+    double* w = Z + zd;
     double* r = w + vec;
     double* partial = r + vec;
     double* hd = partial + part;   // m + 2
@@ -415,12 +445,18 @@ kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, con
         for (int j = 0; j < m; ++j) {
             double* vj = V + j * vec;
             double* zj = Z + j * vec;
+            float* zj32 = Z32 + j * vec;
             // the step's device work, enqueued on c->stream
             auto step = [&]() -> kp_status {
                 kp_status s2;
                 hipStream_t q = c->stream;
-                if ((s2 = pc(vj, zj)) != KP_OK) return s2;
-                if ((s2 = op(zj, w)) != KP_OK) return s2;
+                if (z32) {
+                    if ((s2 = z32->pc(vj, zj32)) != KP_OK) return s2;
+                    if ((s2 = z32->op(zj32, w)) != KP_OK) return s2;
+                } else {
+                    if ((s2 = pc(vj, zj)) != KP_OK) return s2;
+                    if ((s2 = op(zj, w)) != KP_OK) return s2;
+                }
                 // classical Gram-Schmidt, twice
                 KP_HIP(launch_mdot(q, V, vec, j + 1, w, N, partial, hd, 0));
                 KP_HIP(launch_mgs_update(q, V, vec, j + 1, hd, w, N));
@@ -491,7 +527,10 @@ kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, con
             y[i] = d != 0.0 ? t / d : 0.0;
         }
         KP_HIP(hipMemcpyAsync(yd, y, k * sizeof(double), hipMemcpyHostToDevice, s));
-        KP_HIP(launch_combine(s, Z, vec, k, yd, x, N));
+        if (z32)
+            KP_HIP(launch_combine(s, Z32, vec, k, yd, x, N));
+        else
+            KP_HIP(launch_combine(s, Z, vec, k, yd, x, N));
         // true residual
         if ((st = op(x, w)) != KP_OK) return st;
         KP_HIP(launch_axpby(s, r, rhs, 1.0, w, -1.0, N));
@@ -524,6 +563,7 @@ kp_status kp_fgmres(kp_ctx c, const kp_batch* b, int32_t pc_kind, int32_t rank, 
     const int nd = b->dim == 2 ? b->n * b->n : b->n * b->n * b->n;
     const int64_t N = b->num_elems * nd;
     VecFn op = [&](const double* in, double* out) { return kp_operator_apply(c, b, in, out); };
+    bool cached = false;
     if (!b->blocks && nd <= 4096 && b->num_elems > 0) {
         // matrix-free: form every element's structure once for the solve
         const Tables1D* T;
@@ -532,12 +572,21 @@ kp_status kp_fgmres(kp_ctx c, const kp_batch* b, int32_t pc_kind, int32_t rank, 
         if ((st = ensure_ws(c, per * b->num_elems * sizeof(double), &c->strc, &c->strc_bytes)) != KP_OK)
             return st;
         KP_HIP(launch_structure(c->stream, b->num_elems, b->dim, b->n, T, b->params, (double*)c->strc));
-        op = [&](const double* in, double* out) { return operator_cached(c, b, in, out); };
+        cached = true;
+        op = [&](const double* in, double* out) { return operator_run(c, b, true, in, out); };
     }
     VecFn pc = [&](const double* in, double* out) {
         return fg_precond(c, b, pc_kind, rank, pc_data, pc_aux, pc_prec, in, out, N);
     };
-    return fgmres_core(c, N, op, pc, rhs, x, restart, rtol, maxit, iters_h, relres_h, hist_h, hist_len);
+    // the rank-2 apply in FP32, BF16 or split BF16 ends in FP32 arithmetic:
+    // its outputs are FP32 numbers, so the basis Z holds them in FP32 (the
+    // same values, half the bytes)
+    Z32Fns z32{[&](const double* in, float* out) { return kp_apply_z32(c, b, rank, pc_data, pc_prec, 1, in, out); },
+               [&](const float* in, double* out) { return operator_run(c, b, cached, in, out); }};
+    const bool use_z32 = c->fgmres_z32 && pc_kind == KP_PC_KSVD && rank == 2 && pc_prec != KP_FP64 &&
+                         nd <= 4096;
+    return fgmres_core(c, N, op, pc, rhs, x, restart, rtol, maxit, iters_h, relres_h, hist_h, hist_len,
+                       use_z32 ? &z32 : nullptr);
 }
 
 }  // extern "C"

@@ -15,6 +15,10 @@ constexpr int kVecBlocks = 1024;  // grid of the vector kernels (and partial-sum
 hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
                            const double* params, const int32_t* nbr, const double* blocks,
                            const double* strc, const double* x, double* y);
+// the same with x stored in FP32
+hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                           const double* params, const int32_t* nbr, const double* blocks,
+                           const double* strc, const float* x, double* y);
 hipError_t launch_structure(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
                             const double* params, double* strc);
 hipError_t launch_mdot(hipStream_t s, const double* V, int64_t ldv, int k, const double* w,
@@ -22,6 +26,8 @@ hipError_t launch_mdot(hipStream_t s, const double* V, int64_t ldv, int k, const
 hipError_t launch_mgs_update(hipStream_t s, const double* V, int64_t ldv, int k, const double* h,
                              double* w, int64_t N);
 hipError_t launch_combine(hipStream_t s, const double* Z, int64_t ldz, int k, const double* y,
+                          double* x, int64_t N);
+hipError_t launch_combine(hipStream_t s, const float* Z, int64_t ldz, int k, const double* y,
                           double* x, int64_t N);
 hipError_t launch_axpby(hipStream_t s, double* dst, const double* src, double a, const double* other,
                         double b, int64_t N);

@@ -15,11 +15,14 @@
 
 namespace kp {
 
-// One workgroup per element.  LDS: x_e, mass, X_ax, one face trace.
+// One workgroup per element.  LDS: x_e, mass, X_ax, one face trace.  X: the
+// type x is stored in (float for an FGMRES basis of FP32 preconditioner
+// outputs; every value is taken to FP64 exactly on load).
+template <class X>
 __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, const Tables1D* tab,
                                                   const double* params, const int32_t* nbr,
                                                   const double* blocks, const double* strc,
-                                                  const double* x, double* y) {
+                                                  const X* x, double* y) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
     __shared__ Tables1D T;
@@ -43,7 +46,7 @@ __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, con
     double* mass_l = tr + nf;
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const double* rec = params + e * kRecLen;
-        for (int t = threadIdx.x; t < nd; t += blockDim.x) xe[t] = x[e * nd + t];
+        for (int t = threadIdx.x; t < nd; t += blockDim.x) xe[t] = (double)x[e * nd + t];
         const double* mass;
         if (strc) {
             const double* se = strc + e * (int64_t)(nd + 3 * nn);
@@ -96,12 +99,12 @@ __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, con
                 int stride = 1;
                 for (int k = ax + 1; k < dim; ++k) stride *= n;
                 // neighbour's trace on its opposite face: tr[J] = sum_k l_out[k] x_nb[..k..]
-                const double* xf = x + nb * nd;
+                const X* xf = x + nb * nd;
                 for (int J = threadIdx.x; J < nf; J += blockDim.x) {
                     const int lo = J % stride, hi = J / stride;
                     const int base = hi * stride * n + lo;
                     double s = 0.0;
-                    for (int k = 0; k < n; ++k) s += l_out[k] * xf[base + k * stride];
+                    for (int k = 0; k < n; ++k) s += l_out[k] * (double)xf[base + k * stride];
                     tr[J] = s;
                 }
                 __syncthreads();
@@ -184,12 +187,13 @@ __global__ void k_mgs_update(const double* V, int64_t ldv, int k, const double* 
     }
 }
 
-// x += sum_i y[i] Z_i
-__global__ void k_combine(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t N) {
+// x += sum_i y[i] Z_i (Z FP64 or FP32, taken to FP64 exactly)
+template <class ZT>
+__global__ void k_combine(const ZT* Z, int64_t ldz, int k, const double* y, double* x, int64_t N) {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N;
          t += (int64_t)gridDim.x * blockDim.x) {
         double s = x[t];
-        for (int i = 0; i < k; ++i) s += y[i] * Z[i * ldz + t];
+        for (int i = 0; i < k; ++i) s += y[i] * (double)Z[i * ldz + t];
         x[t] = s;
     }
 }
@@ -203,18 +207,31 @@ __global__ void k_axpby(double* dst, const double* src, double a, const double* 
 }
 
 // ------------------------------------------------------------ launchers
-hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
-                           const double* params, const int32_t* nbr, const double* blocks,
-                           const double* strc, const double* x, double* y) {
+template <class X>
+static hipError_t operator_any(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                               const double* params, const int32_t* nbr, const double* blocks,
+                               const double* strc, const X* x, double* y) {
     const int nn = n * n;
     const int nd = dim == 2 ? nn : nn * n;
     if (nd > 16 * 256) return hipErrorInvalidValue;
     const double* sc = blocks ? nullptr : strc;
     size_t lds = ((sc ? 1 : 2) * nd + 3 * nn + nd / n) * sizeof(double);
     int grid = (int)(E < 65536 ? E : 65536);
-    hipLaunchKernelGGL(k_operator, dim3(grid), dim3(256), lds, s, E, dim, n, tab, params, nbr, blocks,
+    hipLaunchKernelGGL(k_operator<X>, dim3(grid), dim3(256), lds, s, E, dim, n, tab, params, nbr, blocks,
                        sc, x, y);
     return hipGetLastError();
+}
+
+hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                           const double* params, const int32_t* nbr, const double* blocks,
+                           const double* strc, const double* x, double* y) {
+    return operator_any(s, E, dim, n, tab, params, nbr, blocks, strc, x, y);
+}
+
+hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                           const double* params, const int32_t* nbr, const double* blocks,
+                           const double* strc, const float* x, double* y) {
+    return operator_any(s, E, dim, n, tab, params, nbr, blocks, strc, x, y);
 }
 
 // the matrix-free elements' structure: per element the mass tensor (n^d) and
@@ -271,7 +288,13 @@ hipError_t launch_mgs_update(hipStream_t s, const double* V, int64_t ldv, int k,
 
 hipError_t launch_combine(hipStream_t s, const double* Z, int64_t ldz, int k, const double* y,
                           double* x, int64_t N) {
-    hipLaunchKernelGGL(k_combine, dim3(vec_grid(N)), dim3(256), 0, s, Z, ldz, k, y, x, N);
+    hipLaunchKernelGGL(k_combine<double>, dim3(vec_grid(N)), dim3(256), 0, s, Z, ldz, k, y, x, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(hipStream_t s, const float* Z, int64_t ldz, int k, const double* y,
+                          double* x, int64_t N) {
+    hipLaunchKernelGGL(k_combine<float>, dim3(vec_grid(N)), dim3(256), 0, s, Z, ldz, k, y, x, N);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ KP_OK, KP_ERR_ARG, KP_ERR_ALLOC, KP_ERR_HIP, KP_ERR_NUMERIC, KP_ERR_NOCONV, KP_E
 KP_FP64, KP_FP32, KP_BF16, KP_BF16X3 = 0, 1, 2, 3
 KP_SETUP_SVD, KP_SETUP_LEARNED, KP_SETUP_LEARNED_WARM = 0, 1, 2
 KP_PC_NONE, KP_PC_KSVD, KP_PC_BJ = 0, 1, 2
-KP_OPT_FGMRES_GRAPHS, KP_OPT_APPLY_MFMA16 = 1, 2
+KP_OPT_FGMRES_GRAPHS, KP_OPT_APPLY_MFMA16, KP_OPT_FGMRES_Z32 = 1, 2, 3
 ELEM_LANCZOS_NOCONV, ELEM_SINGULAR_FACTOR, ELEM_SCHUR_NOCONV, ELEM_NONFINITE = 1, 2, 4, 8
 ELEM_LEARNED_REJECTED, ELEM_LEARNED_WARM = 16, 32
 REC_LEN = 16
@@ -61,6 +61,7 @@ def lib() -> ctypes.CDLL:
             "kp_setup_from_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_get_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_apply": ([vp, bp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
+            "kp_apply_z32": ([vp, bp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
             "kp_blockjacobi_exact": ([vp, bp, vp, vp, vp], ctypes.c_int),
             "kp_blockjacobi_solve": ([vp, bp, vp, vp, i32, vp, vp], ctypes.c_int),
             "kp_operator_apply": ([vp, bp, vp, vp], ctypes.c_int),
@@ -219,6 +220,20 @@ class Ctx:
             z = torch.empty_like(r)
         _check(lib().kp_apply(self.h, ctypes.byref(b.c), rank, _ptr(precond), int(prec), int(nrhs),
                               _ptr(r), _ptr(z)), "kp_apply")
+        return z
+
+    def apply_z32(self, b: Batch, rank: int, precond, prec, r: torch.Tensor, z=None):
+        """kp_apply_z32: as apply, z float32 (rank 2; prec fp32, bf16 or bf16x3)."""
+        prec = PREC.get(prec, prec)
+        if r.dtype != torch.float64:
+            raise ValueError("r must be float64")
+        nrhs = r.numel() // (b.num_elems * b.ndof) if b.num_elems else 1
+        if z is None:
+            z = torch.empty(r.shape, dtype=torch.float32, device=r.device)
+        if z.dtype != torch.float32 or z.numel() != r.numel():
+            raise ValueError("z must be float32 with r's size")
+        _check(lib().kp_apply_z32(self.h, ctypes.byref(b.c), rank, _ptr(precond), int(prec), int(nrhs),
+                                  _ptr(r), _ptr(z)), "kp_apply_z32")
         return z
 
     def blockjacobi_exact(self, b: Batch, lu=None, piv=None, status=None):
