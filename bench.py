@@ -109,8 +109,8 @@ def kernel_source_hash():
 # valid only for the kernel source they were taken on (profiles/ holds the
 # counter summary and the commands).
 MEASURED_TRAFFIC = {
-    "source_sha256": "1259fc28890ed674337502c9e336bf5bccf08e4c29b12d52e926dea7fe9ae9e1",
-    "bytes": {"fp32": 365901143, "fp64": 462487492},
+    "source_sha256": "7594c523c2030485aa815beb3817ccf412a5b6489e62e7acf49ff2aeb0752005",
+    "bytes": {"fp32": 298792857, "fp64": 462476218},
 }
 
 
