@@ -169,8 +169,9 @@ __global__ void __launch_bounds__(64) k_tables_prepare(int64_t E, int dim, int n
 // Aiq: the lane's group's input and output (row-major, may be the same
 // buffer; Aq null: the group idles); slot: 128 doubles per wave.  Returns
 // false on the lanes of a group whose matrix has a zero pivot column.
+// (always inlined: a call left the caller's registers to the call ABI)
 template <int G>
-__device__ bool invert_grp(int n, const double* Aq, double* Aiq, double* slot) {
+__device__ __forceinline__ bool invert_grp(int n, const double* Aq, double* Aiq, double* slot) {
     const int lane = (int)(threadIdx.x & 63), q = lane / G, i = lane % G;
     const bool grp = Aq != nullptr;
     const bool act = grp && i < n;
@@ -273,8 +274,6 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
                                                          int32_t* status, TabAddr ad) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
-    __shared__ double sh[4][kMaxN + 8];
-    __shared__ int ipiv[4][kMaxN];
     __shared__ double scores[8];
     __shared__ int fail[4];
     __shared__ double gslot[4][4 * 32];
@@ -299,13 +298,6 @@ __global__ void __launch_bounds__(256) k_tables_prepare4(int64_t E, int dim, int
         __syncthreads();
         double* tab = tab64 + ad.tab(e);
         double* N = tab + 7 * nn;
-        if (dim == 2 && rank == 1) {
-            // no pair to rotate: the one-team path (its work fits in R6.. onward)
-            const int st = tables_prepare(bt, dim, n, rank, F, tab, N, R6, ipiv[0], sh[0]);
-            if (threadIdx.x == 0) status[e] |= st;
-            __syncthreads();
-            continue;
-        }
         for (long t = threadIdx.x; t < 3 * nn; t += blockDim.x) tab[t] = 0.0;
         // balance the norms within each term
         const double* l1 = dim == 2 ? F : F + nn;
@@ -717,7 +709,8 @@ static hipError_t form_tables(hipStream_t s, int64_t E, int dim, int n, int rank
     // four-wave kernels where their scratch fits in LDS, else one wave per element
     const size_t lds4p = (nf + 4 + (n <= 16 ? 16 : 8)) * nn * sizeof(double);
     const size_t lds4f = (n <= 16 ? 21 : 13) * nn * sizeof(double);
-    if (lds4p <= kTables4LdsMax)
+    // 2D rank 1 has no pair to rotate: the one-wave kernel
+    if (lds4p <= kTables4LdsMax && !(dim == 2 && rank == 1))
         hipLaunchKernelGGL(n <= 16 ? k_tables_prepare4<true> : k_tables_prepare4<false>, dim3(grid), dim3(256),
                            lds4p, s, E, dim, n, rank, factors,
                            tab64, status, ad);

@@ -134,24 +134,39 @@ __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, con
 
 // ---------------------------------------------------------- vector kernels
 // partial[b * k + i] = sum over block b's chunk of V_i . w   (i < k)
+// Eight V_i per pass over the chunk, so w is read ceil(k / 8) times instead of
+// k times; each V_i . w is summed in the same order as one at a time.
 __global__ void __launch_bounds__(256) k_mdot_partial(const double* V, int64_t ldv, int k,
                                                       const double* w, int64_t N, double* partial) {
-    __shared__ double red[4 * 64];
+    constexpr int kG = 8;
+    __shared__ double red[kG][4];
     const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
     const int64_t lo = blockIdx.x * chunk;
     const int64_t hi = lo + chunk < N ? lo + chunk : N;
-    for (int i = 0; i < k; ++i) {
-        const double* v = V + i * ldv;
-        double s = 0.0;
-        for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) s += v[t] * w[t];
-        s = wave_sum(s);
-        if (lane == 0) red[wv] = s;
+    for (int i0 = 0; i0 < k; i0 += kG) {
+        const int kk = k - i0 < kG ? k - i0 : kG;
+        const double* v = V + i0 * ldv;
+        double s[kG];
+#pragma unroll
+        for (int q = 0; q < kG; ++q) s[q] = 0.0;
+        for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+            const double wt = w[t];
+#pragma unroll
+            for (int q = 0; q < kG; ++q)
+                if (q < kk) s[q] += v[q * ldv + t] * wt;
+        }
+#pragma unroll
+        for (int q = 0; q < kG; ++q)
+            if (q < kk) {
+                const double r = wave_sum(s[q]);
+                if (lane == 0) red[q][wv] = r;
+            }
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < kk) {
             double a = 0.0;
-            for (int q = 0; q < nw; ++q) a += red[q];
-            partial[blockIdx.x * (int64_t)k + i] = a;
+            for (int q = 0; q < nw; ++q) a += red[threadIdx.x][q];
+            partial[blockIdx.x * (int64_t)k + i0 + threadIdx.x] = a;
         }
         __syncthreads();
     }
