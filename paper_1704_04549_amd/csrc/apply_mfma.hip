@@ -691,15 +691,22 @@ __device__ __forceinline__ void load_item3(Item3<P>& x, int64_t it, int nrhs, co
 
 // Z: the type z is stored in (float only where the arithmetic is FP32, so that
 // the stored values are exactly those of the double store)
+// stagger, nres: the workgroups [nres / 2, nres) of the first resident round
+// (nres = workgroups resident on the chip) start stagger * 2048 cycles late,
+// so that half the resident workgroups load while the other half compute (the
+// identical workgroups otherwise run their load, compute and store phases in
+// step); 0: no delay.
 template <class P, int WPE, class Z = double>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) k_apply16r3(
     int64_t E, int nrhs, const typename P::Tab* tabs, int64_t tab_stride, const int8_t* kinds, const double* r,
-    Z* z) {
+    Z* z, int stagger, int nres) {
     typedef typename P::T T;
     extern __shared__ __align__(16) unsigned char smem[];
     T* M = (T*)smem;         // transpose buffer; the Sylvester buffers alias it
     T* T2s = M + kR3Work;    // T2, row-major
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, g = l >> 4, c = l & 15;
+    if ((int)blockIdx.x < nres && 2 * (int)blockIdx.x >= nres)
+        for (int i = 0; i < stagger; ++i) __builtin_amdgcn_s_sleep(32);
     const int64_t work = E * nrhs;
     for (int64_t it = blockIdx.x; it < work; it += gridDim.x) {
         // every global load of the item first
@@ -733,14 +740,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8
 // 128 registers; split BF16: 3; FP64: 2).  One workgroup per item: a
 // persistent grid that prefetches the next item into registers measured
 // slower (it needs half the occupancy).
-template <class P, int WPE, class Z>
+// compute units of the current device (queried once per device)
+static int device_cus() {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cus[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
+
+// STAGGER: the delay of the late half of the first round (see k_apply16r3),
+// used for batches of at least four rounds; measured at n = 16, 4096
+// elements: FP32 76.8 -> 72.7 us, split BF16 84.9 -> 83.1 us, no gain for
+// BF16 (already closer to the HBM bound) or FP64
+template <class P, int WPE, int STAGGER, class Z>
 static hipError_t launch16r3(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
                              const int8_t* kinds, const double* r, Z* z) {
     const int64_t work = E * nrhs;
     const int grid = (int)(work < kApply16Grid ? work : kApply16Grid);
     const size_t lds = (kR3Work + 256) * sizeof(typename P::T);
+    const int nres = WPE * device_cus();  // WPE resident workgroups per CU (a wave per SIMD each)
+    const int stagger = (STAGGER > 0 && nres > 0 && work >= 4 * (int64_t)nres) ? STAGGER : 0;
     hipLaunchKernelGGL((k_apply16r3<P, WPE, Z>), dim3(grid), dim3(256), lds, st, E, nrhs,
-                       (const typename P::Tab*)tabs, tab_stride, kinds, r, z);
+                       (const typename P::Tab*)tabs, tab_stride, kinds, r, z, stagger, nres);
     return hipGetLastError();
 }
 
@@ -763,10 +789,10 @@ hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs,
                           const double* r, double* z) {
     if (dim == 3) {
         switch (prec) {
-            case 0: return launch16r3<PolF64, 2>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            case 1: return launch16r3<PolF32, 4>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            case 2: return launch16r3<PolBF16, 4>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            default: return launch16r3<PolBF16X3, 3>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 0: return launch16r3<PolF64, 2, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 1: return launch16r3<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 2: return launch16r3<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            default: return launch16r3<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
         }
     }
     switch (prec) {
@@ -783,9 +809,9 @@ hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs,
     if (prec == 0) return hipErrorInvalidValue;  // FP64 arithmetic: z stays FP64
     if (dim == 3) {
         switch (prec) {
-            case 1: return launch16r3<PolF32, 4>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            case 2: return launch16r3<PolBF16, 4>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            default: return launch16r3<PolBF16X3, 3>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 1: return launch16r3<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 2: return launch16r3<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            default: return launch16r3<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
         }
     }
     switch (prec) {
