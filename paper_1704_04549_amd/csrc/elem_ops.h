@@ -1421,7 +1421,7 @@ KP_HD void contract_axis(const Team& tm, int dim, int n, int ax, const TT* M, co
 
 // X: n^d working tensor (holds the result on return); Y, Hs: n^d scratch.
 template <class Team, typename T, typename TT, class Rnd>
-KP_HD void apply_tensor(const Team& tm, int dim, int n, const TT* tab, const int8_t* kinds, T* X,
+KP_HD_FORCEINLINE void apply_tensor(const Team& tm, int dim, int n, const TT* tab, const int8_t* kinds, T* X,
                         T* Y, T* Hs, Rnd rnd) {
     const int nn = n * n;
     const TT* L[3] = {tab, tab + nn, tab + 2 * nn};

@@ -15,10 +15,14 @@
 #define KP_HD __host__ __device__
 #define KP_DEV __device__
 #define KP_INLINE __host__ __device__ inline
+// always inlined on the device: no calls inside a kernel (the call ABI then
+// handles the caller's registers)
+#define KP_HD_FORCEINLINE __host__ __device__ __forceinline__
 #else
 #define KP_HD
 #define KP_DEV
 #define KP_INLINE inline
+#define KP_HD_FORCEINLINE inline
 #endif
 
 namespace kp {
