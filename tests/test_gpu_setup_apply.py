@@ -108,7 +108,8 @@ def test_setup_and_apply_parity(ctx, dim, n, E, seed, face, explicit):
 
 
 def test_c4_matrix_free_sampled(ctx):
-    """3D p=15 matrix-free setup at full size (4096 elements); sampled oracle check."""
+    """3D p=15 matrix-free setup at full size (4096 elements); sampled oracle check,
+    and the FP32-z apply equal to the FP32 apply on every element."""
     from tests.gpu_util import batch, rel, to_dev
     w = synth.workload("c4_3d_p15")
     n, dim, E = 16, 3, w["num_elems"]
@@ -119,7 +120,11 @@ def test_c4_matrix_free_sampled(ctx):
     rd = to_dev(w["rhs"][:, 0, :])
     z64 = ctx.apply(b, 2, pc, "fp64", rd)
     z32 = ctx.apply(b, 2, pc, "fp32", rd)
+    # the launch the benchmark times (z stored in FP32): the same values on
+    # every element
+    z32f = ctx.apply_z32(b, 2, pc, "fp32", rd)
     torch.cuda.synchronize()
+    assert torch.equal(z32f.double(), z32)
     assert int((st != 0).sum()) == 0
     f_gpu = f_gpu.cpu().numpy()
     T = tables(n)
