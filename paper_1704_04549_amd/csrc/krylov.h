@@ -8,7 +8,7 @@
 
 namespace kp {
 
-constexpr int kVecBlocks = 1024;  // grid of the vector kernels (and partial-sum rows)
+constexpr int kVecBlocks = 8192;  // grid of the vector kernels (and partial-sum rows)
 
 // strc: the elements' structure (mass n^d, then Xax 3 n^2, per element) from
 // launch_structure, or null to form it from the records in every call

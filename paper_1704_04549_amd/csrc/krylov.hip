@@ -133,28 +133,41 @@ __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, con
 }
 
 // ---------------------------------------------------------- vector kernels
-// partial[b * k + i] = sum over block b's chunk of V_i . w   (i < k)
-// Eight V_i per pass over the chunk, so w is read ceil(k / 8) times instead of
-// k times; each V_i . w is summed in the same order as one at a time.
+// partial[b * k + i] = sum over block b's entries of V_i . w   (i < k), the
+// blocks striding over the vector.  Eight V_i per pass, so w is read
+// ceil(k / 8) times; PAIR: two entries per thread and load (16 bytes; N and
+// the vector stride even, the vectors 16-byte aligned), which keeps more bytes
+// in flight per wave.
+template <bool PAIR>
 __global__ void __launch_bounds__(256) k_mdot_partial(const double* V, int64_t ldv, int k,
                                                       const double* w, int64_t N, double* partial) {
     constexpr int kG = 8;
     __shared__ double red[kG][4];
     const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = blockIdx.x * chunk;
-    const int64_t hi = lo + chunk < N ? lo + chunk : N;
+    const int64_t M = PAIR ? N / 2 : N;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int i0 = 0; i0 < k; i0 += kG) {
         const int kk = k - i0 < kG ? k - i0 : kG;
         const double* v = V + i0 * ldv;
         double s[kG];
 #pragma unroll
         for (int q = 0; q < kG; ++q) s[q] = 0.0;
-        for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-            const double wt = w[t];
+        for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < M; t += stride) {
+            if (PAIR) {
+                const double2 wt = ((const double2*)w)[t];
 #pragma unroll
-            for (int q = 0; q < kG; ++q)
-                if (q < kk) s[q] += v[q * ldv + t] * wt;
+                for (int q = 0; q < kG; ++q)
+                    if (q < kk) {
+                        const double2 x = ((const double2*)(v + q * ldv))[t];
+                        s[q] += x.x * wt.x;
+                        s[q] += x.y * wt.y;
+                    }
+            } else {
+                const double wt = w[t];
+#pragma unroll
+                for (int q = 0; q < kG; ++q)
+                    if (q < kk) s[q] += v[q * ldv + t] * wt;
+            }
         }
 #pragma unroll
         for (int q = 0; q < kG; ++q)
@@ -191,14 +204,27 @@ __global__ void __launch_bounds__(256) k_mdot_reduce(const double* partial, int 
     }
 }
 
-// w -= sum_i h[i] V_i
+// w -= sum_i h[i] V_i (PAIR as for k_mdot_partial)
+template <bool PAIR>
 __global__ void k_mgs_update(const double* V, int64_t ldv, int k, const double* h, double* w,
                              int64_t N) {
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N;
+    const int64_t M = PAIR ? N / 2 : N;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < M;
          t += (int64_t)gridDim.x * blockDim.x) {
-        double s = w[t];
-        for (int i = 0; i < k; ++i) s -= h[i] * V[i * ldv + t];
-        w[t] = s;
+        if (PAIR) {
+            double2 s = ((const double2*)w)[t];
+            for (int i = 0; i < k; ++i) {
+                const double2 v = ((const double2*)(V + i * ldv))[t];
+                const double hi = h[i];
+                s.x -= hi * v.x;
+                s.y -= hi * v.y;
+            }
+            ((double2*)w)[t] = s;
+        } else {
+            double s = w[t];
+            for (int i = 0; i < k; ++i) s -= h[i] * V[i * ldv + t];
+            w[t] = s;
+        }
     }
 }
 
@@ -286,10 +312,18 @@ int vec_grid(int64_t N) {
     return (int)g;
 }
 
+// two entries per thread and 16-byte loads where every vector allows them
+static bool pairs_ok(const double* V, int64_t ldv, int k, const double* w, int64_t N) {
+    return N % 2 == 0 && (k <= 1 || ldv % 2 == 0) && ((uintptr_t)V % 16) == 0 && ((uintptr_t)w % 16) == 0;
+}
+
 hipError_t launch_mdot(hipStream_t s, const double* V, int64_t ldv, int k, const double* w,
                        int64_t N, double* partial, double* out, int accumulate) {
     const int g = vec_grid(N);
-    hipLaunchKernelGGL(k_mdot_partial, dim3(g), dim3(256), 0, s, V, ldv, k, w, N, partial);
+    if (pairs_ok(V, ldv, k, w, N))
+        hipLaunchKernelGGL(k_mdot_partial<true>, dim3(g), dim3(256), 0, s, V, ldv, k, w, N, partial);
+    else
+        hipLaunchKernelGGL(k_mdot_partial<false>, dim3(g), dim3(256), 0, s, V, ldv, k, w, N, partial);
     if (k > 0)
         hipLaunchKernelGGL(k_mdot_reduce, dim3(k), dim3(256), 0, s, partial, g, k, out, accumulate);
     return hipGetLastError();
@@ -297,7 +331,10 @@ hipError_t launch_mdot(hipStream_t s, const double* V, int64_t ldv, int k, const
 
 hipError_t launch_mgs_update(hipStream_t s, const double* V, int64_t ldv, int k, const double* h,
                              double* w, int64_t N) {
-    hipLaunchKernelGGL(k_mgs_update, dim3(vec_grid(N)), dim3(256), 0, s, V, ldv, k, h, w, N);
+    if (pairs_ok(V, ldv, k, w, N))
+        hipLaunchKernelGGL(k_mgs_update<true>, dim3(vec_grid(N)), dim3(256), 0, s, V, ldv, k, h, w, N);
+    else
+        hipLaunchKernelGGL(k_mgs_update<false>, dim3(vec_grid(N)), dim3(256), 0, s, V, ldv, k, h, w, N);
     return hipGetLastError();
 }
 
