@@ -121,8 +121,19 @@ kp_status kp_set_stream(kp_ctx ctx, void* stream);
  *     Z in FP32 when the preconditioner is the rank-2 KSVD apply in FP32,
  *     BF16 or split BF16 (kp_apply_z32); its outputs are FP32 numbers, so
  *     the solve is the same as with an FP64 basis, with half the basis
- *     bytes; 0 keeps Z in FP64. */
-typedef enum { KP_OPT_FGMRES_GRAPHS = 1, KP_OPT_APPLY_MFMA16 = 2, KP_OPT_FGMRES_Z32 = 3 } kp_option;
+ *     bytes; 0 keeps Z in FP64.
+ *   KP_OPT_OPERATOR_COLS (default 1): kp_operator_apply and kp_fgmres apply
+ *     the matrix-free operator of 3D batches with n <= 16 with one thread per
+ *     column of each element (the element structure formed first); the
+ *     entries are formed from the same terms in the same order as by the
+ *     one-entry-per-thread kernel (equal to rounding); 0 selects that
+ *     kernel. */
+typedef enum {
+    KP_OPT_FGMRES_GRAPHS = 1,
+    KP_OPT_APPLY_MFMA16 = 2,
+    KP_OPT_FGMRES_Z32 = 3,
+    KP_OPT_OPERATOR_COLS = 4
+} kp_option;
 kp_status kp_set_option(kp_ctx ctx, int32_t option, int64_t value);
 const char* kp_status_string(kp_status s);
 
@@ -211,7 +222,9 @@ kp_status kp_blockjacobi_solve(kp_ctx ctx, const kp_batch* b, const double* lu,
                                const int32_t* piv, int32_t nrhs, const double* r, double* z);
 
 /* y = G x for the global operator: diagonal blocks (explicit or
- * matrix-free) plus the upwind inflow coupling through nbr. x, y: [E][n^d]. */
+ * matrix-free) plus the upwind inflow coupling through nbr. x, y: [E][n^d].
+ * Matrix-free 3D batches with n <= 16 (KP_OPT_OPERATOR_COLS) first form the
+ * element structure into ctx workspace ((n^3 + 3 n^2) doubles per element). */
 kp_status kp_operator_apply(kp_ctx ctx, const kp_batch* b, const double* x, double* y);
 
 /* FGMRES(restart) on G x = rhs from x = 0 with flexible right

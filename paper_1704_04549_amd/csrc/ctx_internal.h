@@ -37,7 +37,8 @@ struct kp_ctx_s {
     // FGMRES steps as HIP graphs: a private stream for capture (default
     // priority) and pinned host memory for the projections
     bool use_graphs = false;
-    bool fgmres_z32 = true;  // FP32 basis Z where the preconditioner's outputs are FP32 numbers
+    bool fgmres_z32 = true;
+    bool op_cols = true;     // column-per-thread operator kernel for 3D n <= 16 (matrix-free)  // FP32 basis Z where the preconditioner's outputs are FP32 numbers
     hipStream_t cap_stream = nullptr;
     double* pinned = nullptr;
     size_t pinned_doubles = 0;

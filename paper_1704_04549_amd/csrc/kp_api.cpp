@@ -76,6 +76,7 @@ kp_status kp_set_option(kp_ctx c, int32_t option, int64_t value) {
         case KP_OPT_FGMRES_GRAPHS: c->use_graphs = value != 0; return KP_OK;
         case KP_OPT_APPLY_MFMA16: c->use_mfma16 = value != 0; return KP_OK;
         case KP_OPT_FGMRES_Z32: c->fgmres_z32 = value != 0; return KP_OK;
+        case KP_OPT_OPERATOR_COLS: c->op_cols = value != 0; return KP_OK;
     }
     return KP_ERR_ARG;
 }
@@ -332,6 +333,15 @@ kp_status kp_operator_apply(kp_ctx c, const kp_batch* b, const double* x, double
     if (nd > 4096) return KP_ERR_UNSUPPORTED;
     const Tables1D* T;
     if ((st = get_tables(c, b->n, &T)) != KP_OK) return st;
+    if (!b->blocks && b->dim == 3 && b->n <= 16 && c->op_cols) {
+        // the column kernel reads the element structure: form it first
+        const size_t per = (size_t)nd + 3 * (size_t)b->n * b->n;
+        if ((st = ensure_ws(c, per * E * sizeof(double), &c->strc, &c->strc_bytes)) != KP_OK) return st;
+        KP_HIP(launch_structure(c->stream, E, b->dim, b->n, T, b->params, (double*)c->strc));
+        KP_HIP(launch_operator(c->stream, E, b->dim, b->n, T, b->params, b->nbr, b->blocks,
+                               (const double*)c->strc, x, y, true));
+        return KP_OK;
+    }
     KP_HIP(launch_operator(c->stream, E, b->dim, b->n, T, b->params, b->nbr, b->blocks, nullptr, x, y));
     return KP_OK;
 }
@@ -348,7 +358,7 @@ static kp_status operator_run(kp_ctx c, const kp_batch* b, bool cached, const X*
     kp_status st = get_tables(c, b->n, &T);
     if (st != KP_OK) return st;
     KP_HIP(launch_operator(c->stream, b->num_elems, b->dim, b->n, T, b->params, b->nbr, b->blocks,
-                           cached ? (const double*)c->strc : nullptr, x, y));
+                           cached ? (const double*)c->strc : nullptr, x, y, c->op_cols));
     return KP_OK;
 }
 

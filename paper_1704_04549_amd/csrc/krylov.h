@@ -11,14 +11,17 @@ namespace kp {
 constexpr int kVecBlocks = 8192;  // grid of the vector kernels (and partial-sum rows)
 
 // strc: the elements' structure (mass n^d, then Xax 3 n^2, per element) from
-// launch_structure, or null to form it from the records in every call
+// launch_structure, or null to form it from the records in every call.
+// cols: 3D elements with n <= 16 and strc take the column-per-thread kernel
+// (the same terms in the same order); false keeps the one-entry-per-thread
+// kernel.
 hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
                            const double* params, const int32_t* nbr, const double* blocks,
-                           const double* strc, const double* x, double* y);
+                           const double* strc, const double* x, double* y, bool cols = true);
 // the same with x stored in FP32
 hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
                            const double* params, const int32_t* nbr, const double* blocks,
-                           const double* strc, const float* x, double* y);
+                           const double* strc, const float* x, double* y, bool cols = true);
 hipError_t launch_structure(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
                             const double* params, double* strc);
 hipError_t launch_mdot(hipStream_t s, const double* V, int64_t ldv, int k, const double* w,

@@ -132,6 +132,131 @@ __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, con
     }
 }
 
+// The same operator for 3D elements with n <= 16 whose structure is cached
+// (strc): thread (b, c) of an element holds the column x[., b, c] in
+// registers and forms y[a, b, c] for every a; x of the element, X0, X1, X2
+// (transposed) and the six face traces of the inflow neighbours sit in LDS
+// (the traces are formed first, all loads of a trace in flight together).
+// 256 / n^2 elements per workgroup.  Every entry is formed from the terms of
+// k_operator in the same order (mass term, the three axes, then the inflow
+// faces in face order); the two agree to rounding (the compiler may fuse
+// multiply-adds differently).
+template <class X>
+__global__ void __launch_bounds__(256) k_operator3_cols(int64_t E, int n, const Tables1D* tab,
+                                                        const double* params, const int32_t* nbr,
+                                                        const double* strc, const X* x, double* y) {
+    extern __shared__ double lds[];
+    const int nn = n * n, nd = nn * n;
+    const int epw = 256 / nn;                 // elements per workgroup
+    const int slot = (int)threadIdx.x / nn;   // this thread's element slot
+    const int bc = (int)threadIdx.x % nn, b = bc / n, c = bc % n;
+    const bool act = slot < epw;
+    double* xs = lds + (act ? slot : 0) * (nd + 9 * nn);  // x of the element (n^3)
+    double* X0 = xs + nd;                                 // axis-0 matrix
+    double* X1 = X0 + nn;                                 // axis-1 matrix
+    double* X2t = X1 + nn;                                // axis-2 matrix, transposed
+    double* trs = X2t + nn;                               // face f's trace at trs + f n^2
+    const double* w = tab->w;
+    const double wb = act ? w[b] : 0.0, wc = act ? w[c] : 0.0;
+    for (int64_t e0 = (int64_t)blockIdx.x * epw; e0 < E; e0 += (int64_t)gridDim.x * epw) {
+        const int64_t e = e0 + slot;
+        const bool live = act && e < E;
+        const double* se = strc + (live ? e : 0) * (int64_t)(nd + 3 * nn);
+        const double* rec = params + (live ? e : 0) * kRecLen;
+        const bool faces = live && nbr && rec[7] != 0.0;
+        double xc[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) xc[k] = (live && k < n) ? (double)x[e * nd + k * nn + bc] : 0.0;
+        if (live) {
+            X0[bc] = se[nd + bc];
+            X1[bc] = se[nd + nn + bc];
+            X2t[c * n + b] = se[nd + 2 * nn + bc];  // X2[b][c] at (c, b)
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k < n) xs[k * nn + bc] = xc[k];
+        }
+        // the inflow faces' traces of the neighbours: face f's entry at
+        // (b, c) is, for axis 0, the trace at (b, c); axis 1, at (a, c) = (b, c);
+        // axis 2, at (a, b) = (b, c)
+        for (int f = 0; f < 6; ++f) {
+            if (!(faces && rec[8 + f] < 0.0)) continue;
+            const int ax = f >> 1;
+            const double* l_out = (f & 1) ? tab->l0 : tab->l1;
+            const X* xf = x + (int64_t)nbr[e * 6 + f] * nd;
+            double xv[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int J = ax == 0 ? k * nn + bc : ax == 1 ? b * nn + k * n + c : b * nn + c * n + k;
+                xv[k] = k < n ? (double)xf[J] : 0.0;
+            }
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k < n) sum += l_out[k] * xv[k];
+            trs[f * nn + bc] = sum;
+        }
+        __syncthreads();
+        if (live) {
+            // the mass column first, its loads in flight together
+            double mv[16];
+#pragma unroll
+            for (int a = 0; a < 16; ++a) mv[a] = a < n ? se[a * nn + bc] : 0.0;
+#pragma unroll
+            for (int a = 0; a < 16; ++a) {
+                if (a >= n) break;
+                const int I = a * nn + bc;
+                double v = mv[a] * xs[I];
+                // axis 0: w_b w_c sum_k X0[a][k] x[k, b, c]
+                {
+                    const double wp = 1.0 * wb * wc;
+                    double sum = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 16; ++k)
+                        if (k < n) sum += X0[a * n + k] * xc[k];
+                    v += wp * sum;
+                }
+                const double wa = w[a];
+                // axis 1: w_a w_c sum_k X1[b][k] x[a, k, c]
+                {
+                    const double wp = 1.0 * wa * wc;
+                    double sum = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 16; ++k)
+                        if (k < n) sum += X1[b * n + k] * xs[a * nn + k * n + c];
+                    v += wp * sum;
+                }
+                // axis 2: w_a w_b sum_k X2[c][k] x[a, b, k]
+                {
+                    const double wp = 1.0 * wa * wb;
+                    double sum = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 16; ++k)
+                        if (k < n) sum += X2t[k * n + c] * xs[a * nn + b * n + k];
+                    v += wp * sum;
+                }
+                // upwind coupling on the inflow faces, in face order
+                if (faces) {
+                    for (int f = 0; f < 6; ++f) {
+                        const double u = rec[8 + f];
+                        if (!(u < 0.0)) continue;
+                        const int ax = f >> 1;
+                        const double* l_in = (f & 1) ? tab->l1 : tab->l0;
+                        const double coef = rec[6] * u;
+                        const double* tf = trs + f * nn;
+                        double wp, li, tr;
+                        if (ax == 0) { wp = 1.0 * wb * wc; li = l_in[a]; tr = tf[bc]; }
+                        else if (ax == 1) { wp = 1.0 * wa * wc; li = l_in[b]; tr = tf[a * n + c]; }
+                        else { wp = 1.0 * wa * wb; li = l_in[c]; tr = tf[a * n + b]; }
+                        v += coef * li * wp * tr;
+                    }
+                }
+                y[e * nd + I] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------- vector kernels
 // partial[b * k + i] = sum over block b's entries of V_i . w   (i < k), the
 // blocks striding over the vector.  Eight V_i per pass, so w is read
@@ -251,11 +376,19 @@ __global__ void k_axpby(double* dst, const double* src, double a, const double* 
 template <class X>
 static hipError_t operator_any(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
                                const double* params, const int32_t* nbr, const double* blocks,
-                               const double* strc, const X* x, double* y) {
+                               const double* strc, const X* x, double* y, bool cols) {
     const int nn = n * n;
     const int nd = dim == 2 ? nn : nn * n;
     if (nd > 16 * 256) return hipErrorInvalidValue;
     const double* sc = blocks ? nullptr : strc;
+    if (cols && sc && dim == 3 && n <= 16) {
+        const int epw = 256 / nn;
+        const int64_t wg = (E + epw - 1) / epw;
+        const int grid3 = (int)(wg < 65536 ? wg : 65536);
+        const size_t lds3 = (size_t)epw * (nd + 9 * nn) * sizeof(double);
+        hipLaunchKernelGGL(k_operator3_cols<X>, dim3(grid3), dim3(256), lds3, s, E, n, tab, params, nbr, sc, x, y);
+        return hipGetLastError();
+    }
     size_t lds = ((sc ? 1 : 2) * nd + 3 * nn + nd / n) * sizeof(double);
     int grid = (int)(E < 65536 ? E : 65536);
     hipLaunchKernelGGL(k_operator<X>, dim3(grid), dim3(256), lds, s, E, dim, n, tab, params, nbr, blocks,
@@ -265,14 +398,14 @@ static hipError_t operator_any(hipStream_t s, int64_t E, int dim, int n, const T
 
 hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
                            const double* params, const int32_t* nbr, const double* blocks,
-                           const double* strc, const double* x, double* y) {
-    return operator_any(s, E, dim, n, tab, params, nbr, blocks, strc, x, y);
+                           const double* strc, const double* x, double* y, bool cols) {
+    return operator_any(s, E, dim, n, tab, params, nbr, blocks, strc, x, y, cols);
 }
 
 hipError_t launch_operator(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
                            const double* params, const int32_t* nbr, const double* blocks,
-                           const double* strc, const float* x, double* y) {
-    return operator_any(s, E, dim, n, tab, params, nbr, blocks, strc, x, y);
+                           const double* strc, const float* x, double* y, bool cols) {
+    return operator_any(s, E, dim, n, tab, params, nbr, blocks, strc, x, y, cols);
 }
 
 // the matrix-free elements' structure: per element the mass tensor (n^d) and

@@ -105,3 +105,32 @@ def test_fgmres_iterations_and_solution(ctx, dim, n, mesh, seed):
     assert abs(res["ksvd64"] - it_k) <= 1
     assert abs(res["bj"] - it_j) <= 1
     assert res["ksvd32"] <= res["ksvd64"] + 1
+
+
+@pytest.mark.parametrize("n,mesh,seed", [(16, 3, 35), (8, 3, 36), (5, 4, 37), (2, 5, 38), (11, 2, 39)])
+def test_operator_column_kernel_matches_entry_kernel(ctx, n, mesh, seed):
+    """The column-per-thread kernel of the matrix-free 3D operator forms every
+    entry from the same terms in the same order as the one-entry-per-thread
+    kernel; only the fusing of multiply-adds may differ, so the two agree to
+    rounding: relative 2-norm difference <= 1e-14, every entry within
+    1e-13 of the largest |y| (several elements per workgroup for n <= 8, a
+    partly filled workgroup for n = 5 and 11, upwind faces on a periodic
+    mesh).  The oracle comparison of test_operator_matches_oracle runs on
+    this kernel too."""
+    import torch
+
+    from paper_1704_04549_amd import kp
+    from tests.gpu_util import batch, to_dev
+    print(f"operator columns n={n} mesh={mesh}", flush=True)
+    E = mesh ** 3
+    params, nbr = synth.mesh_params(mesh, 3, seed)
+    b = batch(params, 3, n, nbr=nbr)
+    x = to_dev(np.random.default_rng(seed).standard_normal((E, n ** 3)))
+    y_cols = ctx.operator_apply(b, x)
+    ctx.set_option(kp.KP_OPT_OPERATOR_COLS, 0)
+    y_entry = ctx.operator_apply(b, x)
+    ctx.set_option(kp.KP_OPT_OPERATOR_COLS, 1)
+    torch.cuda.synchronize()
+    d = (y_cols - y_entry).abs()
+    assert float(torch.linalg.norm(y_cols - y_entry) / torch.linalg.norm(y_entry)) <= 1e-14
+    assert float(d.max()) <= 1e-13 * float(y_entry.abs().max())
