@@ -1412,6 +1412,7 @@ KP_HD void contract_axis(const Team& tm, int dim, int n, int ax, const TT* M, co
         const int hi = idx / (stride * n);
         const int base = hi * stride * n + lo;
         T acc = (T)0;
+#pragma unroll 8
         for (int k = 0; k < n; ++k) acc += (T)ldt(M, i * n + k) * rnd(X[base + k * stride]);
         out[idx] = acc;
     }
@@ -1450,6 +1451,7 @@ KP_HD_FORCEINLINE void apply_tensor(const Team& tm, int dim, int n, const TT* ta
             for (int t = tm.tid(); t < rows; t += tm.size()) {
                 const int s = t / n, i = t % n;
                 T acc = (T)0;
+#pragma unroll 8
                 for (int k = 0; k < n; ++k) acc += (T)ldt(Nj, i * n + k) * rnd(F[s * nn + k * n + j]);
                 S[s * nn + i * n + j] = acc;
             }
@@ -1468,6 +1470,7 @@ KP_HD_FORCEINLINE void apply_tensor(const Team& tm, int dim, int n, const TT* ta
             for (int t = tm.tid(); t < rows; t += tm.size()) {
                 const int s = t / n, i = t % n;
                 T a1 = (T)0, a2 = (T)0;
+#pragma unroll 8
                 for (int k = 0; k < n; ++k) {
                     const T tk = (T)ldt(T1, i * n + k);
                     a1 += tk * rnd(F[s * nn + k * n + j1]);
@@ -1481,6 +1484,7 @@ KP_HD_FORCEINLINE void apply_tensor(const Team& tm, int dim, int n, const TT* ta
             for (int t = tm.tid(); t < 2 * rows; t += tm.size()) {
                 const int s = t / (2 * n), h = (t / n) % 2, i = t % n;
                 T acc = (T)0;
+#pragma unroll 8
                 for (int k = 0; k < n; ++k) acc += (T)ldt(Nj, i * n + k) * rnd(Hs[s * 2 * n + h * n + k]);
                 S[s * nn + i * n + (h ? j : j1)] = acc;
             }
