@@ -389,7 +389,7 @@ kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, con
     if (N == 0) return KP_OK;
     // workspace: V (m+1) N, Z m N (FP64, or FP32 with z32), w N, r N,
     // partial, h (2 (m+2)), y (m)
-    const size_t vec = (size_t)N;
+    const size_t vec = (size_t)N + (N & 1);  // vector stride: even, so every vector is 16-byte aligned
     const size_t part = (size_t)kVecBlocks * (m + 2);
     const size_t zd = z32 ? ((size_t)m * vec + 1) / 2 : (size_t)m * vec;  // Z in doubles
     const size_t need = ((m + 3) * vec + zd + part + 3 * (size_t)(m + 2)) * sizeof(double);

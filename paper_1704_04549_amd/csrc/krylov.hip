@@ -294,6 +294,12 @@ __global__ void __launch_bounds__(256) k_mdot_partial(const double* V, int64_t l
                     if (q < kk) s[q] += v[q * ldv + t] * wt;
             }
         }
+        if (PAIR && (N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            const double wt = w[N - 1];
+#pragma unroll
+            for (int q = 0; q < kG; ++q)
+                if (q < kk) s[q] += v[q * ldv + N - 1] * wt;
+        }
 #pragma unroll
         for (int q = 0; q < kG; ++q)
             if (q < kk) {
@@ -329,7 +335,8 @@ __global__ void __launch_bounds__(256) k_mdot_reduce(const double* partial, int 
     }
 }
 
-// w -= sum_i h[i] V_i (PAIR as for k_mdot_partial)
+// w -= sum_i h[i] V_i (PAIR as for k_mdot_partial, the last entry of an odd N
+// by thread 0 of block 0)
 template <bool PAIR>
 __global__ void k_mgs_update(const double* V, int64_t ldv, int k, const double* h, double* w,
                              int64_t N) {
@@ -350,6 +357,11 @@ __global__ void k_mgs_update(const double* V, int64_t ldv, int k, const double* 
             for (int i = 0; i < k; ++i) s -= h[i] * V[i * ldv + t];
             w[t] = s;
         }
+    }
+    if (PAIR && (N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = w[N - 1];
+        for (int i = 0; i < k; ++i) s -= h[i] * V[i * ldv + N - 1];
+        w[N - 1] = s;
     }
 }
 
@@ -447,7 +459,7 @@ int vec_grid(int64_t N) {
 
 // two entries per thread and 16-byte loads where every vector allows them
 static bool pairs_ok(const double* V, int64_t ldv, int k, const double* w, int64_t N) {
-    return N % 2 == 0 && (k <= 1 || ldv % 2 == 0) && ((uintptr_t)V % 16) == 0 && ((uintptr_t)w % 16) == 0;
+    return N >= 2 && (k <= 1 || ldv % 2 == 0) && ((uintptr_t)V % 16) == 0 && ((uintptr_t)w % 16) == 0;
 }
 
 hipError_t launch_mdot(hipStream_t s, const double* V, int64_t ldv, int k, const double* w,
