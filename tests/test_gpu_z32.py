@@ -70,17 +70,22 @@ def test_apply_z32_refuses_fp64_and_rank3(ctx):
     assert ei.value.status == kp.KP_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("dim,n,mesh,restart,prec", [(3, 16, 3, 10, "fp32"), (2, 8, 12, 6, "bf16x3"),
-                                                     (3, 6, 5, 8, "bf16")])
-def test_fgmres_z32_basis_identical(ctx, dim, n, mesh, restart, prec):
+@pytest.mark.parametrize("dim,n,mesh,restart,prec,explicit", [(3, 16, 3, 10, "fp32", False),
+                                                              (2, 8, 12, 6, "bf16x3", False),
+                                                              (3, 6, 5, 8, "bf16", False),
+                                                              (2, 8, 10, 7, "fp32", True)])
+def test_fgmres_z32_basis_identical(ctx, dim, n, mesh, restart, prec, explicit):
     import torch
 
     from paper_1704_04549_amd import kp
     from tests.gpu_util import batch, to_dev
-    print(f"z32 fgmres dim={dim} n={n} mesh={mesh} restart={restart} {prec}", flush=True)
+    print(f"z32 fgmres dim={dim} n={n} mesh={mesh} restart={restart} {prec} explicit={explicit}", flush=True)
     params, nbr = synth.mesh_params(mesh, dim, 61)
     E = mesh ** dim
     b = batch(params, dim, n, nbr=nbr)
+    if explicit:
+        # the operator reads the explicit blocks (and the FP32 basis through them)
+        b = batch(params, dim, n, blocks=ctx.build_blocks(b), nbr=nbr)
     rhs = to_dev(np.random.default_rng(8).standard_normal((E, n ** dim)))
     pc, _ = ctx.setup(b, 2)
     out = {}
