@@ -17,7 +17,8 @@ namespace kp {
 
 // w = P3 u for one element.  F: the six factors A1,B1,A2,B2,A3,B3 (n x n,
 // row-major); u, w: n^2 (row-major X[i][k] = x[i*n + k], so (A (x) B) x is
-// A X B^T); tmp: 3 n^2.
+// A X B^T); tmp: 3 n^2.  The inner loops are unrolled by eight so that a
+// lane's factor loads are in flight together (the summation order is kept).
 template <class Team>
 KP_HD void kron3_apply(const Team& tm, int n, const double* F, const double* u, double* w,
                        double* tmp) {
@@ -27,6 +28,7 @@ KP_HD void kron3_apply(const Team& tm, int n, const double* F, const double* u, 
         const int j = t / nn, k = (t % nn) / n, l = t % n;
         const double* B = F + (2 * j + 1) * nn;
         double s = 0.0;
+#pragma unroll 8
         for (int q = 0; q < n; ++q) s += u[k * n + q] * B[l * n + q];
         tmp[t] = s;
     }
@@ -37,6 +39,7 @@ KP_HD void kron3_apply(const Team& tm, int n, const double* F, const double* u, 
         double s = 0.0;
         for (int j = 0; j < 3; ++j) {
             const double* A = F + 2 * j * nn;
+#pragma unroll 8
             for (int k = 0; k < n; ++k) s += A[i * n + k] * tmp[j * nn + k * n + l];
         }
         w[t] = s;
