@@ -106,6 +106,7 @@ struct OpStruct2 {
         c = tm.sum(c);
         for (int k = tm.tid(); k < n; k += tm.size()) {
             double s = 0.0;
+            #pragma unroll 8
             for (int i = 0; i < n; ++i) s += x[i * n + i] * m[i * n + k];
             g[k] = s + w[k] * p1;
         }
@@ -132,6 +133,7 @@ struct OpStruct2 {
             double v = X[t] * t1;
             if (i == i2) {
                 double s = 0.0;
+                #pragma unroll 8
                 for (int k = 0; k < n; ++k) s += m[i * n + k] * d[k];
                 v += s + w[i] * t2;
             }
@@ -253,6 +255,7 @@ struct OpStruct3 {
             double v = X[t] * t1;
             if (a == a2) {
                 double s = 0.0;
+                #pragma unroll 8
                 for (int b = 0; b < n; ++b) s += G[a * n + b] * x[b * n + b];
                 v += s + p1 * mv[a] + c * mv[n + a] + w[a] * t2;
             }
@@ -273,6 +276,7 @@ struct OpStruct3 {
         c = tm.sum(c);
         for (int q = tm.tid(); q < nn; q += tm.size()) {
             double s = 0.0;
+            #pragma unroll 8
             for (int a = 0; a < n; ++a) s += x[a * n + a] * m[a * nn + q];
             g[q] = s + p1 * w[q / n] * w[q % n];
         }
@@ -778,6 +782,7 @@ KP_HD void mm(const Team& tm, int n, const double* A, const double* B, double* C
     for (int t = tm.tid(); t < n * n; t += tm.size()) {
         const int i = t / n, j = t % n;
         double s = 0.0;
+        #pragma unroll 8
         for (int k = 0; k < n; ++k) s += A[i * n + k] * B[k * n + j];
         C[t] = s;
     }
@@ -789,6 +794,7 @@ KP_HD void mtm(const Team& tm, int n, const double* A, const double* B, double* 
     for (int t = tm.tid(); t < n * n; t += tm.size()) {
         const int i = t / n, j = t % n;
         double s = 0.0;
+        #pragma unroll 8
         for (int k = 0; k < n; ++k) s += A[k * n + i] * B[k * n + j];
         C[t] = s;
     }
