@@ -65,6 +65,7 @@ __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, con
             if (I < nd) {
                 if (blocks) {
                     const double* row = blocks + (e * nd + I) * (int64_t)nd;
+                    #pragma unroll 8
                     for (int J = 0; J < nd; ++J) v += row[J] * xe[J];
                 } else {
                     v = mass[I] * xe[I];
@@ -80,6 +81,7 @@ __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, con
                         const double* Xr = Xax + ax * nn + idx[ax] * n;
                         const int base = I - idx[ax] * stride;
                         double s = 0.0;
+                        #pragma unroll 8
                         for (int k = 0; k < n; ++k) s += Xr[k] * xe[base + k * stride];
                         v += wp * s;
                     }
@@ -104,6 +106,7 @@ __global__ void __launch_bounds__(256) k_operator(int64_t E, int dim, int n, con
                     const int lo = J % stride, hi = J / stride;
                     const int base = hi * stride * n + lo;
                     double s = 0.0;
+                    #pragma unroll 8
                     for (int k = 0; k < n; ++k) s += l_out[k] * (double)xf[base + k * stride];
                     tr[J] = s;
                 }

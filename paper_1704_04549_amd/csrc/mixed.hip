@@ -188,6 +188,7 @@ __global__ void __launch_bounds__(256) k_mixed_operator(int64_t E, const MixedEl
                 const double* Xr = Xax + ax * nn + idx[ax] * n;
                 const long b0 = I - idx[ax] * stride;
                 double sacc = 0.0;
+                #pragma unroll 8
                 for (int k = 0; k < n; ++k) sacc += Xr[k] * xe[b0 + k * stride];
                 v += wp * sacc;
             }
