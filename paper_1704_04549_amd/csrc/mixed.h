@@ -27,14 +27,21 @@ struct MixedElem {
 // one per wave, each processed by its wave alone.
 constexpr int kMixedItemWidth = 4;
 
-// Dynamic LDS of one apply launch: three element-sized buffers per workgroup
-// item, or per wave of a wave item.  A launch above the limit is refused; a
-// (dim, n) class takes the wave mode only if it fits at FP64, so one work list
-// serves every precision.
+// Entries of the apply's third LDS buffer for one element: the Sylvester
+// sweep's 2 x 2-block right-hand sides, two n-vectors per slice (one slice in
+// 2D, n in 3D).
+inline long mixed_apply_h(int dim, int n) { return 2L * n * (dim == 3 ? n : 1); }
+
+// Dynamic LDS of one apply launch: per workgroup item the tensor, one scratch
+// tensor and the block buffer (2 block_nd + block_h entries); per wave of a
+// wave item the same for its own element (2 wave_nd + wave_h each).  A launch
+// above the limit is refused; a (dim, n) class takes the wave mode only if it
+// fits at FP64, so one work list serves every precision.
 constexpr size_t kMixedApplyLdsMax = 150 * 1024;
-inline size_t mixed_apply_lds(size_t elem_bytes, long block_nd, long wave_nd) {
-    const long need = block_nd > kMixedItemWidth * wave_nd ? block_nd : kMixedItemWidth * wave_nd;
-    return 3 * (size_t)need * elem_bytes;
+inline size_t mixed_apply_lds(size_t elem_bytes, long block_nd, long block_h, long wave_nd, long wave_h) {
+    const long blk = 2 * block_nd + block_h;
+    const long wav = kMixedItemWidth * (2 * wave_nd + wave_h);
+    return (size_t)(blk > wav ? blk : wav) * elem_bytes;
 }
 
 hipError_t launch_mixed_setup(hipStream_t s, int grid, int64_t E, const MixedElem* el, const int32_t* order,
@@ -49,7 +56,7 @@ hipError_t launch_mixed_setup_waves(hipStream_t s, int grid4, int64_t E, const M
                                     int64_t ws_stride, int64_t small_stride);
 hipError_t launch_mixed_apply(hipStream_t s, int prec, int grid, int n_items, int n_block, const int32_t* items,
                               const MixedElem* el, const void* tabs, const int8_t* kinds, const double* r,
-                              double* z, long block_nd, long wave_nd);
+                              double* z, long block_nd, long block_h, long wave_nd, long wave_h);
 hipError_t launch_mixed_operator(hipStream_t s, int64_t E, const MixedElem* el, Tables1D* const* tabs,
                                  const double* params, const double* x, double* y, int max_n, int max_nd);
 

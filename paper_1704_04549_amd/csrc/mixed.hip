@@ -87,13 +87,14 @@ hipError_t launch_mixed_setup_waves(hipStream_t s, int grid4, int64_t E, const M
 
 // ---------------------------------------------------------------- apply
 // 256 threads.  Block items: the workgroup applies one element with the
-// tensor and two scratch tensors in LDS (3 block_nd values).  Wave items:
-// each wave applies its own element in its own quarter of LDS (3 wave_nd).
+// tensor, a scratch tensor (block_nd values each) and the sweep's block buffer
+// in LDS.  Wave items: each wave applies its own element in its own part of
+// LDS (2 wave_nd + wave_h values).
 template <typename T, typename TT, class Rnd>
 __global__ void __launch_bounds__(256) k_mixed_apply(int n_items, int n_block, const int32_t* items,
                                                      const MixedElem* el, const TT* tabs, const int8_t* kinds,
                                                      const double* r, double* z, long block_nd, long wave_nd,
-                                                     Rnd rnd) {
+                                                     long wave_h, Rnd rnd) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
     T* base = (T*)lds;
@@ -118,7 +119,7 @@ __global__ void __launch_bounds__(256) k_mixed_apply(int n_items, int n_block, c
             if (e >= 0) {
                 const MixedElem d = el[e];
                 const long nd = d.dim == 2 ? (long)d.n * d.n : (long)d.n * d.n * d.n;
-                T* X = base + 3 * wave_nd * wv;
+                T* X = base + (2 * wave_nd + wave_h) * wv;
                 T* Y = X + wave_nd;
                 T* H = Y + wave_nd;
                 for (long t = tm.tid(); t < nd; t += 64) X[t] = (T)r[d.vec_off + t];
@@ -136,23 +137,24 @@ __global__ void __launch_bounds__(256) k_mixed_apply(int n_items, int n_block, c
 
 hipError_t launch_mixed_apply(hipStream_t s, int prec, int grid, int n_items, int n_block, const int32_t* items,
                               const MixedElem* el, const void* tabs, const int8_t* kinds, const double* r,
-                              double* z, long block_nd, long wave_nd) {
+                              double* z, long block_nd, long block_h, long wave_nd, long wave_h) {
     if (n_items <= 0) return hipSuccess;
-    const size_t lds = mixed_apply_lds(prec == 0 ? sizeof(double) : sizeof(float), block_nd, wave_nd);
+    const size_t lds =
+        mixed_apply_lds(prec == 0 ? sizeof(double) : sizeof(float), block_nd, block_h, wave_nd, wave_h);
     if (lds > kMixedApplyLdsMax) return hipErrorInvalidValue;
     if (prec == 0)
         hipLaunchKernelGGL((k_mixed_apply<double, double, RoundNone>), dim3(grid), dim3(256), lds, s, n_items,
-                           n_block, items, el, (const double*)tabs, kinds, r, z, block_nd, wave_nd, RoundNone());
+                           n_block, items, el, (const double*)tabs, kinds, r, z, block_nd, wave_nd, wave_h, RoundNone());
     else if (prec == 1)
         hipLaunchKernelGGL((k_mixed_apply<float, float, RoundNone>), dim3(grid), dim3(256), lds, s, n_items,
-                           n_block, items, el, (const float*)tabs, kinds, r, z, block_nd, wave_nd, RoundNone());
+                           n_block, items, el, (const float*)tabs, kinds, r, z, block_nd, wave_nd, wave_h, RoundNone());
     else if (prec == 2)
         hipLaunchKernelGGL((k_mixed_apply<float, uint16_t, RoundBf16>), dim3(grid), dim3(256), lds, s, n_items,
-                           n_block, items, el, (const uint16_t*)tabs, kinds, r, z, block_nd, wave_nd,
+                           n_block, items, el, (const uint16_t*)tabs, kinds, r, z, block_nd, wave_nd, wave_h,
                            RoundBf16());
     else
         hipLaunchKernelGGL((k_mixed_apply<float, float, RoundBf16x2>), dim3(grid), dim3(256), lds, s, n_items,
-                           n_block, items, el, (const float*)tabs, kinds, r, z, block_nd, wave_nd,
+                           n_block, items, el, (const float*)tabs, kinds, r, z, block_nd, wave_nd, wave_h,
                            RoundBf16x2());
     return hipGetLastError();
 }

@@ -47,7 +47,8 @@ struct kp_mixed_plan_s {
     std::map<std::pair<int, int>, int> mode;  // (dim, n) -> 0 workgroup, 1 wave
     int32_t* d_items = nullptr;
     int n_items = 0, n_block = 0;
-    long block_nd = 0, wave_nd = 0;
+    long block_nd = 0, wave_nd = 0;  // largest element tensor of each kind
+    long block_h = 0, wave_h = 0;    // largest sweep block buffer of each kind
     bool tuned = false;
 };
 
@@ -68,15 +69,19 @@ kp_status build_items(kp_mixed_plan p) {
     std::vector<int32_t> blk, wav;
     p->block_nd = 0;
     p->wave_nd = 0;
+    p->block_h = 0;
+    p->wave_h = 0;
     for (int64_t e = 0; e < p->E; ++e) {
         const MixedElem& d = p->h_el[e];
         const int md = p->mode[{d.dim, d.n}];
         if (md == 0) {
             blk.push_back((int32_t)e);
             p->block_nd = std::max(p->block_nd, elem_nd(d));
+            p->block_h = std::max(p->block_h, mixed_apply_h(d.dim, d.n));
         } else {
             wav.push_back((int32_t)e);
             p->wave_nd = std::max(p->wave_nd, elem_nd(d));
+            p->wave_h = std::max(p->wave_h, mixed_apply_h(d.dim, d.n));
         }
     }
     // longest first within each kind, for the tail of the persistent grid
@@ -110,7 +115,7 @@ kp_status mixed_apply_launch(kp_ctx c, kp_mixed_plan p, const void* precond, int
     const int grid = p->n_items < 65536 ? p->n_items : 65536;
     MX_HIP(launch_mixed_apply(c->stream, prec, grid, p->n_items, p->n_block, p->d_items, p->d_el,
                               table_section(p, pc, prec), (const int8_t*)(pc + p->kinds), r, z, p->block_nd,
-                              p->wave_nd));
+                              p->block_h, p->wave_nd, p->wave_h));
     return KP_OK;
 }
 
@@ -335,15 +340,19 @@ kp_status kp_mixed_autotune(kp_ctx c, kp_mixed_plan p, const void* precond, int3
         for (int md = 0; md < 2 && st == KP_OK; ++md) {
             // a work list of this class only
             std::vector<int32_t> items;
-            long nd = 0;
+            long nd = 0, h = 0;
             std::vector<int32_t> members;
             for (int64_t e = 0; e < p->E; ++e)
                 if (p->h_el[e].dim == kv.first.first && p->h_el[e].n == kv.first.second) {
                     members.push_back((int32_t)e);
                     nd = elem_nd(p->h_el[e]);
+                    h = mixed_apply_h(p->h_el[e].dim, p->h_el[e].n);
                 }
-            // the wave mode holds four elements per workgroup: only where they fit at FP64
-            if (md == 1 && mixed_apply_lds(sizeof(double), 0, nd) > kMixedApplyLdsMax) break;
+            // the wave mode holds four elements per workgroup: only for classes
+            // whose four elements fit at FP64 with three full tensors each, so
+            // that the wave part of a launch stays at or below the size of its
+            // largest workgroup elements (n <= 40 in 2D, n <= 11 in 3D)
+            if (md == 1 && 3 * kMixedItemWidth * nd * (long)sizeof(double) > (long)kMixedApplyLdsMax) break;
             const int width = md == 0 ? 1 : kMixedItemWidth;
             const int nit = (int)((members.size() + width - 1) / width);
             items.assign((size_t)nit * kMixedItemWidth, -1);
@@ -362,7 +371,8 @@ kp_status kp_mixed_autotune(kp_ctx c, kp_mixed_plan p, const void* precond, int3
                 hipEventRecord(e0, c->stream);
                 if (launch_mixed_apply(c->stream, prec, grid, nit, md == 0 ? nit : 0, d_items, p->d_el,
                                        table_section(p, pc, prec), (const int8_t*)(pc + p->kinds), r, z,
-                                       md == 0 ? nd : 0, md == 0 ? 0 : nd) != hipSuccess)
+                                       md == 0 ? nd : 0, md == 0 ? h : 0, md == 0 ? 0 : nd, md == 0 ? 0 : h) !=
+                                    hipSuccess)
                     st = KP_ERR_HIP;
                 hipEventRecord(e1, c->stream);
                 hipEventSynchronize(e1);
