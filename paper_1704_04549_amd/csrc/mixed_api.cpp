@@ -43,6 +43,13 @@ struct kp_mixed_plan_s {
     };
     std::vector<Class> classes;
     int32_t* d_cls = nullptr;
+    // side streams (default priority) over which the classes' table kernels
+    // run concurrently, and the events that fork them from and join them back
+    // to the context's stream; created at the first setup
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr, join[kSide] = {};
+    bool side_ready = false;
     // apply work list and its launch shape
     std::map<std::pair<int, int>, int> mode;  // (dim, n) -> 0 workgroup, 1 wave
     int32_t* d_items = nullptr;
@@ -257,6 +264,11 @@ kp_status kp_mixed_plan_destroy(kp_mixed_plan p) {
     if (p->d_cls) hipFree(p->d_cls);
     if (p->d_tabs) hipFree(p->d_tabs);
     if (p->d_items) hipFree(p->d_items);
+    for (int i = 0; i < kp_mixed_plan_s::kSide; ++i) {
+        if (p->side[i]) hipStreamDestroy(p->side[i]);
+        if (p->join[i]) hipEventDestroy(p->join[i]);
+    }
+    if (p->fork) hipEventDestroy(p->fork);
     delete p;
     return KP_OK;
 }
@@ -290,11 +302,41 @@ kp_status kp_mixed_setup(kp_ctx c, kp_mixed_plan p, const double* params, void* 
                                     (int32_t*)(pc + p->status), (double*)c->ws, p->ws_stride,
                                     (int64_t)p->small_wave));
     // the tables one (dim, n) class at a time, each in the launch shape of
-    // a uniform batch of that class
-    for (const auto& k : p->classes)
-        MX_HIP(launch_form_tables_list(c->stream, k.count, p->d_cls + k.start, p->d_el, k.dim, k.n,
+    // a uniform batch of that class.  A class fills a fraction of the chip,
+    // so the classes are spread over the side streams and run concurrently:
+    // they read the factors and write the tables, kinds and status entries
+    // of their own elements only.
+    if (!p->side_ready) {
+        for (int i = 0; i < kp_mixed_plan_s::kSide; ++i) {
+            MX_HIP(hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking));
+            MX_HIP(hipEventCreateWithFlags(&p->join[i], hipEventDisableTiming));
+        }
+        MX_HIP(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
+        p->side_ready = true;
+    }
+    MX_HIP(hipEventRecord(p->fork, c->stream));
+    for (int i = 0; i < kp_mixed_plan_s::kSide; ++i) MX_HIP(hipStreamWaitEvent(p->side[i], p->fork, 0));
+    // most expensive class first (count n^3), each on the least loaded stream
+    std::vector<size_t> by_cost(p->classes.size());
+    for (size_t k = 0; k < by_cost.size(); ++k) by_cost[k] = k;
+    auto cost = [&](size_t k) {
+        const double n = p->classes[k].n;
+        return (double)p->classes[k].count * n * n * n;
+    };
+    std::stable_sort(by_cost.begin(), by_cost.end(), [&](size_t a, size_t b) { return cost(a) > cost(b); });
+    double load[kp_mixed_plan_s::kSide] = {};
+    for (size_t k : by_cost) {
+        const auto& cl = p->classes[k];
+        const int i = (int)(std::min_element(load, load + kp_mixed_plan_s::kSide) - load);
+        load[i] += cost(k);
+        MX_HIP(launch_form_tables_list(p->side[i], cl.count, p->d_cls + cl.start, p->d_el, cl.dim, cl.n,
                                        (const double*)(pc + p->factors), (double*)(pc + p->t64),
                                        (int8_t*)(pc + p->kinds), (int32_t*)(pc + p->status)));
+    }
+    for (int i = 0; i < kp_mixed_plan_s::kSide; ++i) {
+        MX_HIP(hipEventRecord(p->join[i], p->side[i]));
+        MX_HIP(hipStreamWaitEvent(c->stream, p->join[i], 0));
+    }
     MX_HIP(launch_cast_tables(c->stream, p->tab_total, (const double*)(pc + p->t64), (float*)(pc + p->t32),
                               (uint16_t*)(pc + p->thi), (uint16_t*)(pc + p->tlo), (float*)(pc + p->t2)));
     if (elem_status)
