@@ -263,7 +263,12 @@ kp_status kp_mixed_plan_destroy(kp_mixed_plan plan);
 /* Packed vector length (sum of n_e^d_e) and preconditioner bytes. */
 kp_status kp_mixed_plan_info(kp_mixed_plan plan, int64_t* vec_len_h, size_t* precond_bytes_h);
 
-/* Setup of every element (Alg. 5 / Alg. 7 with its own n); elem_status [E] or NULL. */
+/* Setup of every element (Alg. 5 / Alg. 7 with its own n); elem_status [E] or NULL.
+ * Ordered on ctx's stream as a whole: the table kernels of the (dim, n)
+ * classes run concurrently on three side streams that the plan owns (created
+ * at the first setup, default priority, destroyed with the plan), forked from
+ * and joined back to ctx's stream with events.  Calls on one plan must not
+ * overlap. */
 kp_status kp_mixed_setup(kp_ctx ctx, kp_mixed_plan plan, const double* params, void* precond,
                          int32_t* elem_status);
 
