@@ -172,3 +172,31 @@ def test_mixed_fgmres_matches_oracle(ctx):
     assert abs(res["fp64"] - it_ref) <= 1
     assert res["fp32"] <= res["fp64"] + 1
     plan.close()
+
+
+def test_mixed_setup_concurrent_classes_deterministic(ctx):
+    """The table kernels of the (dim, n) classes run concurrently on the plan's
+    side streams and are joined back to the context's stream: a setup read
+    right after it on the context's stream (no device-wide sync) holds exactly
+    the bytes of a setup read after a full synchronisation, and repeated
+    setups agree bit for bit."""
+    import torch
+
+    from paper_1704_04549_amd import kp
+    from tests.gpu_util import to_dev
+    dims, ns, recs = mixed_case(11)
+    print(f"mixed E={len(dims)} classes={len(set(zip(dims.tolist(), ns.tolist())))}", flush=True)
+    plan = kp.MixedPlan(ctx, dims, ns, to_dev(recs))
+    dev = ctx.device
+    ref = torch.zeros(plan.precond_bytes, dtype=torch.uint8, device=dev)
+    st = torch.empty(plan.E, dtype=torch.int32, device=dev)
+    plan.setup(ref, st)
+    torch.cuda.synchronize()
+    ref_h = ref.cpu()
+    assert int(st.abs().sum()) == 0
+    for rep in range(3):
+        buf = torch.zeros(plan.precond_bytes, dtype=torch.uint8, device=dev)
+        plan.setup(buf, st)
+        got = buf.to("cpu")  # ordered on the context's stream only
+        assert torch.equal(got, ref_h), rep
+    plan.close()
