@@ -728,11 +728,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8
         transpose_tg<P>(R, M, g, c, w);    // (c, a, b)
         contract_reg<P, true>(x.fR1, R);   // R1 on c: (c, a, b) -> (a, c, b)
 
+        // z is written once and read only by a later kernel: streaming
+        // (non-temporal) stores keep it from taking L2 lines from the loads
+        // of the items in flight
         Z* zw = z + it * 4096;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) zw[P::orow(g, v) * 256 + tile_of(s, w) * 16 + c] = (Z)R[s][v];
+            for (int v = 0; v < 4; ++v)
+                __builtin_nontemporal_store((Z)R[s][v], &zw[P::orow(g, v) * 256 + tile_of(s, w) * 16 + c]);
     }
 }
 
