@@ -657,7 +657,8 @@ __global__ void __launch_bounds__(256) k_apply_generic(int64_t E, int dim, int n
         for (long t = threadIdx.x; t < nd; t += blockDim.x) X[t] = (T)r[w * nd + t];
         __syncthreads();
         apply_tensor(tm, dim, n, tabs + e * tab_stride, kinds + e * kMaxN, X, Y, H, rnd);
-        for (long t = threadIdx.x; t < nd; t += blockDim.x) z[w * nd + t] = (Z)X[t];
+        // streaming stores: z is read only by a later kernel
+        for (long t = threadIdx.x; t < nd; t += blockDim.x) __builtin_nontemporal_store((Z)X[t], &z[w * nd + t]);
         __syncthreads();
     }
 }
