@@ -191,7 +191,7 @@ def bench_mixed(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the path is measured on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "c5_mixed":

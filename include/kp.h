@@ -305,7 +305,7 @@ kp_status kp_mixed_fgmres(kp_ctx ctx, kp_mixed_plan plan, const double* params, 
                           double* hist_h, int32_t hist_len);
 
 /* ------------------------------------------------------ learned setup
- * Not part of the paper, whose SVD setup (Sec. 4.1) stays the judge.  A small
+ * Not part of the paper, whose SVD setup (Sec. 4.1) stays the arbiter.  A small
  * MLP maps 12 features of an element record to its Kronecker factors:
  *   features: beta_x, beta_y, beta_z (0 in 2D), log10 nu, tau, alpha, sin phi,
  *     cos phi, and c = 1 + alpha sin(pi x y [z] + phi) at the reference

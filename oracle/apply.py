@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 ``dense_solve``: the plain definition z = P^{-1} r with P assembled densely
 from its factors and solved by LAPACK LU (eqs. 2d-kron-sum, 3d-simple-precond).
-This is the reference every other apply is judged against.
+This is the reference every other apply is compared against.
 
 ``SchurPrecond``: the paper's own fast route, written from Sec. 4.2 (eq.
 quad-triang) and Sec. 4.3 and Algs. 5-8.

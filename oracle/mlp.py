@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 The paper forms the factors by an SVD of the rearranged block (Sec. 4.1).
 The learned variant predicts them from the element's record and keeps the SVD
-as the judge.  Everything here is the plain FP64 definition:
+as the arbiter.  Everything here is the plain FP64 definition:
 
 features(rec, dim): 12 numbers per element
     beta_x, beta_y, beta_z (0 in 2D), log10 nu, tau, alpha, sin phi, cos phi,

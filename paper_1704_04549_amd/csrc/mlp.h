@@ -1,6 +1,6 @@
 // Learned setup: the model buffer layout and the MLP kernels' launchers.
 //
-// Network (not part of the paper; the paper's SVD stays the judge):
+// Network (not part of the paper; the paper's SVD stays the arbiter):
 //   xn = (features - x_mean) / x_std            (12 features per element)
 //   h1 = silu(W1 xn + b1), h2 = silu(W2 h1 + b2), y = W3 h2 + b3,
 //   factors = y * (per-block scale)             (3D: A1,B1,C1,B2,C2; 2D: A1,B1,A2,B2)
