@@ -307,11 +307,22 @@ kp_status kp_mixed_setup(kp_ctx c, kp_mixed_plan p, const double* params, void* 
     // they read the factors and write the tables, kinds and status entries
     // of their own elements only.
     if (!p->side_ready) {
-        for (int i = 0; i < kp_mixed_plan_s::kSide; ++i) {
-            MX_HIP(hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking));
-            MX_HIP(hipEventCreateWithFlags(&p->join[i], hipEventDisableTiming));
+        // all or nothing: a failure releases what was created
+        bool ok = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; ok && i < kp_mixed_plan_s::kSide; ++i)
+            ok = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&p->join[i], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            for (int i = 0; i < kp_mixed_plan_s::kSide; ++i) {
+                if (p->side[i]) hipStreamDestroy(p->side[i]);
+                if (p->join[i]) hipEventDestroy(p->join[i]);
+                p->side[i] = nullptr;
+                p->join[i] = nullptr;
+            }
+            if (p->fork) hipEventDestroy(p->fork);
+            p->fork = nullptr;
+            return KP_ERR_HIP;
         }
-        MX_HIP(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
         p->side_ready = true;
     }
     MX_HIP(hipEventRecord(p->fork, c->stream));
