@@ -30,12 +30,20 @@ Residuals: res(A, f) = ||A - P(f)||_F^2 by dense assembly; the Rayleigh-Ritz
 proxy of a prediction keeps only its left subspaces and completes them
 optimally (2D: U = orth[vec A1, vec A2], proxy = ||A||^2 - ||U^T R(A)||_F^2;
 3D: u = vec A1 / ||vec A1||, D = unvec(R(A)^T u), U2 = orth[vec B1, vec B2],
-proxy = ||A||^2 - ||U2^T R(D)||_F^2).  A prediction is accepted when
-res(pred) <= 1.1 * proxy and res(pred) < ||A||^2.
+proxy = ||A||^2 - ||U2^T R(D)||_F^2); it is never below the SVD's residual.
+
+Acceptance (``accept``): the SVD's factors judge.  A prediction is used
+directly when ||A - P_pred||_F <= 1.1 ||A - P_svd||_F (the rearranged
+residual within 1.1 times the SVD's), ||A - P_pred||_F < ||A||_F, and the
+spectral guard ||P_svd^{-1} P_pred - I||_2 <= 0.1 holds by a three-step power
+estimate (``guard_estimate``).
 
 Pinned by tests/test_oracle_mlp.py (central differences, sign invariance of
 P and of the loss, residual identities, proxy = SVD residual on the SVD's
-own subspaces).
+own subspaces, each acceptance branch on constructed predictions: the SVD's
+own factors, a rescaled prediction, an all-zero prediction, and a
+near-singular perturbation that keeps the Frobenius residual but fails the
+guard, whose estimate is checked against the exact norm).
 """
 from __future__ import annotations
 
@@ -186,11 +194,46 @@ def proxy_residual(A: np.ndarray, farr: np.ndarray, dim: int, n: int) -> float:
     return a2 - float(np.sum((U2.T @ R2) ** 2))
 
 
-def accept(A: np.ndarray, farr: np.ndarray, dim: int, n: int, factor: float = 1.1):
-    """Acceptance test of a predicted factor stack; returns (accepted, res, proxy).
+GUARD_STEPS = 3
 
-    A prediction that explains nothing (res >= ||A||^2) is rejected: the proxy
-    of degenerate (e.g. zero) left subspaces is ||A||^2 too."""
-    res = residual(A, farr, dim)
-    prox = proxy_residual(A, farr, dim, n)
-    return (res <= factor * prox) and (res < float(np.sum(A * A))), res, prox
+
+def guard_estimate(f_pred: dict, f_svd: dict, steps: int = GUARD_STEPS) -> float:
+    """Power estimate of ||P_svd^{-1} P_pred - I||_2 from the normalised ones
+    vector: gamma = max_k ||E v_k||, v_{k+1} = E v_k / ||E v_k||, k < steps
+    (each ||E v_k|| is a lower bound of the norm)."""
+    from .apply import dense_solve
+    Pp = precond_matrix(f_pred)
+    N = Pp.shape[0]
+    v = np.ones(N) / np.sqrt(N)
+    gamma = 0.0
+    for _ in range(steps):
+        e = dense_solve(f_svd, Pp @ v) - v
+        ne = float(np.linalg.norm(e))
+        gamma = max(gamma, ne)
+        if not ne > 0.0:
+            break
+        v = e / ne
+    return gamma
+
+
+def accept(A: np.ndarray, farr: np.ndarray, svd_farr: np.ndarray, dim: int, factor: float = 1.1,
+           guard: float = 0.1, steps: int = GUARD_STEPS):
+    """Acceptance test of a predicted factor stack against the SVD's.
+
+    The prediction is used directly only when its rearranged residual is
+    within ``factor`` of the SVD's, ||A - P_pred||_F <= factor ||A - P_svd||_F,
+    when it explains part of A (||A - P_pred||_F < ||A||_F: an all-zero
+    prediction is never taken), and when the spectral guard holds: the power
+    estimate of ||P_svd^{-1} P_pred - I||_2 (``guard_estimate``) is at most
+    ``guard``.  A Frobenius residual does not bound the spectrum of P_pred; the
+    guard does, since with ||E|| <= g < 1, P_pred^{-1} A = (I + E)^{-1}
+    P_svd^{-1} A differs from the SVD's preconditioned operator by at most
+    g / (1 - g) relatively.  Returns (accepted, res_pred, res_svd, gamma),
+    residuals as Frobenius norms."""
+    res_p = np.sqrt(residual(A, farr, dim))
+    res_s = np.sqrt(residual(A, svd_farr, dim))
+    a = float(np.linalg.norm(A))
+    frob = res_p <= factor * res_s and res_p < a
+    gamma = guard_estimate(factors_from_array(np.asarray(farr, np.float64), dim),
+                           factors_from_array(np.asarray(svd_farr, np.float64), dim), steps)
+    return bool(frob and gamma <= guard), res_p, res_s, gamma

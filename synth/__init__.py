@@ -164,3 +164,77 @@ def mixed_batch(n2d: int = 50000, n3d: int = 2000, seed: int = MIXED_SEED):
             recs.append(rec)
     return (np.asarray(dims, np.int8), np.asarray(ns, np.int16),
             np.asarray(recs, np.float64))
+
+
+QUAD_SEED = 1006
+
+
+def quad_points01(mu: int) -> np.ndarray:
+    """The mu Gauss-Legendre points of [0,1]: where a DG code evaluates the
+    flux Jacobians that a general element carries (input layout only)."""
+    xi, _ = np.polynomial.legendre.leggauss(mu)
+    return 0.5 * (xi + 1.0)
+
+
+def quad_elements(num_elems: int, dim: int, mu: int, seed: int = QUAD_SEED, tau: float = TAU) -> dict:
+    """General elements: coefficients at the mu^d quadrature points (and
+    mu^(d-1) per face) of smoothly varying, non-separable fields, as a DG
+    code's linearisation hands them over on curved elements.
+
+    Per element, drawn in order: beta (d values, U[-1,1]), log10 nu
+    (U[-3,-1]), alpha (U[0,0.5]), phi (U[0,2pi)), gamma (U[0,0.3]: velocity
+    variation), kappa (U[0,0.2]: metric variation), psi (d phases, U[0,2pi)).
+    With x the point's coordinates on [0,1]^d:
+      J(x)     = 1 + kappa sin(pi (x_0 + ... + x_{d-1}) + psi_0)
+      c(x)     = J(x) (1 + alpha sin(pi x_0 ... x_{d-1} + phi))
+      a_i(x)   = -beta_i J(x) (1 + gamma sin(pi x_{i+1 mod d} + psi_i))
+      nu(x)    = nu J(x) (1 + gamma cos(pi x_0 x_1 + psi_0))
+      g_f(x)   = max(a(x) . n_f, 0) on face f (outflow part of the upwind flux)
+    Arrays: c [E][mu^d], a [E][d][mu^d], nu [E][mu^d], g [E][2d][mu^(d-1)]
+    (C order, x slowest; on a face the remaining axes in order)."""
+    rng = np.random.default_rng(seed)
+    xq = quad_points01(mu)
+    E = num_elems
+    k = 2 * dim + 6
+    u = rng.random((E, k))
+    beta = 2.0 * u[:, 0:dim] - 1.0
+    nu0 = 10.0 ** (-3.0 + 2.0 * u[:, dim])
+    alpha = 0.5 * u[:, dim + 1]
+    phi = 2.0 * np.pi * u[:, dim + 2]
+    gamma = 0.3 * u[:, dim + 3]
+    kappa = 0.2 * u[:, dim + 4]
+    psi = 2.0 * np.pi * u[:, dim + 5:dim + 5 + dim]
+
+    def fields(X):
+        # X: list of d coordinate arrays of one shape
+        s = sum(X)
+        prod = X[0].copy()
+        for t in X[1:]:
+            prod = prod * t
+        J = 1.0 + kappa[:, None] * np.sin(np.pi * s[None] + psi[:, 0:1])
+        c = J * (1.0 + alpha[:, None] * np.sin(np.pi * prod[None] + phi[:, None]))
+        a = np.stack([-beta[:, i:i + 1] * J *
+                      (1.0 + gamma[:, None] * np.sin(np.pi * X[(i + 1) % dim][None] + psi[:, i:i + 1]))
+                      for i in range(dim)], axis=1)
+        nu = nu0[:, None] * J * (1.0 + gamma[:, None] * np.cos(np.pi * X[0][None] * X[1][None] + psi[:, 0:1]))
+        return c, a, nu
+
+    grid = np.meshgrid(*([xq] * dim), indexing="ij")
+    c, a, nu = fields([g.ravel() for g in grid])
+    g = []
+    for ax in range(dim):
+        for side in (0, 1):
+            coords = [t.ravel() for t in np.meshgrid(*([xq] * (dim - 1)), indexing="ij")] if dim > 1 else []
+            X = coords[:ax] + [np.full(mu ** (dim - 1), float(side))] + coords[ax:]
+            _, af, _ = fields(X)
+            un = af[:, ax, :] * (1.0 if side == 1 else -1.0)
+            g.append(np.maximum(un, 0.0))
+    return dict(dim=dim, mu=mu, tau=tau, c=c, a=a, nu=nu, g=np.stack(g, axis=1),
+                draws=np.concatenate([beta, nu0[:, None], alpha[:, None], phi[:, None], gamma[:, None],
+                                      kappa[:, None], psi], axis=1))
+
+
+def quad_element(q: dict, e: int, n: int) -> dict:
+    """Element e of a quad_elements batch as the oracle's element dict."""
+    return dict(dim=q["dim"], n=n, mu=q["mu"], tau=q["tau"], c=q["c"][e], a=q["a"][e], nu=q["nu"][e],
+                g=q["g"][e])

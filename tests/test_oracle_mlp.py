@@ -101,8 +101,6 @@ def test_residual_and_proxy_identities(dim, n):
         # optimally, so it never exceeds the prediction's own residual
         Fp = F + 0.05 * np.random.default_rng(5).standard_normal(F.shape) * np.abs(F).max()
         assert mlp.residual(A, Fp, dim) >= mlp.proxy_residual(A, Fp, dim, n) - 1e-12 * np.sum(A * A)
-        ok, _, _ = mlp.accept(A, F, dim, n)
-        assert ok
 
 
 def test_adam_step_closed_form():
@@ -112,3 +110,93 @@ def test_adam_step_closed_form():
     q, m, v = mlp.adam_step(p, g, np.zeros(3), np.zeros(3), 1, 0.01)
     assert np.allclose(q, p - 0.01 * g / (np.abs(g) + 1e-8))
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def orth_pair(rng, n):
+    """Two n x n matrices, orthogonal in the Frobenius inner product."""
+    X = rng.standard_normal((n, n)) + 3 * np.eye(n)
+    Y = rng.standard_normal((n, n))
+    Y -= np.sum(X * Y) / np.sum(X * X) * X
+    return X, Y
+
+
+def constructed_case(dim, n, seed, noise=0.3, cond=1e-2):
+    """A block with a known KSVD: A = P0 + N, whose rearrangement N is
+    orthogonal to P0's singular vectors on both sides, so the SVD's factors are
+    P0's; the first factor has a smallest singular value cond times its largest."""
+    from oracle.ksvd import rearrange
+    rng = np.random.default_rng(seed)
+    Uq, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Vq, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    X1 = Uq @ np.diag(np.linspace(1.0, cond, n)) @ Vq
+    if dim == 2:
+        _, X2 = orth_pair(rng, n)
+        X2 -= np.sum(X1 * X2) / np.sum(X1 * X1) * X1
+        Y1, Y2 = orth_pair(rng, n)
+        P0 = np.kron(X1, Y1) + 0.3 * np.kron(X2, Y2)
+        shape = (n, n, n, n)
+        L = np.stack([X1.ravel(), X2.ravel()], 1)
+        R = np.stack([Y1.ravel(), Y2.ravel()], 1)
+    else:
+        Y1, Y2 = orth_pair(rng, n)
+        Z1, Z2 = orth_pair(rng, n)
+        D = np.kron(Y1, Z1) + 0.3 * np.kron(Y2, Z2)
+        P0 = np.kron(X1, D)
+        shape = (n, n, n * n, n * n)
+        L = X1.ravel()[:, None]
+        R = D.ravel()[:, None]
+    R0 = rearrange(P0, *shape)
+    G = rng.standard_normal(R0.shape)
+    Ql, _ = np.linalg.qr(L)
+    Qr, _ = np.linalg.qr(R)
+    G = G - Ql @ (Ql.T @ G)
+    G = G - (G @ Qr) @ Qr.T
+    G *= noise * np.linalg.norm(R0) / np.linalg.norm(G)
+    # back from the rearranged layout (the rearrangement is a permutation)
+    N = np.zeros_like(P0)
+    idx = np.arange(P0.size).reshape(P0.shape)
+    perm = rearrange(idx, *shape).ravel()
+    N.ravel()[perm] = G.ravel()
+    A = P0 + N
+    f = ksvd3d(A, n) if dim == 3 else ksvd2d(A, n, 2)
+    return A, factor_array(f), f
+
+
+@pytest.mark.parametrize("dim,n", [(2, 5), (3, 4)])
+def test_accept_branches(dim, n):
+    from oracle.apply import dense_solve
+    A, F, f = constructed_case(dim, n, 41)
+    # the SVD reproduces the construction: the first factor is ill-conditioned
+    s0 = np.linalg.svd(F[0], compute_uv=False)
+    assert s0[-1] / s0[0] == pytest.approx(1e-2, rel=1e-6)
+    # the SVD's own factors: equal residuals, E = 0
+    ok, rp, rs, g = mlp.accept(A, F, F, dim)
+    assert ok and rp == pytest.approx(rs, rel=1e-12) and g <= 1e-12
+    assert rs == pytest.approx(0.3 * np.linalg.norm(A - 0.0 * A) / np.sqrt(1.09), rel=0.2)
+    # a mild perturbation is taken
+    Fm = F * (1.0 + 1e-5 * np.random.default_rng(2).standard_normal(F.shape))
+    ok, rp, rs, g = mlp.accept(A, Fm, F, dim)
+    assert ok and rp <= 1.1 * rs and g <= 0.1
+    # rescaled prediction: the residual grows past 1.1 x the SVD's
+    Fs = F.copy()
+    Fs[0] *= 0.5
+    ok, rp, rs, g = mlp.accept(A, Fs, F, dim)
+    assert not ok and rp > 1.1 * rs
+    # all-zero prediction: explains nothing
+    ok, rp, rs, g = mlp.accept(A, np.zeros_like(F), F, dim)
+    assert not ok and rp == pytest.approx(np.linalg.norm(A), rel=1e-14)
+    # near-singular prediction: remove (1 - 1e-6) of the smallest singular
+    # direction of the first factor.  The Frobenius change is 1% of ||A||,
+    # far inside the 1.1 x bar, but P_pred is nearly singular: the guard
+    # rejects it
+    U, s, Vt = np.linalg.svd(F[0])
+    Fn = F.copy()
+    Fn[0] = F[0] - (1.0 - 1e-6) * s[-1] * np.outer(U[:, -1], Vt[-1])
+    ok, rp, rs, g = mlp.accept(A, Fn, F, dim)
+    assert rp <= 1.1 * rs, (rp, rs)
+    assert not ok and g > 0.1
+    # the estimate is a lower bound of the exact norm, and of its order here
+    Pp = precond_matrix(factors_from_array(Fn, dim))
+    E = np.stack([dense_solve(f, Pp[:, k]) for k in range(Pp.shape[0])], axis=1) - np.eye(Pp.shape[0])
+    exact = np.linalg.norm(E, 2)
+    assert g <= exact * (1 + 1e-9) and g >= 0.2 * exact
