@@ -13,8 +13,9 @@
  * ---------------------------------------
  * - All array arguments are DEVICE pointers unless the name ends in _h.
  * - The caller owns every buffer it passes; the library owns only the
- *   workspace held by a kp_ctx (allocated on first need, grown on demand,
- *   freed by kp_destroy).
+ *   workspace held by a kp_ctx (the 1D tables of every n, built by kp_create;
+ *   the rest allocated on first need, grown on demand, freed by kp_destroy)
+ *   and the static scratch array of kp_setup_noalloc.
  * - Work is enqueued on the context's HIP stream; only kp_fgmres and
  *   kp_blockjacobi_exact synchronise (kp_fgmres once per Arnoldi step to read
  *   the Givens residual, kp_blockjacobi_exact never except on error).
@@ -176,6 +177,22 @@ kp_status kp_build_blocks(kp_ctx ctx, const kp_batch* b, double* out);
  * precond: kp_precond_bytes bytes.  elem_status: [E] int32, or NULL. */
 kp_status kp_setup(kp_ctx ctx, const kp_batch* b, int32_t rank, int32_t mode,
                    void* precond, int32_t* elem_status);
+
+/* kp_setup without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  SVD mode only; same arguments, outputs and per-element status
+ * as kp_setup(ctx, b, rank, KP_SETUP_SVD, precond, elem_status), and the same
+ * preconditioner bytes.  The Lanczos workspace lives in a static device array
+ * of 128 MiB per device (held until the process ends); the 1D tables were
+ * built by kp_create.  Batches whose per-element workspace needs more than a
+ * quarter of that array (four slots) return KP_ERR_UNSUPPORTED; a batch with
+ * fewer slots than kp_setup would use runs with fewer workgroups.  Every call
+ * on one device shares the array: calls that overlap in time on one device
+ * (two streams, two contexts, two threads) race and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero.  KP_ERR_HIP if the
+ * array's device address could not be resolved at kp_create. */
+kp_status kp_setup_noalloc(kp_ctx ctx, const kp_batch* b, int32_t rank, void* precond,
+                           int32_t* elem_status);
 
 /* Build only the apply tables from given Kronecker factors
  * (factors: [E][nf][n][n] FP64, 2D rank r: A1,B1,A2,B2,...; 3D: A1,B1,C1,B2,C2). */

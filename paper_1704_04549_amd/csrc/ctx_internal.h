@@ -42,6 +42,9 @@ struct kp_ctx_s {
     hipStream_t cap_stream = nullptr;
     double* pinned = nullptr;
     size_t pinned_doubles = 0;
+    // device address of the allocation-free setup's scratch array on this
+    // context's device (kp_setup_noalloc), or NULL if it could not be resolved
+    double* scratch = nullptr;
 };
 
 #define KP_HIP(call)                                   \

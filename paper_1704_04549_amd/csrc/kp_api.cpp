@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -18,6 +19,33 @@
 #include "ctx_internal.h"
 
 using namespace kp;
+
+// Scratch of the allocation-free setup (kp_setup_noalloc): the Lanczos
+// workspace slots of the setup kernels, 128 MiB on every device the library
+// runs on, held until the process ends.  Host code never passes the array's
+// name to a kernel: kp_create resolves its device address once per device
+// (hipGetSymbolAddress, with that device current) and every use goes through
+// that address.
+constexpr size_t kNoAllocScratchDoubles = (size_t)16 * 1024 * 1024;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+constexpr int kMaxDevices = 64;
+static double* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// device address of `scratch` on the current device `device` (resolved once)
+static double* scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        double* ptr = nullptr;
+        if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_ptr[device];
+}
 
 extern "C" {
 
@@ -50,6 +78,16 @@ kp_status kp_create(kp_ctx* ctx, int device, void* stream) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cus = prop.multiProcessorCount;
+    // the 1D tables of every supported n, so that no later call allocates them
+    for (int n = 2; n <= kMaxN; ++n) {
+        const Tables1D* T;
+        kp_status st = get_tables(c, n, &T);
+        if (st != KP_OK) {
+            kp_destroy(c);
+            return st;
+        }
+    }
+    c->scratch = scratch_address(device);
     *ctx = c;
     return KP_OK;
 }
@@ -191,6 +229,38 @@ kp_status kp_setup(kp_ctx c, const kp_batch* b, int32_t rank, int32_t mode, void
                             factors, sigma, status, (double*)c->ws, wsd, skip,
                             direct ? KP_ELEM_LEARNED_REJECTED : 0));
     }
+    if ((st = finish_tables(c, b, rank, pc, L)) != KP_OK) return st;
+    return copy_status(c, b, pc, L, elem_status);
+}
+
+kp_status kp_setup_noalloc(kp_ctx c, const kp_batch* b, int32_t rank, void* precond,
+                           int32_t* elem_status) {
+    if (!c) return KP_ERR_ARG;
+    kp_status st = check_batch(b);
+    if (st != KP_OK) return st;
+    PcLayout L;
+    if (!pc_layout(b->dim, b->n, rank, b->num_elems, &L)) return KP_ERR_ARG;
+    if (!precond && b->num_elems > 0) return KP_ERR_ARG;
+    if (b->dim == 3 && b->blocks && b->n * b->n > 64) return KP_ERR_UNSUPPORTED;
+    const int64_t E = b->num_elems;
+    if (E == 0) return KP_OK;
+    if (!c->scratch) return KP_ERR_HIP;
+    // the tables were built by kp_create; nothing here allocates
+    const Tables1D* T = c->d_tables[b->n];
+    if (!T) return KP_ERR_HIP;
+    hipSetDevice(c->device);
+    const bool expl = b->blocks != nullptr;
+    const int64_t wsd = setup_work_doubles(b->dim, b->n, expl, rank);
+    // as many workspace slots as the scratch holds (a multiple of 4), at most
+    // the number kp_setup uses; fewer slots only serialise more elements per slot
+    int64_t cap = (int64_t)(kNoAllocScratchDoubles / (size_t)wsd) / 4 * 4;
+    if (cap < 4) return KP_ERR_UNSUPPORTED;
+    int64_t grid = setup_slots(E);
+    if (grid > cap) grid = cap;
+    char* pc = (char*)precond;
+    KP_HIP(launch_setup(c->stream, (int)grid, E, b->dim, b->n, rank, T, b->params, b->blocks, nullptr,
+                        (double*)(pc + L.factors), (double*)(pc + L.sigma), (int32_t*)(pc + L.status),
+                        c->scratch, wsd));
     if ((st = finish_tables(c, b, rank, pc, L)) != KP_OK) return st;
     return copy_status(c, b, pc, L, elem_status);
 }

@@ -58,6 +58,7 @@ def lib() -> ctypes.CDLL:
             "kp_precond_bytes": ([i32, i32, i32, i64], ctypes.c_size_t),
             "kp_build_blocks": ([vp, bp, vp], ctypes.c_int),
             "kp_setup": ([vp, bp, i32, i32, vp, vp], ctypes.c_int),
+            "kp_setup_noalloc": ([vp, bp, i32, vp, vp], ctypes.c_int),
             "kp_setup_from_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_get_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_apply": ([vp, bp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
@@ -190,6 +191,13 @@ class Ctx:
             status = torch.empty(b.num_elems, dtype=torch.int32, device=self.device)
         _check(lib().kp_setup(self.h, ctypes.byref(b.c), rank, mode, _ptr(precond), _ptr(status)),
                "kp_setup")
+        return precond, status
+
+    def setup_noalloc(self, b: Batch, rank: int, precond: torch.Tensor, status: torch.Tensor = None):
+        """kp_setup_noalloc: the caller passes the preconditioner buffer (and the
+        status array, or None); the library allocates nothing."""
+        _check(lib().kp_setup_noalloc(self.h, ctypes.byref(b.c), rank, _ptr(precond), _ptr(status)),
+               "kp_setup_noalloc")
         return precond, status
 
     def setup_from_factors(self, b: Batch, rank: int, factors: torch.Tensor, precond=None, status=None):
