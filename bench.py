@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c4_3d_p15")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "bf16x3", "fp64"])
+    ap.add_argument("--setup", default="svd", choices=["svd", "learned"],
+                    help="learned: the MLP (12 -> 256 -> 256 -> 5 n^2, trained on 20000 generated "
+                         "elements before the timed region) predicts the factors, the SVD judges")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU oracle sample: elements are added until this much time is spent")
@@ -246,6 +249,36 @@ def apply_flops(dim, n):
     return 14 * n ** 3 if dim == 2 else 16 * n ** 4
 
 
+def train_learned(ctx, dim, n, hidden=256, num_train=20000, epochs=60):
+    """The learned setup's network, trained on the GPU by the library's own
+    kernels on the SVD factors of num_train generated elements (seed 3004):
+    Kaiming initialisation (seed 5004), Adam, lr 1e-3, batch 256."""
+    import torch
+
+    import synth
+    from paper_1704_04549_amd import kp
+
+    dev = torch.device("cuda", 0)
+    tr = synth.draw_params(num_train, dim, synth.MLP_TRAIN_SEED, face=dim == 3)
+    btr = kp.Batch(torch.from_numpy(tr).to(dev), dim, n)
+    pc, _ = ctx.setup(btr, 2)
+    F, _ = ctx.get_factors(btr, 2, pc)
+    del pc
+    O = (5 if dim == 3 else 4) * n * n
+    rng = np.random.default_rng(5004)
+    I, H = 12, hidden
+    parts = [rng.standard_normal((H, I)) * np.sqrt(2.0 / I), rng.standard_normal(H) * 0.1,
+             rng.standard_normal((H, H)) * np.sqrt(2.0 / H), rng.standard_normal(H) * 0.1,
+             rng.standard_normal((O, H)) * np.sqrt(2.0 / H) * 0.1, rng.standard_normal(O) * 0.01]
+    p0 = np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+    model = ctx.mlp_create(dim, n, H, torch.from_numpy(p0).to(dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = ctx.mlp_train(model, btr, F, epochs=epochs, batch=256, lr=1e-3, seed=synth.MLP_TRAIN_SEED)
+    torch.cuda.synchronize()
+    return {"model": model, "train_s": time.perf_counter() - t0, "loss": (hist[0], hist[-1]), "keep": (btr, F)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -279,7 +312,15 @@ def main():
     b = kp.Batch(params, dim, n, nbr=nbr)
     rank = w["rank"]
     ndof = E * n ** dim
-    pc, st = ctx.setup(b, rank)
+    mode = kp.KP_SETUP_SVD
+    learned = None
+    if args.setup == "learned":
+        if rank != 2 or b.blocks is not None:
+            raise SystemExit("--setup learned needs a rank-2 workload of element records")
+        learned = train_learned(ctx, dim, n)
+        ctx.set_model(learned["model"])
+        mode = kp.KP_SETUP_LEARNED
+    pc, st = ctx.setup(b, rank, mode=mode)
     z = torch.empty_like(rhs_all)
     z32 = torch.empty(rhs_all.shape, dtype=torch.float32, device=dev)
 
@@ -304,9 +345,12 @@ def main():
         n64 = nv = args.fixed_iters
         valid = False
     else:
-        # iteration counts (outside the timed region)
-        out64 = ctx.fgmres(b, rhs, pc_kind=kp.KP_PC_KSVD, rank=rank, pc_data=pc, pc_prec="fp64",
+        # iteration counts (outside the timed region); the plain FP64
+        # preconditioner's count always with the SVD setup
+        pc64 = pc if mode == kp.KP_SETUP_SVD else ctx.setup(b, rank)[0]
+        out64 = ctx.fgmres(b, rhs, pc_kind=kp.KP_PC_KSVD, rank=rank, pc_data=pc64, pc_prec="fp64",
                            restart=30, rtol=1e-10, maxit=3000)
+        del pc64
         torch.cuda.synchronize()
         t_solve = time.perf_counter()
         outv = ctx.fgmres(b, rhs, pc_kind=kp.KP_PC_KSVD, rank=rank, pc_data=pc,
@@ -316,11 +360,11 @@ def main():
         n64, nv = out64["iters"], outv["iters"]
         valid = outv["converged"] and out64["converged"] and nv <= n64 + 1
 
-    def timed(prec, N, K, W):
+    def timed(prec, N, K, W, mode=kp.KP_SETUP_SVD):
         """W untimed steps, then K timed steps; HIP events on the library's
         stream bracket the setup and the N applies of every timed step."""
         for _ in range(W):
-            ctx.setup(b, rank, precond=pc, status=st)
+            ctx.setup(b, rank, mode=mode, precond=pc, status=st)
             for _ in range(N):
                 apply(prec)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
@@ -329,7 +373,7 @@ def main():
         t0 = time.perf_counter()
         for k in range(K):
             ev[k][0].record(stream)
-            ctx.setup(b, rank, precond=pc, status=st)
+            ctx.setup(b, rank, mode=mode, precond=pc, status=st)
             ev[k][1].record(stream)
             for _ in range(N):
                 apply(prec)
@@ -340,7 +384,12 @@ def main():
         apply_ms = sum(e1.elapsed_time(e2) for _, e1, e2 in ev) / (K * N)
         return sec, setup_ms, apply_ms
 
-    sec, t_setup, t_apply = timed(args.prec, nv, args.steps, args.warmup)
+    sec, t_setup, t_apply = timed(args.prec, nv, args.steps, args.warmup, mode)
+    accepted = float((st == 0).float().mean()) if args.setup == "learned" else None
+    if args.setup == "learned":
+        ctx.set_model(None)
+    # the plain FP64 preconditioner: SVD setup, FP64 apply, its own count
+    pc, st = ctx.setup(b, rank)
     sec64, _, t_apply64 = timed("fp64", n64, max(3, args.steps // 4), 1)
     value = ndof * nrhs * nv / sec
     value64 = ndof * nrhs * n64 / sec64
@@ -400,9 +449,12 @@ def main():
                                   if dim == 3 and not w["coupled"] else
                                   "upwind-coupled periodic mesh, rank 2 two-stage KSVD" if dim == 3 else
                                   f"rank {rank} KSVD, {nrhs} right-hand sides per element")
-                               + f", matrix-free setup, {args.prec} apply (z stored in "
+                               + f", matrix-free {'learned (MLP, SVD-judged)' if args.setup == 'learned' else 'SVD'} "
+                               f"setup, {args.prec} apply (z stored in "
                                f"{'FP32' if z_bytes == 4 else 'FP64'}), FP64 FGMRES(30) to 1e-10",
                    "elements": E, "dof": ndof, "nrhs": nrhs, "precision": args.prec,
+                   "setup": args.setup, "learned_accepted_frac": accepted,
+                   "learned_train_s": learned["train_s"] if learned else None,
                    "fgmres_iters": nv, "fgmres_iters_fp64": n64, "valid": valid,
                    "fixed_iters": args.fixed_iters or None},
         "fp64_value": value64,

@@ -128,12 +128,19 @@ kp_status kp_set_stream(kp_ctx ctx, void* stream);
  *     column of each element (the element structure formed first); the
  *     entries are formed from the same terms in the same order as by the
  *     one-entry-per-thread kernel (equal to rounding); 0 selects that
- *     kernel. */
+ *     kernel.
+ *   KP_OPT_LEARNED_GUARD (default 10000): the spectral guard of the learned
+ *     setup (kp_setup mode KP_SETUP_LEARNED) in millionths: a prediction is
+ *     used only if its estimate of ||P_svd^{-1} P_pred - I||_2 is at most
+ *     value * 1e-6 (default 0.01).  Values in [0, 1000000].  At 3D p = 15 a
+ *     guard of 0.1 lets through predictions that cost FGMRES(30) 32 more
+ *     iterations (258 against 226); 0.01 keeps the count. */
 typedef enum {
     KP_OPT_FGMRES_GRAPHS = 1,
     KP_OPT_APPLY_MFMA16 = 2,
     KP_OPT_FGMRES_Z32 = 3,
-    KP_OPT_OPERATOR_COLS = 4
+    KP_OPT_OPERATOR_COLS = 4,
+    KP_OPT_LEARNED_GUARD = 5
 } kp_option;
 kp_status kp_set_option(kp_ctx ctx, int32_t option, int64_t value);
 const char* kp_status_string(kp_status s);
@@ -156,24 +163,18 @@ kp_status kp_build_blocks(kp_ctx ctx, const kp_batch* b, double* out);
  * records), factors vec(A_j) = sqrt(sigma_j) u_j, vec(B_j) = sqrt(sigma_j) v_j,
  * then LU inverses and real Schur forms in FP64 and the apply tables.
  * mode KP_SETUP_LEARNED (rank 2, records only, a model for this dim and n
- * attached with kp_set_model): the network's factors are kept for an
- * element when ||A - P_pred||_F^2 <= 1.1 * proxy + 1e-12 ||A||_F^2 and
- * ||A - P_pred||_F^2 < ||A||_F^2 (the prediction explains part of A), where
- * the proxy is the residual of the best completion of the predicted left
- * subspaces (one Rayleigh-Ritz step, never above the prediction's own
- * residual; equal to the SVD residual on the SVD's subspaces), with both
- * computed in closed form from the record.  A rejected element runs the
- * Lanczos setup started from the predicted vec(A1) (status
- * KP_ELEM_LEARNED_REJECTED | KP_ELEM_LEARNED_WARM), and a cold Lanczos setup
- * if that does not converge (KP_ELEM_LEARNED_REJECTED).  For accepted
- * elements sigma holds the Rayleigh-Ritz estimates.  A Frobenius residual
- * close to the SVD's does not bound the spectrum of P_pred: a small change of
- * the factors can move an eigenvalue sum of the Kronecker sum onto zero, so
- * directly used factors can break a Krylov solve.
+ * attached with kp_set_model; 3D n <= 16): the network predicts every
+ * element's factors; the SVD setup runs as judge and fallback, its Lanczos
+ * started from the predicted vec(A1) (in 3D the second stage from vec(B1)),
+ * and cold where that does not converge; then kp_learned_judge with factor
+ * 1.1 and the guard of KP_OPT_LEARNED_GUARD decides per element.  Accepted elements keep the
+ * predicted factors (status 0); rejected ones keep the SVD's (status
+ * KP_ELEM_LEARNED_REJECTED, plus KP_ELEM_LEARNED_WARM when the warm-started
+ * Lanczos converged).  sigma holds the SVD's singular values either way.
+ * The judge needs the SVD, so this mode costs more than KP_SETUP_SVD.
  * mode KP_SETUP_LEARNED_WARM: every element runs the Lanczos setup started
- * from the prediction (vec A1; in 3D the second stage from vec B1), status
- * KP_ELEM_LEARNED_WARM, with the cold fallback as above (status 0); the
- * factors are the SVD's to the Lanczos tolerance.
+ * from the prediction, status KP_ELEM_LEARNED_WARM, with the cold fallback
+ * (status 0); the factors are the SVD's to the Lanczos tolerance.
  * precond: kp_precond_bytes bytes.  elem_status: [E] int32, or NULL. */
 kp_status kp_setup(kp_ctx ctx, const kp_batch* b, int32_t rank, int32_t mode,
                    void* precond, int32_t* elem_status);
@@ -193,6 +194,23 @@ kp_status kp_setup(kp_ctx ctx, const kp_batch* b, int32_t rank, int32_t mode,
  * array's device address could not be resolved at kp_create. */
 kp_status kp_setup_noalloc(kp_ctx ctx, const kp_batch* b, int32_t rank, void* precond,
                            int32_t* elem_status);
+
+/* Judge predicted rank-2 factors against the SVD's (the learned setup's
+ * acceptance test; not in the paper, which always takes the SVD, Sec. 4.1).
+ * pred_factors: [E][nf][n][n] FP64 (3D: A1,B1,C1,B2,C2; 2D: A1,B1,A2,B2);
+ * precond: a KP_SETUP_SVD preconditioner of the same batch (its factors and
+ * FP64 apply tables are the judge).  Per element, with A the record's block:
+ *   out[e][0] = ||A - P_pred||_F, out[e][1] = ||A - P_svd||_F (both in
+ *   closed form from the record), out[e][2] = ||A||_F,
+ *   out[e][3] = gamma, a three-step power estimate of
+ *   ||P_svd^{-1} P_pred - I||_2 from the normalised ones vector (a lower
+ *   bound of that norm);
+ *   accept[e] = 1 iff out0 <= factor * out1, out0 < out2 and gamma <= guard.
+ * Records only (b->blocks NULL), rank 2, 3D n <= 16.  out or accept may be
+ * NULL (not both). */
+kp_status kp_learned_judge(kp_ctx ctx, const kp_batch* b, int32_t rank, const double* pred_factors,
+                           const void* precond, double factor, double guard, double* out,
+                           int32_t* accept);
 
 /* Build only the apply tables from given Kronecker factors
  * (factors: [E][nf][n][n] FP64, 2D rank r: A1,B1,A2,B2,...; 3D: A1,B1,C1,B2,C2). */

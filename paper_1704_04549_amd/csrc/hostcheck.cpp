@@ -133,15 +133,21 @@ int kph_apply_rank3(int n, int prec, const double* F, const double* tab, const i
                        rtol, kRank3MaxIters, RoundBf16());
 }
 
-// acceptance test of predicted factors: out[0..6) = res, proxy, ||A||^2, sigma estimates
-int kph_learned_check(int dim, int n, const double* rec, const double* F, double factor, double* out) {
+// learned-setup judge of predicted factors Fp against SVD factors Fs (rank 2):
+// out[0..4) = ||A - P(Fp)||_F, ||A - P(Fs)||_F, ||A||_F, guard estimate;
+// returns 1 if accepted, 0 if not, -1 on a table failure
+int kph_learned_judge(int dim, int n, const double* rec, const double* Fp, const double* Fs, double factor,
+                      double guard, double* out) {
     Tables1D t;
     if (!make_tables(n, &t)) return -1;
+    std::vector<double> tab(tab_entries(n));
+    std::vector<int8_t> kinds(kMaxN);
+    if (kph_form_tables(dim, n, 2, Fs, tab.data(), kinds.data()) != 0) return -1;
     HostTeam tm;
-    const long nn = (long)n * n;
-    const long nd = dim == 2 ? nn : nn * n;
-    std::vector<double> mass(nd), Xax(3 * nn), work(8 * nn + n);
-    return learned_check(tm, dim, n, t, rec, F, mass.data(), Xax.data(), work.data(), factor, out) ? 1 : 0;
+    std::vector<double> work(judge_work_doubles(dim, n));
+    return learned_judge(tm, dim, n, t, rec, Fp, Fs, tab.data(), kinds.data(), work.data(), factor, guard, out)
+               ? 1
+               : 0;
 }
 
 int kph_schur(int n, const double* C, double* T, double* Q) {

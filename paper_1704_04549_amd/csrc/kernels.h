@@ -23,12 +23,16 @@ hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int 
                         const double* guess, double* factors, double* sigma, int32_t* status,
                         double* ws, int64_t ws_stride, const int32_t* skip = nullptr,
                         int32_t status_or = 0);
-// learned setup: per-element acceptance of predicted factors (in `factors`);
-// accept[e] = 1 keeps them; guess[e] = vec A1 (and vec B1 in 3D) for a warm
-// Lanczos start ([E][2 or 1][n^2])
-hipError_t launch_learned_check(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
-                                const double* params, const double* factors, double* sigma,
-                                int32_t* status, double* guess, int32_t* accept, double factor);
+// learned setup: the judge of predicted factors `pred` against the SVD's
+// (`factors` with their FP64 tables, learned.h); out [E][4] and accept [E]
+// optional; use_pred: accepted predictions replace the factors (status 0),
+// rejected elements' status gains status_rejected
+size_t learned_judge_lds(int dim, int n);
+hipError_t launch_learned_judge(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                                const double* params, const double* pred, double* factors, const double* tab64,
+                                int64_t tab_stride, const int8_t* kinds, double factor, double guard,
+                                double* out, int32_t* accept, int32_t* status, bool use_pred,
+                                int32_t status_rejected);
 // guess[e] = vec A1 (and vec B1 in 3D) of predicted factors: [E][2 or 1][n^2]; accept[e] = 0
 hipError_t launch_learned_guess(hipStream_t s, int64_t E, int dim, int n, const double* factors,
                                 double* guess, int32_t* accept);

@@ -47,6 +47,11 @@ static double* scratch_address(int device) {
     return g_scratch_ptr[device];
 }
 
+// the learned setup's acceptance: residual within 1.1x the SVD's (the guard
+// is a context option, KP_OPT_LEARNED_GUARD)
+constexpr double kLearnedFactor = 1.1;
+constexpr size_t kJudgeLdsMax = 150 * 1024;
+
 extern "C" {
 
 const char* kp_status_string(kp_status s) {
@@ -115,6 +120,10 @@ kp_status kp_set_option(kp_ctx c, int32_t option, int64_t value) {
         case KP_OPT_APPLY_MFMA16: c->use_mfma16 = value != 0; return KP_OK;
         case KP_OPT_FGMRES_Z32: c->fgmres_z32 = value != 0; return KP_OK;
         case KP_OPT_OPERATOR_COLS: c->op_cols = value != 0; return KP_OK;
+        case KP_OPT_LEARNED_GUARD:
+            if (value < 0 || value > 1000000) return KP_ERR_ARG;
+            c->learned_guard = (double)value * 1e-6;
+            return KP_OK;
     }
     return KP_ERR_ARG;
 }
@@ -178,9 +187,10 @@ kp_status kp_setup(kp_ctx c, const kp_batch* b, int32_t rank, int32_t mode, void
         return KP_ERR_ARG;
     if (b->dim == 3 && b->blocks && b->n * b->n > 64) return KP_ERR_UNSUPPORTED;
     if (mode != KP_SETUP_SVD) {
-        // a model for this (dim, n), rank 2, records only
+        // a model for this (dim, n), rank 2, records only, the judge's scratch in LDS
         if (!c->model || c->model_dim != b->dim || c->model_n != b->n) return KP_ERR_ARG;
         if (rank != 2 || b->blocks) return KP_ERR_UNSUPPORTED;
+        if (learned_judge_lds(b->dim, b->n) > kJudgeLdsMax) return KP_ERR_UNSUPPORTED;
     }
     const int64_t E = b->num_elems;
     if (E == 0) return KP_OK;
@@ -200,34 +210,37 @@ kp_status kp_setup(kp_ctx c, const kp_batch* b, int32_t rank, int32_t mode, void
         KP_HIP(launch_setup(c->stream, grid, E, b->dim, b->n, rank, T, b->params, b->blocks, nullptr,
                             factors, sigma, status, (double*)c->ws, wsd));
     } else {
-        // 1. predicted factors straight into the factor section
-        if ((st = kp_mlp_predict(c, c->model, b, KP_FP32, factors)) != KP_OK) return st;
-        // 2. acceptance test (LEARNED) or none (LEARNED_WARM); the Lanczos
-        //    starts vec A1 (and vec B1 in 3D) come from the prediction
+        // 1. predicted factors into the context's scratch
         const size_t nn = (size_t)b->n * b->n;
         const size_t gs = b->dim == 3 ? 2 : 1;
-        if ((st = ensure_ws(c, E * gs * nn * sizeof(double) + 2 * E * sizeof(int32_t) + 1024, &c->ks,
-                            &c->ks_bytes)) != KP_OK)
+        const size_t pred_d = E * L.nf * nn;
+        if ((st = ensure_ws(c, (pred_d + E * gs * nn) * sizeof(double) + 2 * E * sizeof(int32_t) + 1024,
+                            &c->ks, &c->ks_bytes)) != KP_OK)
             return st;
-        double* guess = (double*)c->ks;
+        double* pred = (double*)c->ks;
+        double* guess = pred + pred_d;
         int32_t* accept = (int32_t*)(guess + E * gs * nn);
         int32_t* skip = accept + E;
-        const bool direct = mode == KP_SETUP_LEARNED;
-        if (direct) {
-            KP_HIP(launch_learned_check(c->stream, E, b->dim, b->n, T, b->params, factors, sigma, status,
-                                        guess, accept, 1.1));
-        } else {
-            KP_HIP(launch_learned_guess(c->stream, E, b->dim, b->n, factors, guess, accept));
-        }
-        // 3. warm-started Lanczos for the elements not accepted
-        const int32_t warm_bits = (direct ? KP_ELEM_LEARNED_REJECTED : 0) | KP_ELEM_LEARNED_WARM;
+        if ((st = kp_mlp_predict(c, c->model, b, KP_FP32, pred)) != KP_OK) return st;
+        // 2. the SVD (the judge, and the fallback): Lanczos started from the
+        //    prediction (vec A1; in 3D the second stage from vec B1), then a
+        //    cold Lanczos where that did not converge
+        KP_HIP(launch_learned_guess(c->stream, E, b->dim, b->n, pred, guess, accept));
         KP_HIP(launch_setup(c->stream, grid, E, b->dim, b->n, rank, T, b->params, nullptr, guess, factors,
-                            sigma, status, (double*)c->ws, wsd, direct ? accept : nullptr, warm_bits));
-        // 4. cold SVD where the warm start did not converge
+                            sigma, status, (double*)c->ws, wsd, nullptr, KP_ELEM_LEARNED_WARM));
         KP_HIP(launch_fallback_mask(c->stream, E, accept, status, skip));
         KP_HIP(launch_setup(c->stream, grid, E, b->dim, b->n, rank, T, b->params, nullptr, nullptr,
-                            factors, sigma, status, (double*)c->ws, wsd, skip,
-                            direct ? KP_ELEM_LEARNED_REJECTED : 0));
+                            factors, sigma, status, (double*)c->ws, wsd, skip, 0));
+        if (mode == KP_SETUP_LEARNED) {
+            // 3. tables of the SVD's factors, the judge, and the tables again
+            //    (those of the accepted predictions; the other elements' factors
+            //    are unchanged, so are their tables)
+            if ((st = finish_tables(c, b, rank, pc, L)) != KP_OK) return st;
+            KP_HIP(launch_learned_judge(c->stream, E, b->dim, b->n, T, b->params, pred, factors,
+                                        (const double*)(pc + L.t64), L.ne, (const int8_t*)(pc + L.kinds),
+                                        kLearnedFactor, c->learned_guard, nullptr, nullptr, status, true,
+                                        KP_ELEM_LEARNED_REJECTED));
+        }
     }
     if ((st = finish_tables(c, b, rank, pc, L)) != KP_OK) return st;
     return copy_status(c, b, pc, L, elem_status);
@@ -263,6 +276,27 @@ kp_status kp_setup_noalloc(kp_ctx c, const kp_batch* b, int32_t rank, void* prec
                         c->scratch, wsd));
     if ((st = finish_tables(c, b, rank, pc, L)) != KP_OK) return st;
     return copy_status(c, b, pc, L, elem_status);
+}
+
+kp_status kp_learned_judge(kp_ctx c, const kp_batch* b, int32_t rank, const double* pred_factors,
+                           const void* precond, double factor, double guard, double* out, int32_t* accept) {
+    if (!c) return KP_ERR_ARG;
+    kp_status st = check_batch(b);
+    if (st != KP_OK) return st;
+    PcLayout L;
+    if (rank != 2 || !pc_layout(b->dim, b->n, rank, b->num_elems, &L)) return KP_ERR_ARG;
+    if (b->blocks) return KP_ERR_UNSUPPORTED;
+    if (learned_judge_lds(b->dim, b->n) > kJudgeLdsMax) return KP_ERR_UNSUPPORTED;
+    const int64_t E = b->num_elems;
+    if (E == 0) return KP_OK;
+    if (!pred_factors || !precond || (!out && !accept)) return KP_ERR_ARG;
+    const Tables1D* T;
+    if ((st = get_tables(c, b->n, &T)) != KP_OK) return st;
+    const char* pc = (const char*)precond;
+    KP_HIP(launch_learned_judge(c->stream, E, b->dim, b->n, T, b->params, pred_factors,
+                                (double*)(pc + L.factors), (const double*)(pc + L.t64), L.ne,
+                                (const int8_t*)(pc + L.kinds), factor, guard, out, accept, nullptr, false, 0));
+    return KP_OK;
 }
 
 kp_status kp_setup_from_factors(kp_ctx c, const kp_batch* b, int32_t rank, const double* factors,

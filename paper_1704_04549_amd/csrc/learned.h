@@ -1,18 +1,21 @@
 // Acceptance test of predicted Kronecker factors (learned setup).
 //
-// For the structured block of an element record (elem_ops.h,
-// record_structure) and a predicted factor stack F (3D: A1,B1,C1,B2,C2; 2D:
-// A1,B1,A2,B2), computes
-//   res   = ||A - P(F)||_F^2 = ||A||^2 - 2 <A, P> + ||P||^2, all in closed form
-//           from the structure (no block is formed);
-//   proxy = ||A||^2 - (energy of the best completion of F's left subspaces):
-//           2D: U = orth[vec A1, vec A2], energy = ||R(A)^T U||_F^2;
-//           3D: u = vec A1 / ||A1||, D = unvec(R(A)^T u) (a structured 2D
-//           block), U2 = orth[vec B1, vec B2], energy = ||R(D)^T U2||_F^2.
-// The proxy completes the predicted subspaces optimally, so it never exceeds
-// the optimum's residual by more than the subspaces' error, and it equals the
-// SVD residual on the SVD's own subspaces.  The prediction is accepted when
-// res <= factor * proxy + 1e-12 ||A||^2 and res < ||A||^2.
+// The SVD's factors judge a prediction.  For the structured block A of an
+// element record (elem_ops.h, record_structure), a predicted factor stack Fp
+// and the SVD's stack Fs (3D: A1,B1,C1,B2,C2; 2D: A1,B1,A2,B2) with the SVD
+// preconditioner's FP64 apply tables:
+//   res_p = ||A - P(Fp)||_F and res_s = ||A - P(Fs)||_F, in closed form from
+//           the structure (||A||^2 - 2 <A, P> + ||P||^2; no block is formed);
+//   gamma = a power estimate of ||P(Fs)^{-1} P(Fp) - I||_2: from the
+//           normalised ones vector v_0, e_k = P(Fs)^{-1} P(Fp) v_k - v_k,
+//           gamma = max_k ||e_k||, v_{k+1} = e_k / ||e_k|| (steps k < 3);
+//           every ||e_k|| is a lower bound of the norm.
+// The prediction is used when res_p <= factor * res_s (the rearranged
+// residual within factor times the SVD's, Sec. 4.1), res_p < ||A||_F (it
+// explains part of A), and gamma <= guard.  A Frobenius residual says nothing
+// about an eigenvalue sum of the Kronecker sum near zero; with
+// ||P(Fs)^{-1} P(Fp) - I|| <= g < 1 the preconditioned operators of the two
+// factor sets differ by at most g / (1 - g) relatively.
 #pragma once
 
 #include "elem_ops.h"
@@ -94,107 +97,121 @@ KP_HD double struct_inner(const Team& tm, int dim, int n, const double* m, const
            w1 * w2 * frob_dot(tm, nn, Xax + 2 * nn, M3);
 }
 
-// orthonormalise two vectors of length len in place (Gram-Schmidt twice);
-// a zero vector stays zero
+// ||A - P(F)||_F^2 of the structured block (closed form); a2 = ||A||_F^2
 template <class Team>
-KP_HD void orth2(const Team& tm, int len, double* a, double* b) {
-    double na = sqrt(frob_dot(tm, len, a, a));
-    const double ia = na > 0.0 ? 1.0 / na : 0.0;
-    for (int t = tm.tid(); t < len; t += tm.size()) a[t] *= ia;
-    tm.sync();
-    for (int pass = 0; pass < 2; ++pass) {
-        const double h = frob_dot(tm, len, a, b);
-        for (int t = tm.tid(); t < len; t += tm.size()) b[t] -= h * a[t];
-        tm.sync();
-    }
-    const double nb = sqrt(frob_dot(tm, len, b, b));
-    const double ib = nb > 0.0 ? 1.0 / nb : 0.0;
-    for (int t = tm.tid(); t < len; t += tm.size()) b[t] *= ib;
-    tm.sync();
-}
-
-// Work: mass n^d, Xax 3 n^2, then 8 n^2 + n doubles.  out[0] = res,
-// out[1] = proxy, out[2] = ||A||^2, out[3..5] = Rayleigh-Ritz singular value
-// estimates (3D: ||D||, then the two stage-2 values; 2D: the two values).
-template <class Team>
-KP_HD bool learned_check(const Team& tm, int dim, int n, const Tables1D& T, const double* rec,
-                         const double* F, double* mass, double* Xax, double* work, double factor,
-                         double* out) {
+KP_HD double struct_residual2(const Team& tm, int dim, int n, const double* m, const double* Xax,
+                              const double* w, const double* F, double a2) {
     const int nn = n * n;
-    record_structure(tm, rec, T, dim, mass, Xax);
-    const double a2 = struct_norm2(tm, dim, n, mass, Xax, T.w);
-    double res, energy;
-    double* q1 = work;
-    double* q2 = work + nn;
-    double* Wt = work + 2 * nn;
-    double* m2 = work + 3 * nn;
-    double* X2 = work + 4 * nn;
-    double* Y2 = work + 5 * nn;
-    double* dsc = work + 6 * nn;   // n^2 operator scratch
-    double s1, s2, s0 = 0.0;
     if (dim == 2) {
         const double *A1 = F, *B1 = F + nn, *A2 = F + 2 * nn, *B2 = F + 3 * nn;
-        const double ip = struct_inner(tm, 2, n, mass, Xax, T.w, A1, B1, nullptr) +
-                          struct_inner(tm, 2, n, mass, Xax, T.w, A2, B2, nullptr);
+        const double ip = struct_inner(tm, 2, n, m, Xax, w, A1, B1, nullptr) +
+                          struct_inner(tm, 2, n, m, Xax, w, A2, B2, nullptr);
         const double p2 = frob_dot(tm, nn, A1, A1) * frob_dot(tm, nn, B1, B1) +
                           frob_dot(tm, nn, A2, A2) * frob_dot(tm, nn, B2, B2) +
                           2.0 * frob_dot(tm, nn, A1, A2) * frob_dot(tm, nn, B1, B2);
-        res = a2 - 2.0 * ip + p2;
-        for (int t = tm.tid(); t < nn; t += tm.size()) {
-            q1[t] = A1[t];
-            q2[t] = A2[t];
-        }
-        tm.sync();
-        orth2(tm, nn, q1, q2);
-        OpStruct2 op{n, mass, Xax, Xax + nn, T.w, dsc, nullptr, struct2_normY2(n, Xax + nn)};
-        op.right_factor(tm, q1, 1.0, Wt);
-        s1 = sqrt(frob_dot(tm, nn, Wt, Wt));
-        op.right_factor(tm, q2, 1.0, Wt);
-        s2 = sqrt(frob_dot(tm, nn, Wt, Wt));
-    } else {
-        const double *A1 = F, *B1 = F + nn, *C1 = F + 2 * nn, *B2 = F + 3 * nn, *C2 = F + 4 * nn;
-        const double ip = struct_inner(tm, 3, n, mass, Xax, T.w, A1, B1, C1) +
-                          struct_inner(tm, 3, n, mass, Xax, T.w, A1, B2, C2);
-        const double p2 = frob_dot(tm, nn, A1, A1) *
-                          (frob_dot(tm, nn, B1, B1) * frob_dot(tm, nn, C1, C1) +
-                           frob_dot(tm, nn, B2, B2) * frob_dot(tm, nn, C2, C2) +
-                           2.0 * frob_dot(tm, nn, B1, B2) * frob_dot(tm, nn, C1, C2));
-        res = a2 - 2.0 * ip + p2;
-        // stage 1: D = R(A)^T u, u = vec A1 / ||A1||, as the structured 2D block (m2, X2, Y2)
-        const double na = sqrt(frob_dot(tm, nn, A1, A1));
-        const double ia = na > 0.0 ? 1.0 / na : 0.0;
-        for (int t = tm.tid(); t < nn; t += tm.size()) q1[t] = A1[t] * ia;
-        tm.sync();
-        OpStruct3 op{n, mass, Xax, Xax + nn, Xax + 2 * nn, T.w, dsc, 0.0};
-        op.right_factor(tm, q1, 1.0, m2, X2, Y2);
-        s0 = sqrt(struct_norm2(tm, 2, n, m2, X2, T.w));
-        // stage 2 on D with U2 = orth[vec B1, vec B2]
-        for (int t = tm.tid(); t < nn; t += tm.size()) {
-            q1[t] = B1[t];
-            q2[t] = B2[t];
-        }
-        tm.sync();
-        orth2(tm, nn, q1, q2);
-        OpStruct2 op2{n, m2, X2, Y2, T.w, dsc, nullptr, struct2_normY2(n, Y2)};
-        op2.right_factor(tm, q1, 1.0, Wt);
-        s1 = sqrt(frob_dot(tm, nn, Wt, Wt));
-        op2.right_factor(tm, q2, 1.0, Wt);
-        s2 = sqrt(frob_dot(tm, nn, Wt, Wt));
+        return a2 - 2.0 * ip + p2;
     }
-    energy = s1 * s1 + s2 * s2;
-    const double proxy = a2 - energy;
+    const double *A1 = F, *B1 = F + nn, *C1 = F + 2 * nn, *B2 = F + 3 * nn, *C2 = F + 4 * nn;
+    const double ip = struct_inner(tm, 3, n, m, Xax, w, A1, B1, C1) + struct_inner(tm, 3, n, m, Xax, w, A1, B2, C2);
+    const double p2 = frob_dot(tm, nn, A1, A1) *
+                      (frob_dot(tm, nn, B1, B1) * frob_dot(tm, nn, C1, C1) +
+                       frob_dot(tm, nn, B2, B2) * frob_dot(tm, nn, C2, C2) +
+                       2.0 * frob_dot(tm, nn, B1, B2) * frob_dot(tm, nn, C1, C2));
+    return a2 - 2.0 * ip + p2;
+}
+
+// W = P(F) V for the rank-2 stack F (2D: A1(x)B1 + A2(x)B2; 3D:
+// A1(x)(B1(x)C1 + B2(x)C2)); X, Y: n^d scratch
+template <class Team>
+KP_HD void kron_apply(const Team& tm, int dim, int n, const double* F, const double* V, double* W, double* X,
+                      double* Y) {
+    const int nn = n * n;
+    const long nd = dim == 2 ? nn : (long)nn * n;
+    RoundNone rn;
+    if (dim == 2) {
+        contract_axis(tm, 2, n, 1, F + nn, V, X, rn);
+        contract_axis(tm, 2, n, 0, F, X, W, rn);
+        contract_axis(tm, 2, n, 1, F + 3 * nn, V, X, rn);
+        contract_axis(tm, 2, n, 0, F + 2 * nn, X, Y, rn);
+        for (long t = tm.tid(); t < nd; t += tm.size()) W[t] += Y[t];
+        tm.sync();
+        return;
+    }
+    contract_axis(tm, 3, n, 2, F + 2 * nn, V, X, rn);
+    contract_axis(tm, 3, n, 1, F + nn, X, Y, rn);
+    contract_axis(tm, 3, n, 2, F + 4 * nn, V, X, rn);
+    contract_axis(tm, 3, n, 1, F + 3 * nn, X, W, rn);
+    for (long t = tm.tid(); t < nd; t += tm.size()) W[t] += Y[t];
+    tm.sync();
+    contract_axis(tm, 3, n, 0, F, W, X, rn);
+    for (long t = tm.tid(); t < nd; t += tm.size()) W[t] = X[t];
+    tm.sync();
+}
+
+constexpr int kGuardSteps = 3;
+
+// number of doubles of the judge's scratch: X, Y, V, W (n^d each), Hs (2 n^2),
+// Xax (3 n^2)
+KP_INLINE long judge_work_doubles(int dim, int n) {
+    const long nn = (long)n * n;
+    const long nd = dim == 2 ? nn : nn * n;
+    return 4 * nd + 5 * nn;
+}
+
+// out[0..4) = res_p, res_s, ||A||_F, gamma (Frobenius norms, not squares).
+// tab / kinds: the element's FP64 apply tables of the SVD factors Fs.
+template <class Team>
+KP_HD bool learned_judge(const Team& tm, int dim, int n, const Tables1D& T, const double* rec, const double* Fp,
+                         const double* Fs, const double* tab, const int8_t* kinds, double* work, double factor,
+                         double guard, double* out) {
+    const int nn = n * n;
+    const long nd = dim == 2 ? nn : (long)nn * n;
+    double* X = work;
+    double* Y = X + nd;
+    double* V = Y + nd;
+    double* W = V + nd;
+    double* Hs = W + nd;
+    double* Xax = Hs + 2 * nn;
+    record_structure(tm, rec, T, dim, X, Xax);
+    const double a2 = struct_norm2(tm, dim, n, X, Xax, T.w);
+    const double rp2 = struct_residual2(tm, dim, n, X, Xax, T.w, Fp, a2);
+    const double rs2 = struct_residual2(tm, dim, n, X, Xax, T.w, Fs, a2);
+    const double rp = sqrt(rp2 > 0.0 ? rp2 : 0.0), rs = sqrt(rs2 > 0.0 ? rs2 : 0.0), a = sqrt(a2);
+    tm.sync();
+    const double v0 = 1.0 / sqrt((double)nd);
+    for (long t = tm.tid(); t < nd; t += tm.size()) V[t] = v0;
+    tm.sync();
+    double gamma = 0.0;
+    for (int k = 0; k < kGuardSteps; ++k) {
+        kron_apply(tm, dim, n, Fp, V, W, X, Y);
+        for (long t = tm.tid(); t < nd; t += tm.size()) X[t] = W[t];
+        tm.sync();
+        apply_tensor(tm, dim, n, tab, kinds, X, Y, Hs, RoundNone());
+        double p = 0.0;
+        for (long t = tm.tid(); t < nd; t += tm.size()) {
+            const double e = X[t] - V[t];
+            X[t] = e;
+            p += e * e;
+        }
+        const double ne = sqrt(tm.sum(p));
+        if (!(ne == ne)) {   // NaN: the prediction is not finite
+            gamma = ne;
+            break;
+        }
+        gamma = ne > gamma ? ne : gamma;
+        if (!(ne > 0.0)) break;
+        const double inv = 1.0 / ne;
+        for (long t = tm.tid(); t < nd; t += tm.size()) V[t] = X[t] * inv;
+        tm.sync();
+    }
     if (tm.leader()) {
-        out[0] = res;
-        out[1] = proxy;
-        out[2] = a2;
-        out[3] = dim == 3 ? s0 : s1;
-        out[4] = dim == 3 ? s1 : s2;
-        out[5] = dim == 3 ? s2 : 0.0;
+        out[0] = rp;
+        out[1] = rs;
+        out[2] = a;
+        out[3] = gamma;
     }
     tm.sync();
-    // a prediction that explains nothing (res >= ||A||^2, e.g. all zeros, where
-    // the proxy degenerates to ||A||^2 as well) is never accepted
-    return res <= factor * proxy + 1e-12 * a2 && res < a2;
+    return rp <= factor * rs && rp < a && gamma <= guard;
 }
 
 }  // namespace kp

@@ -1,5 +1,6 @@
-// Learned setup kernels: the per-element acceptance test of predicted factors
-// (learned.h) and the mask of the cold-start fallback.
+// Learned setup kernels: the per-element judge of predicted factors against
+// the SVD's (learned.h), the Lanczos starts and the mask of the cold-start
+// fallback.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -7,54 +8,54 @@
 
 namespace kp {
 
-// One workgroup per element (persistent).  LDS: mass n^d, Xax 3 n^2, work 7 n^2.
-__global__ void __launch_bounds__(256) k_learned_check(int64_t E, int dim, int n, const Tables1D* tab,
-                                                       const double* params, const double* factors,
-                                                       double* sigma, int32_t* status, double* guess,
-                                                       int32_t* accept, double factor) {
+// One workgroup per element (persistent).  LDS: judge_work_doubles.
+// pred: predicted factors [E][nf][n][n]; factors: the SVD's factors with
+// their FP64 apply tables tab64 [E][tab_stride] and kinds [E][kMaxN].
+// out [E][4] (res_p, res_s, ||A||, gamma) and accept [E] may be NULL.  With
+// use_pred set, an accepted element's prediction replaces its factors and its
+// status becomes 0; a rejected element's status gains status_rejected.
+__global__ void __launch_bounds__(256) k_learned_judge(int64_t E, int dim, int n, const Tables1D* tab,
+                                                       const double* params, const double* pred,
+                                                       double* factors, const double* tab64, int64_t tab_stride,
+                                                       const int8_t* kinds, double factor, double guard,
+                                                       double* out, int32_t* accept, int32_t* status,
+                                                       int use_pred, int32_t status_rejected) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
-    __shared__ Tables1D T;
-    __shared__ double out[8];
+    __shared__ double res[4];
     BlockTeam tm{red};
-    {
-        const double* src = (const double*)tab;
-        double* dst = (double*)&T;
-        for (int i = threadIdx.x; i < (int)(sizeof(Tables1D) / sizeof(double)); i += blockDim.x)
-            dst[i] = src[i];
-        __syncthreads();
-    }
-    const int nn = n * n;
-    const long nd = dim == 2 ? nn : (long)nn * n;
+    const long nn = (long)n * n;
     const int nb = dim == 3 ? 5 : 4;
-    double* mass = lds;
-    double* Xax = mass + nd;
-    double* work = Xax + 3 * nn;
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
-        const double* F = factors + e * nb * nn;
-        const bool ok = learned_check(tm, dim, n, T, params + e * kRecLen, F, mass, Xax, work, factor, out);
-        // Lanczos starts: vec A1 (and vec B1 for the second stage in 3D)
-        const int gs = dim == 3 ? 2 : 1;
-        for (int t = threadIdx.x; t < gs * nn; t += blockDim.x) guess[e * gs * nn + t] = F[t];
+        const double* Fp = pred + e * nb * nn;
+        double* Fs = factors + e * nb * nn;
+        const bool ok = learned_judge(tm, dim, n, *tab, params + e * kRecLen, Fp, Fs, tab64 + e * tab_stride,
+                                      kinds + e * kMaxN, lds, factor, guard, res);
+        if (use_pred && ok)
+            for (long t = threadIdx.x; t < nb * nn; t += blockDim.x) Fs[t] = Fp[t];
         if (threadIdx.x == 0) {
-            accept[e] = ok ? 1 : 0;
-            status[e] = ok ? 0 : kStatusLearnedRejected;
-            for (int j = 0; j < 4; ++j) sigma[e * 4 + j] = j < 3 ? out[3 + j] : 0.0;
+            if (out)
+                for (int j = 0; j < 4; ++j) out[e * 4 + j] = res[j];
+            if (accept) accept[e] = ok ? 1 : 0;
+            if (use_pred && status) status[e] = ok ? 0 : (status[e] | status_rejected);
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_learned_check(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
-                                const double* params, const double* factors, double* sigma,
-                                int32_t* status, double* guess, int32_t* accept, double factor) {
+size_t learned_judge_lds(int dim, int n) { return (size_t)judge_work_doubles(dim, n) * sizeof(double); }
+
+hipError_t launch_learned_judge(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
+                                const double* params, const double* pred, double* factors, const double* tab64,
+                                int64_t tab_stride, const int8_t* kinds, double factor, double guard,
+                                double* out, int32_t* accept, int32_t* status, bool use_pred,
+                                int32_t status_rejected) {
     if (E <= 0) return hipSuccess;
-    const long nn = (long)n * n;
-    const long nd = dim == 2 ? nn : nn * n;
-    const size_t lds = (nd + 3 * nn + 7 * nn) * sizeof(double);
+    const size_t lds = learned_judge_lds(dim, n);
     const int grid = (int)(E < 65536 ? E : 65536);
-    hipLaunchKernelGGL(k_learned_check, dim3(grid), dim3(256), lds, s, E, dim, n, tab, params, factors, sigma,
-                       status, guess, accept, factor);
+    hipLaunchKernelGGL(k_learned_judge, dim3(grid), dim3(256), lds, s, E, dim, n, tab, params, pred, factors,
+                       tab64, tab_stride, kinds, factor, guard, out, accept, status, use_pred ? 1 : 0,
+                       status_rejected);
     return hipGetLastError();
 }
 

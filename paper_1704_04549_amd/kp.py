@@ -21,6 +21,7 @@ KP_FP64, KP_FP32, KP_BF16, KP_BF16X3 = 0, 1, 2, 3
 KP_SETUP_SVD, KP_SETUP_LEARNED, KP_SETUP_LEARNED_WARM = 0, 1, 2
 KP_PC_NONE, KP_PC_KSVD, KP_PC_BJ = 0, 1, 2
 KP_OPT_FGMRES_GRAPHS, KP_OPT_APPLY_MFMA16, KP_OPT_FGMRES_Z32, KP_OPT_OPERATOR_COLS = 1, 2, 3, 4
+KP_OPT_LEARNED_GUARD = 5
 ELEM_LANCZOS_NOCONV, ELEM_SINGULAR_FACTOR, ELEM_SCHUR_NOCONV, ELEM_NONFINITE = 1, 2, 4, 8
 ELEM_LEARNED_REJECTED, ELEM_LEARNED_WARM = 16, 32
 REC_LEN = 16
@@ -59,6 +60,7 @@ def lib() -> ctypes.CDLL:
             "kp_build_blocks": ([vp, bp, vp], ctypes.c_int),
             "kp_setup": ([vp, bp, i32, i32, vp, vp], ctypes.c_int),
             "kp_setup_noalloc": ([vp, bp, i32, vp, vp], ctypes.c_int),
+            "kp_learned_judge": ([vp, bp, i32, vp, vp, dbl, dbl, vp, vp], ctypes.c_int),
             "kp_setup_from_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_get_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_apply": ([vp, bp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
@@ -199,6 +201,14 @@ class Ctx:
         _check(lib().kp_setup_noalloc(self.h, ctypes.byref(b.c), rank, _ptr(precond), _ptr(status)),
                "kp_setup_noalloc")
         return precond, status
+
+    def learned_judge(self, b: Batch, pred_factors: torch.Tensor, precond, factor=1.1, guard=0.1):
+        """kp_learned_judge (rank 2): returns (out [E][4], accept [E])."""
+        out = torch.empty((b.num_elems, 4), dtype=torch.float64, device=self.device)
+        acc = torch.empty(b.num_elems, dtype=torch.int32, device=self.device)
+        _check(lib().kp_learned_judge(self.h, ctypes.byref(b.c), 2, _ptr(pred_factors), _ptr(precond),
+                                      float(factor), float(guard), _ptr(out), _ptr(acc)), "kp_learned_judge")
+        return out, acc
 
     def setup_from_factors(self, b: Batch, rank: int, factors: torch.Tensor, precond=None, status=None):
         if self.precond_bytes(b.dim, b.n, rank, 1) == 0:

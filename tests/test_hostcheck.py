@@ -210,32 +210,39 @@ def test_rank3_setup_then_apply_end_to_end(lib, n, explicit):
 
 
 @pytest.mark.parametrize("dim,n,face", [(2, 6, False), (2, 8, True), (3, 4, True), (3, 5, False)])
-def test_learned_check_matches_oracle_residual_and_proxy(lib, dim, n, face):
-    """Closed-form residual ||A - P||^2 and the Rayleigh-Ritz proxy of the
-    learned-setup acceptance test against the oracle's dense definitions, on
-    SVD factors (accepted, proxy = residual) and on perturbed factors."""
+def test_learned_judge_matches_oracle_accept(lib, dim, n, face):
+    """The learned setup's judge (closed-form residuals of the prediction and
+    of the SVD, the guard's power estimate through the SVD's apply tables)
+    against oracle.mlp.accept on the same factors: the SVD's own factors,
+    perturbations of several sizes, an all-zero prediction and a first factor
+    made nearly singular."""
     from oracle import mlp as omlp
-    params = synth.draw_params(4, dim, 41, face=face)
+    params = synth.draw_params(3, dim, 41, face=face)
     rng = np.random.default_rng(7)
-    lib.kph_learned_check.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
-                                      ctypes.c_double, ctypes.c_void_p]
+    lib.kph_learned_judge.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+    seen = set()
     for rec in params:
         A = element_block(rec, n, dim)
         fo = ksvd2d(A, n, 2) if dim == 2 else ksvd3d(A, n)
-        F = factor_array(fo)
-        for pert in (0.0, 0.02, 0.3):
-            Fp = np.ascontiguousarray(F + pert * rng.standard_normal(F.shape) * np.abs(F).max())
-            out = np.zeros(8)
-            ok = lib.kph_learned_check(dim, n, P(rec), P(Fp), 1.1, P(out))
-            a2 = np.sum(A * A)
-            assert out[2] == pytest.approx(a2, rel=1e-13)
-            res = omlp.residual(A, Fp, dim)
-            prox = omlp.proxy_residual(A, Fp, dim, n)
-            assert abs(out[0] - res) <= 1e-12 * a2
-            assert abs(out[1] - prox) <= 1e-12 * a2
-            assert ok == int(res <= 1.1 * prox + 1e-12 * a2 and res < a2)
-            if pert == 0.0:
-                assert ok == 1
-        # an all-zero prediction explains nothing and is rejected (its proxy is ||A||^2 too)
-        out = np.zeros(8)
-        assert lib.kph_learned_check(dim, n, P(rec), P(np.zeros_like(F)), 1.1, P(out)) == 0
+        F = np.ascontiguousarray(factor_array(fo))
+        U, sv, Vt = np.linalg.svd(F[0])
+        Fn = F.copy()
+        Fn[0] = F[0] - (1.0 - 1e-6) * sv[-1] * np.outer(U[:, -1], Vt[-1])
+        preds = [F, np.zeros_like(F), Fn]
+        for pert in (1e-6, 0.01, 0.3):
+            preds.append(F * (1.0 + pert * rng.standard_normal(F.shape)))
+        for Fp in preds:
+            Fp = np.ascontiguousarray(Fp)
+            out = np.zeros(4)
+            ok = lib.kph_learned_judge(dim, n, P(rec), P(Fp), P(F), 1.1, 0.1, P(out))
+            ok_ref, rp, rs, g = omlp.accept(A, Fp, F, dim)
+            a = np.linalg.norm(A)
+            assert out[2] == pytest.approx(a, rel=1e-13)
+            assert abs(out[0] - rp) <= 1e-7 * a and abs(out[1] - rs) <= 1e-7 * a, (out, rp, rs)
+            assert abs(out[3] - g) <= 1e-9 * max(1.0, g), (out[3], g)
+            margin = min(abs(rp - 1.1 * rs) / a, abs(g - 0.1), abs(rp - a) / a)
+            if margin > 1e-9:
+                assert ok == int(ok_ref)
+            seen.add(bool(ok))
+    assert seen == {True, False}
