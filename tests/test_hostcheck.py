@@ -236,7 +236,7 @@ def test_learned_judge_matches_oracle_accept(lib, dim, n, face):
             Fp = np.ascontiguousarray(Fp)
             out = np.zeros(4)
             ok = lib.kph_learned_judge(dim, n, P(rec), P(Fp), P(F), 1.1, 0.1, P(out))
-            ok_ref, rp, rs, g = omlp.accept(A, Fp, F, dim)
+            ok_ref, rp, rs, g = omlp.accept(A, Fp, F, dim, guard=0.1)
             a = np.linalg.norm(A)
             assert out[2] == pytest.approx(a, rel=1e-13)
             assert abs(out[0] - rp) <= 1e-7 * a and abs(out[1] - rs) <= 1e-7 * a, (out, rp, rs)
