@@ -182,3 +182,26 @@ def test_c3_generator_fgmres_converges_at_mesh4(ctx):
     torch.cuda.synchronize()
     print(f"  mesh 4: exact block Jacobi {out['iters']} iterations", flush=True)
     assert int(sbj.abs().sum()) == 0 and out["converged"]
+
+
+def test_c4_fgmres_precisions(ctx):
+    """3D p = 15 at full size (4096 elements, block-diagonal, FGMRES(30) to
+    1e-10): FP32 and split BF16 applies need at most one iteration more than
+    the FP64 apply.  Plain BF16 is outside that bar on this workload (229
+    against 226 when measured): it must converge, and its count is printed."""
+    from paper_1704_04549_amd import kp
+    from tests.gpu_util import batch, to_dev
+    w = synth.workload("c4_3d_p15")
+    print(f"case c4 fgmres precisions E={w['num_elems']}", flush=True)
+    b = batch(w["params"], 3, 16)
+    pc, st = ctx.setup(b, 2)
+    rd = to_dev(w["rhs"][:, 0, :])
+    it = {}
+    for prec in ("fp64", "fp32", "bf16x3", "bf16"):
+        out = ctx.fgmres(b, rd, pc_kind=kp.KP_PC_KSVD, rank=2, pc_data=pc, pc_prec=prec,
+                         restart=30, rtol=1e-10, maxit=3000)
+        it[prec] = out["iters"]
+        print(f"  {prec}: {out['iters']} iterations, relres {out['relres']:.2e}", flush=True)
+        assert out["converged"] and out["relres"] <= 1e-10
+    assert it["fp32"] <= it["fp64"] + 1
+    assert it["bf16x3"] <= it["fp64"] + 1

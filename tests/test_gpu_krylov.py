@@ -95,6 +95,7 @@ def test_fgmres_iterations_and_solution(ctx, dim, n, mesh, seed):
     for name, kw in (("ksvd64", dict(pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec="fp64")),
                      ("ksvd32", dict(pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec="fp32")),
                      ("ksvd16", dict(pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec="bf16")),
+                     ("ksvd16x3", dict(pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec="bf16x3")),
                      ("bj", dict(pc_kind=kp.KP_PC_BJ, pc_data=lu, pc_aux=piv))):
         out = ctx.fgmres(b, rd, restart=30, rtol=1e-10, maxit=2000, **kw)
         res[name] = out["iters"]
@@ -105,6 +106,8 @@ def test_fgmres_iterations_and_solution(ctx, dim, n, mesh, seed):
     assert abs(res["ksvd64"] - it_k) <= 1
     assert abs(res["bj"] - it_j) <= 1
     assert res["ksvd32"] <= res["ksvd64"] + 1
+    assert res["ksvd16x3"] <= res["ksvd64"] + 1
+    assert res["ksvd16"] <= res["ksvd64"] + 1
 
 
 @pytest.mark.parametrize("n,mesh,seed", [(16, 3, 35), (8, 3, 36), (5, 4, 37), (2, 5, 38), (11, 2, 39)])

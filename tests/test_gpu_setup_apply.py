@@ -190,3 +190,31 @@ def test_mfma16_apply_matches_generic_and_oracle(ctx, dim, nrhs, monkeypatch):
         print(f"  {prec}: mfma {em:.2e} generic {eg:.2e}", flush=True)
         assert em <= tol and eg <= tol
     gctx.close()
+
+
+def test_c4_stratified_64_elements(ctx):
+    """3D p = 15 at full size (4096 elements): on 64 elements spread evenly
+    over the batch, singular values within 1e-12 of the oracle's full SVDs and
+    the global relative error of z = P^{-1} r over those elements within
+    1e-12 (FP64), 1e-5 (FP32), 1e-4 (split BF16) and 2e-2 (BF16) of the
+    oracle's solves (tests/golden/c4_sampled.npz, written by
+    tests/golden/make_c4_sampled.py from oracle/ alone)."""
+    import os
+
+    from tests.gpu_util import batch, rel, to_dev
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_sampled.npz"))
+    idx, sig, zref = g["idx"], g["sigma"], g["z"]
+    w = synth.workload("c4_3d_p15")
+    print(f"case c4 stratified {len(idx)} of {w['num_elems']}", flush=True)
+    b = batch(w["params"], 3, 16)
+    pc, st = ctx.setup(b, 2)
+    _, s_gpu = ctx.get_factors(b, 2, pc)
+    s_gpu = s_gpu.cpu().numpy()[idx, :3]
+    assert np.max(np.abs(s_gpu / sig - 1)) <= 1e-12
+    rd = to_dev(w["rhs"][:, 0, :])
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5), ("bf16x3", 1e-4), ("bf16", 2e-2)):
+        z = ctx.apply(b, 2, pc, prec, rd)
+        torch.cuda.synchronize()
+        err = rel(z.cpu().numpy()[idx], zref)
+        print(f"  {prec}: {err:.2e}", flush=True)
+        assert err <= tol, (prec, err)
