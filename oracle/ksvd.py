@@ -18,12 +18,21 @@ vec(A_j) = sqrt(sigma_j) u_j, vec(B_j) = sqrt(sigma_j) v_j (Sec. 4.1, KSVD).
 n^2 x n^4 rearrangement), then D1 ~ B1 (x) C1 + B2 (x) C2 (rank 2 of R(D1)),
 giving P = A1 (x) B1 (x) C1 + A1 (x) B2 (x) C2 (eq. 3d-simple-precond).
 
+Split axis (Sec. 4.3.1 splits the first factor; which axis carries the rank-1
+stage is a choice the paper does not vary): ``ksvd3d_axis`` runs the two-stage
+KSVD on the block with its tensor axes relabelled so that the chosen axis comes
+first (orders x,y,z; y,x,z; z,x,y), and ``precond_matrix`` maps P back;
+``ksvd3d_best_axis`` takes the axis whose rank-1 stage keeps the most of
+||A||_F (the largest stage-1 sigma_1; ties to the lowest axis).
+
 Canonical sign: the pair (u_j, v_j) -> (-u_j, -v_j) leaves P unchanged, so
 each u_j is flipped to make its largest-magnitude entry (lowest index on
 ties) positive.
 
 Pinned by tests/test_oracle_ksvd.py (index formula by loops, rank-1 recovery,
-Eckart-Young residual, exact separable cases).
+Eckart-Young residual, exact separable cases, the relabelling by loops, a block
+separable only along y or z recovered exactly by its own axis and not by the
+first).
 """
 from __future__ import annotations
 
@@ -71,12 +80,49 @@ def ksvd3d(A: np.ndarray, n: int) -> dict:
                 A1=A1[0], D1=D1[0], B=Bs, C=Cs)
 
 
+# axis orders of the 3D split: the chosen axis first, the other two in order
+AXIS_ORDERS = {0: (0, 1, 2), 1: (1, 0, 2), 2: (2, 0, 1)}
+
+
+def permute_block(A: np.ndarray, n: int, order) -> np.ndarray:
+    """The 3D block with its tensor axes relabelled: axis q of the result is
+    axis order[q] of A (rows and columns alike; C order, first axis slowest)."""
+    A6 = A.reshape((n,) * 6)
+    return A6.transpose(*order, *(3 + q for q in order)).reshape(n ** 3, n ** 3)
+
+
+def inverse_order(order):
+    inv = [0, 0, 0]
+    for q, o in enumerate(order):
+        inv[o] = q
+    return tuple(inv)
+
+
+def ksvd3d_axis(A: np.ndarray, n: int, axis: int) -> dict:
+    """Two-stage KSVD with the rank-1 stage on `axis` (factors in the
+    relabelled frame; precond_matrix maps P back)."""
+    f = ksvd3d(permute_block(A, n, AXIS_ORDERS[axis]), n)
+    f["axis"] = axis
+    return f
+
+
+def ksvd3d_best_axis(A: np.ndarray, n: int) -> dict:
+    fs = [ksvd3d_axis(A, n, k) for k in range(3)]
+    k = int(np.argmax([f["sigma1"][0] for f in fs]))
+    return fs[k]
+
+
 def precond_matrix(f: dict) -> np.ndarray:
-    """Dense P assembled from the factors (eqs. 2d-kron-sum, 3d-simple-precond)."""
+    """Dense P assembled from the factors (eqs. 2d-kron-sum, 3d-simple-precond),
+    in the block's own axis order."""
     if f["dim"] == 2:
         return sum(np.kron(a, b) for a, b in zip(f["A"], f["B"]))
     A1 = f["A1"]
-    return sum(np.kron(A1, np.kron(b, c)) for b, c in zip(f["B"], f["C"]))
+    P = sum(np.kron(A1, np.kron(b, c)) for b, c in zip(f["B"], f["C"]))
+    axis = f.get("axis", 0)
+    if axis:
+        P = permute_block(P, f["n"], inverse_order(AXIS_ORDERS[axis]))
+    return P
 
 
 def factor_array(f: dict) -> np.ndarray:

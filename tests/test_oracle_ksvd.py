@@ -4,7 +4,8 @@ import pytest
 
 import synth
 from oracle.blocks import element_block
-from oracle.ksvd import canonical_sign, ksvd, ksvd2d, ksvd3d, precond_matrix, rearrange
+from oracle.ksvd import (AXIS_ORDERS, canonical_sign, ksvd, ksvd2d, ksvd3d, ksvd3d_axis, ksvd3d_best_axis,
+                         permute_block, precond_matrix, rearrange)
 from oracle.tables import tables
 
 
@@ -87,3 +88,58 @@ def test_canonical_sign():
     for a in f["A"]:
         k = np.argmax(np.abs(a.ravel()))
         assert a.ravel()[k] > 0
+
+
+def test_permute_block_by_loops():
+    n = 3
+    A = np.random.default_rng(5).standard_normal((n ** 3, n ** 3))
+    for order in AXIS_ORDERS.values():
+        B = permute_block(A, n, order)
+        for I in range(n ** 3):
+            i = (I // 9, (I // 3) % 3, I % 3)
+            for J in range(0, n ** 3, 5):
+                j = (J // 9, (J // 3) % 3, J % 3)
+                # new index q holds old axis order[q]
+                oi = [0, 0, 0]
+                oj = [0, 0, 0]
+                for q in range(3):
+                    oi[order[q]] = i[q]
+                    oj[order[q]] = j[q]
+                assert B[I, J] == A[oi[0] * 9 + oi[1] * 3 + oi[2], oj[0] * 9 + oj[1] * 3 + oj[2]]
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+def test_split_axis_recovers_a_block_separable_along_that_axis(axis):
+    """A = sum over the two other axes' terms with a single factor on `axis`:
+    X (x) (Y1 (x) Z1 + Y2 (x) Z2) placed so that X acts on `axis`.  The KSVD
+    split on `axis` reproduces A exactly; the paper's fixed split of the
+    first axis does not; the best-axis rule picks `axis`."""
+    n = 4
+    rng = np.random.default_rng(10 + axis)
+    X, Y1, Z1, Y2, Z2 = (rng.standard_normal((n, n)) for _ in range(5))
+    B = np.kron(X, np.kron(Y1, Z1) + np.kron(Y2, Z2))     # X on the first axis
+    order = AXIS_ORDERS[axis]
+    inv = [0, 0, 0]
+    for q, o in enumerate(order):
+        inv[o] = q
+    A = permute_block(B, n, tuple(inv))                    # X on `axis`
+    # by loops: A's entry with X's indices on `axis`
+    i, j = (1, 2, 3), (3, 0, 2)
+    other = [q for q in range(3) if q != axis]
+    val = X[i[axis], j[axis]] * (Y1[i[other[0]], j[other[0]]] * Z1[i[other[1]], j[other[1]]] +
+                                 Y2[i[other[0]], j[other[0]]] * Z2[i[other[1]], j[other[1]]])
+    assert abs(A[i[0] * 16 + i[1] * 4 + i[2], j[0] * 16 + j[1] * 4 + j[2]] - val) < 1e-12
+    f = ksvd3d_axis(A, n, axis)
+    np.testing.assert_allclose(precond_matrix(f), A, atol=1e-12 * np.abs(A).max())
+    f0 = ksvd3d(A, n)
+    assert np.linalg.norm(A - precond_matrix(f0)) > 1e-3 * np.linalg.norm(A)
+    best = ksvd3d_best_axis(A, n)
+    assert best["axis"] == axis
+
+
+def test_split_axis_zero_is_the_paper_split():
+    n = 4
+    A = element_block(synth.draw_params(1, 3, seed=8, face=True)[0], n, 3)
+    f = ksvd3d_axis(A, n, 0)
+    g = ksvd3d(A, n)
+    np.testing.assert_allclose(precond_matrix(f), precond_matrix(g), atol=1e-13 * np.abs(A).max())
