@@ -134,13 +134,27 @@ kp_status kp_set_stream(kp_ctx ctx, void* stream);
  *     used only if its estimate of ||P_svd^{-1} P_pred - I||_2 is at most
  *     value * 1e-6 (default 0.01).  Values in [0, 1000000].  At 3D p = 15 a
  *     guard of 0.1 lets through predictions that cost FGMRES(30) 32 more
- *     iterations (258 against 226); 0.01 keeps the count. */
+ *     iterations (258 against 226); 0.01 keeps the count.
+ *   KP_OPT_SPLIT_AXIS (default 0): 3D only.  0: the rank-1 stage of the
+ *     two-stage KSVD splits the x axis, as the paper does (Sec. 4.3.1).  1:
+ *     kp_setup forms the two-stage KSVD with the split on each of x, y and z
+ *     and keeps, per element, the one whose rank-1 stage keeps the most of
+ *     ||A||_F (the largest stage-1 sigma_1; ties to x); kp_get_axes reports
+ *     the choice.  Factors are then in the element's relabelled axis order
+ *     (y,x,z for y; z,x,y for z), and kp_apply / kp_apply_z32 / kp_fgmres on
+ *     the same context load and store each element's tensor in that order.
+ *     Records only (the record's mass coefficient is symmetric in the axes,
+ *     so the relabelled block is that of the record with its per-axis data
+ *     permuted); explicit 3D blocks, the learned modes and kp_setup_noalloc
+ *     return KP_ERR_UNSUPPORTED.  A preconditioner formed with the option on
+ *     must be applied with it on.  Three times the Lanczos work of the setup. */
 typedef enum {
     KP_OPT_FGMRES_GRAPHS = 1,
     KP_OPT_APPLY_MFMA16 = 2,
     KP_OPT_FGMRES_Z32 = 3,
     KP_OPT_OPERATOR_COLS = 4,
-    KP_OPT_LEARNED_GUARD = 5
+    KP_OPT_LEARNED_GUARD = 5,
+    KP_OPT_SPLIT_AXIS = 6
 } kp_option;
 kp_status kp_set_option(kp_ctx ctx, int32_t option, int64_t value);
 const char* kp_status_string(kp_status s);
@@ -223,6 +237,10 @@ kp_status kp_setup_from_factors(kp_ctx ctx, const kp_batch* b, int32_t rank,
 kp_status kp_get_factors(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* precond,
                          double* factors, double* sigma);
 
+/* Copy the 3D elements' split axes ([E] int8: 0 = x, 1 = y, 2 = z) out of a
+ * preconditioner buffer (all 0 unless formed under KP_OPT_SPLIT_AXIS). */
+kp_status kp_get_axes(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* precond, int8_t* axes);
+
 /* z = P^{-1} r per element (Alg. 6 in 2D, Alg. 8 in 3D) for nrhs
  * right-hand sides.  r, z: [E][nrhs][n^d] FP64.  prec selects the arithmetic
  * of the contractions and the Sylvester solve (FP64, FP32, or BF16 operands
@@ -246,11 +264,15 @@ kp_status kp_apply(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* prec
 kp_status kp_apply_z32(kp_ctx ctx, const kp_batch* b, int32_t rank, const void* precond,
                        int32_t prec, int32_t nrhs, const double* r, float* z);
 
-/* Exact block Jacobi.  Factor every explicit block by LU with partial
- * pivoting: lu [E][N][N] column-major per element (entry (i,j) at j*N + i;
- * unit lower triangle below the diagonal, U on and above), piv [E][N] (row
- * swapped with row k at step k), N = n^d <= 4096.  A zero pivot sets
- * KP_ELEM_SINGULAR_FACTOR in elem_status (may be NULL).  Then z = A_k^{-1} r. */
+/* Exact block Jacobi (the paper's comparator, Sec. 5).  Factor every explicit
+ * block b->blocks by LU with partial pivoting: lu [E][N][N] row-major per
+ * element (entry (i,j) at i*N + j; unit lower triangle below the diagonal, U
+ * on and above), piv [E][N] (row swapped with row k at step k), N = n^d <=
+ * 4096.  lu may be b->blocks itself (factored in place: 64 GiB instead of 128
+ * for 32768 blocks of 512 x 512).  Blocked right-looking LU, the trailing
+ * updates on the FP64 matrix cores.  A zero pivot sets
+ * KP_ELEM_SINGULAR_FACTOR in elem_status (may be NULL).  Then z = A_k^{-1} r
+ * for nrhs right-hand sides ([E][nrhs][N]). */
 kp_status kp_blockjacobi_exact(kp_ctx ctx, const kp_batch* b, double* lu, int32_t* piv,
                                int32_t* elem_status);
 kp_status kp_blockjacobi_solve(kp_ctx ctx, const kp_batch* b, const double* lu,

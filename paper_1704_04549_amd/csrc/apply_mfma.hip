@@ -665,17 +665,35 @@ struct Item3 {
     int kd[16];
 };
 
-template <class P>
+// Strides of the item's tensor axes (a, b, c) in the element's vector: the
+// natural order (256, 16, 1), or, where the rank-1 split is on y or z, the
+// relabelled orders y,x,z (16, 256, 1) and z,x,y (1, 256, 16)
+struct AxStrides {
+    int sa, sb, sc;
+};
+__device__ __forceinline__ AxStrides ax_strides(int ax) {
+    return ax == 1 ? AxStrides{16, 256, 1} : ax == 2 ? AxStrides{1, 256, 16} : AxStrides{256, 16, 1};
+}
+// offset of tensor entry (a, b, c) in the element's vector
+template <bool AX>
+__device__ __forceinline__ int r3idx(int a, int b, int c, const AxStrides& ax) {
+    if constexpr (AX)
+        return a * ax.sa + b * ax.sb + c * ax.sc;
+    else
+        return a * 256 + b * 16 + c;
+}
+
+template <class P, bool AX>
 __device__ __forceinline__ void load_item3(Item3<P>& x, int64_t it, int nrhs, const typename P::Tab* tabs,
                                            int64_t tab_stride, const int8_t* kinds, const double* r, int g,
-                                           int c, int w, int tid) {
+                                           int c, int w, int tid, const AxStrides& ax) {
     const int64_t e = it / nrhs;
     const typename P::Tab* tab = tabs + e * tab_stride;
     const double* rw = r + it * 4096;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) x.rb[s][v] = rw[P::orow(g, v) * 256 + tile_of(s, w) * 16 + c];
+        for (int v = 0; v < 4; ++v) x.rb[s][v] = rw[r3idx<AX>(P::orow(g, v), tile_of(s, w), c, ax)];
     x.fL0 = P::row_frag(tab, 0, g, c);
     x.fL1 = P::row_frag(tab, 1, g, c);
     x.fL2 = P::row_frag(tab, 2, g, c);
@@ -696,10 +714,12 @@ __device__ __forceinline__ void load_item3(Item3<P>& x, int64_t it, int nrhs, co
 // so that half the resident workgroups load while the other half compute (the
 // identical workgroups otherwise run their load, compute and store phases in
 // step); 0: no delay.
-template <class P, int WPE, class Z = double>
+// AX: the elements' split axes (axes[E]) are read and the tensor is loaded and
+// stored in the relabelled order; without it every element is split on x.
+template <class P, int WPE, class Z = double, bool AX = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) k_apply16r3(
     int64_t E, int nrhs, const typename P::Tab* tabs, int64_t tab_stride, const int8_t* kinds, const double* r,
-    Z* z, int stagger, int nres) {
+    Z* z, int stagger, int nres, const int8_t* axes) {
     typedef typename P::T T;
     extern __shared__ __align__(16) unsigned char smem[];
     T* M = (T*)smem;         // transpose buffer; the Sylvester buffers alias it
@@ -710,8 +730,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8
     const int64_t work = E * nrhs;
     for (int64_t it = blockIdx.x; it < work; it += gridDim.x) {
         // every global load of the item first
+        AxStrides ax{256, 16, 1};
+        if constexpr (AX) ax = ax_strides(axes[it / nrhs]);
         Item3<P> x;
-        load_item3<P>(x, it, nrhs, tabs, tab_stride, kinds, r, g, c, w, tid);
+        load_item3<P, AX>(x, it, nrhs, tabs, tab_stride, kinds, r, g, c, w, tid, ax);
         typename P::Vec R[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
@@ -736,7 +758,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8
         for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                __builtin_nontemporal_store((Z)R[s][v], &zw[P::orow(g, v) * 256 + tile_of(s, w) * 16 + c]);
+                __builtin_nontemporal_store((Z)R[s][v], &zw[r3idx<AX>(P::orow(g, v), tile_of(s, w), c, ax)]);
     }
 }
 
@@ -763,14 +785,18 @@ static int device_cus() {
 // BF16 (already closer to the HBM bound) or FP64
 template <class P, int WPE, int STAGGER, class Z>
 static hipError_t launch16r3(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
-                             const int8_t* kinds, const double* r, Z* z) {
+                             const int8_t* kinds, const double* r, Z* z, const int8_t* axes) {
     const int64_t work = E * nrhs;
     const int grid = (int)(work < kApply16Grid ? work : kApply16Grid);
     const size_t lds = (kR3Work + 256) * sizeof(typename P::T);
     const int nres = WPE * device_cus();  // WPE resident workgroups per CU (a wave per SIMD each)
     const int stagger = (STAGGER > 0 && nres > 0 && work >= 4 * (int64_t)nres) ? STAGGER : 0;
-    hipLaunchKernelGGL((k_apply16r3<P, WPE, Z>), dim3(grid), dim3(256), lds, st, E, nrhs,
-                       (const typename P::Tab*)tabs, tab_stride, kinds, r, z, stagger, nres);
+    if (axes)
+        hipLaunchKernelGGL((k_apply16r3<P, WPE, Z, true>), dim3(grid), dim3(256), lds, st, E, nrhs,
+                           (const typename P::Tab*)tabs, tab_stride, kinds, r, z, stagger, nres, axes);
+    else
+        hipLaunchKernelGGL((k_apply16r3<P, WPE, Z, false>), dim3(grid), dim3(256), lds, st, E, nrhs,
+                           (const typename P::Tab*)tabs, tab_stride, kinds, r, z, stagger, nres, axes);
     return hipGetLastError();
 }
 
@@ -790,13 +816,13 @@ static hipError_t launch16(hipStream_t st, int64_t E, int nrhs, const void* tabs
 
 hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
                           int64_t tab_stride, const void* frags, const int8_t* kinds,
-                          const double* r, double* z) {
+                          const double* r, double* z, const int8_t* axes) {
     if (dim == 3) {
         switch (prec) {
-            case 0: return launch16r3<PolF64, 2, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            case 1: return launch16r3<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            case 2: return launch16r3<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            default: return launch16r3<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 0: return launch16r3<PolF64, 2, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
+            case 1: return launch16r3<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
+            case 2: return launch16r3<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
+            default: return launch16r3<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
         }
     }
     switch (prec) {
@@ -809,13 +835,13 @@ hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs,
 
 hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
                           int64_t tab_stride, const void* frags, const int8_t* kinds,
-                          const double* r, float* z) {
+                          const double* r, float* z, const int8_t* axes) {
     if (prec == 0) return hipErrorInvalidValue;  // FP64 arithmetic: z stays FP64
     if (dim == 3) {
         switch (prec) {
-            case 1: return launch16r3<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            case 2: return launch16r3<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            default: return launch16r3<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 1: return launch16r3<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
+            case 2: return launch16r3<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
+            default: return launch16r3<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
         }
     }
     switch (prec) {

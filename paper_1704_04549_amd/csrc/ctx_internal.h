@@ -45,6 +45,8 @@ struct kp_ctx_s {
     // device address of the allocation-free setup's scratch array on this
     // context's device (kp_setup_noalloc), or NULL if it could not be resolved
     double* scratch = nullptr;
+    // 3D split-axis choice (KP_OPT_SPLIT_AXIS)
+    bool split_axis = false;
     // spectral guard of the learned setup (KP_OPT_LEARNED_GUARD)
     double learned_guard = 0.01;
 };

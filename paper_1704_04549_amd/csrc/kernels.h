@@ -66,19 +66,29 @@ hipError_t launch_frag_tables(hipStream_t s, int64_t E, const double* t64, doubl
 // tabs: row-major tables of the precision (T2 is read from them); frags: the
 // fragment-ordered copy of the same precision.
 constexpr int64_t kApply16Grid = 1 << 20;
+// axes: the 3D elements' split axes (kp_setup with KP_OPT_SPLIT_AXIS), or NULL
+// (every element split on x)
 hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
                           int64_t tab_stride, const void* frags, const int8_t* kinds,
-                          const double* r, double* z);
+                          const double* r, double* z, const int8_t* axes = nullptr);
 hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
                                 const void* tabs, int64_t tab_stride, const int8_t* kinds,
-                                const double* r, double* z);
+                                const double* r, double* z, const int8_t* axes = nullptr);
 // the same two with z stored in FP32 (prec FP32, BF16, split BF16 only: their
 // results are FP32 numbers, stored exactly; prec FP64 is refused)
 hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
                           int64_t tab_stride, const void* frags, const int8_t* kinds,
-                          const double* r, float* z);
+                          const double* r, float* z, const int8_t* axes = nullptr);
 hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
                                 const void* tabs, int64_t tab_stride, const int8_t* kinds,
-                                const double* r, float* z);
+                                const double* r, float* z, const int8_t* axes = nullptr);
+
+// split-axis choice of the 3D setup: the records relabelled for axes 1 and 2
+// (out [2][E][16]); the per-element choice by the largest stage-1 sigma_1
+// (axis 0 in place, axes 1 and 2 in fac/sig/st [2][E][...]); a byte fill
+hipError_t launch_permute_records(hipStream_t s, int64_t E, const double* params, double* out);
+hipError_t launch_choose_axis(hipStream_t s, int64_t E, int64_t nfnn, const double* fac, const double* sig,
+                              const int32_t* st, double* factors, double* sigma, int32_t* status, int8_t* axis);
+hipError_t launch_fill_i8(hipStream_t s, int64_t count, int8_t* p, int8_t v);
 
 }  // namespace kp

@@ -641,10 +641,12 @@ __global__ void k_cast_tables(int64_t count, const double* t64, float* t32, uint
 // --------------------------------------------------------- generic apply
 // One workgroup per (element, rhs); tensor in LDS, tables read from global.
 template <typename T, typename TT, class Rnd, class Z = double>
+// axes (3D, or NULL): the elements' split axes; the tensor is loaded and
+// stored in the relabelled order (y,x,z or z,x,y) of its element
 __global__ void __launch_bounds__(256) k_apply_generic(int64_t E, int dim, int n, int nrhs,
                                                        const TT* tabs, int64_t tab_stride,
                                                        const int8_t* kinds, const double* r,
-                                                       Z* z, Rnd rnd) {
+                                                       Z* z, Rnd rnd, const int8_t* axes) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
     BlockTeam tm{red};
@@ -654,11 +656,30 @@ __global__ void __launch_bounds__(256) k_apply_generic(int64_t E, int dim, int n
     T* H = Y + nd;
     for (int64_t w = blockIdx.x; w < E * nrhs; w += gridDim.x) {
         const int64_t e = w / nrhs;
-        for (long t = threadIdx.x; t < nd; t += blockDim.x) X[t] = (T)r[w * nd + t];
+        const int ax = (axes && dim == 3) ? axes[e] : 0;
+        if (ax == 0) {
+            for (long t = threadIdx.x; t < nd; t += blockDim.x) X[t] = (T)r[w * nd + t];
+        } else {
+            // logical (a, b, c) at a*n^2 + b*n + c; natural address a*sa + b*sb + c*sc
+            const int sa = ax == 1 ? n : 1, sb = n * n, sc = ax == 1 ? 1 : n;
+            for (long t = threadIdx.x; t < nd; t += blockDim.x) {
+                const int a = (int)(t / (n * n)), bb = (int)((t / n) % n), cc = (int)(t % n);
+                X[t] = (T)r[w * nd + a * sa + bb * sb + cc * sc];
+            }
+        }
         __syncthreads();
         apply_tensor(tm, dim, n, tabs + e * tab_stride, kinds + e * kMaxN, X, Y, H, rnd);
         // streaming stores: z is read only by a later kernel
-        for (long t = threadIdx.x; t < nd; t += blockDim.x) __builtin_nontemporal_store((Z)X[t], &z[w * nd + t]);
+        if (ax == 0) {
+            for (long t = threadIdx.x; t < nd; t += blockDim.x)
+                __builtin_nontemporal_store((Z)X[t], &z[w * nd + t]);
+        } else {
+            const int sa = ax == 1 ? n : 1, sb = n * n, sc = ax == 1 ? 1 : n;
+            for (long t = threadIdx.x; t < nd; t += blockDim.x) {
+                const int a = (int)(t / (n * n)), bb = (int)((t / n) % n), cc = (int)(t % n);
+                __builtin_nontemporal_store((Z)X[t], &z[w * nd + a * sa + bb * sb + cc * sc]);
+            }
+        }
         __syncthreads();
     }
 }
@@ -801,43 +822,119 @@ hipError_t launch_cast_tables(hipStream_t s, int64_t count, const double* t64, f
 
 template <class Z>
 static hipError_t apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs, const void* tabs,
-                                int64_t tab_stride, const int8_t* kinds, const double* r, Z* z) {
+                                int64_t tab_stride, const int8_t* kinds, const double* r, Z* z,
+                                const int8_t* axes) {
     const long nd = dim == 2 ? n * n : n * n * n;
     int64_t work = E * nrhs;
     int grid = (int)(work < 65536 ? work : 65536);
     if (prec == 0) {
         size_t lds = 4 * nd * sizeof(double);
         hipLaunchKernelGGL((k_apply_generic<double, double, RoundNone, Z>), dim3(grid), dim3(256), lds, s,
-                           E, dim, n, nrhs, (const double*)tabs, tab_stride, kinds, r, z, RoundNone());
+                           E, dim, n, nrhs, (const double*)tabs, tab_stride, kinds, r, z, RoundNone(), axes);
     } else if (prec == 1) {
         size_t lds = 4 * nd * sizeof(float);
         hipLaunchKernelGGL((k_apply_generic<float, float, RoundNone, Z>), dim3(grid), dim3(256), lds, s,
-                           E, dim, n, nrhs, (const float*)tabs, tab_stride, kinds, r, z, RoundNone());
+                           E, dim, n, nrhs, (const float*)tabs, tab_stride, kinds, r, z, RoundNone(), axes);
     } else if (prec == 2) {
         size_t lds = 4 * nd * sizeof(float);
         hipLaunchKernelGGL((k_apply_generic<float, uint16_t, RoundBf16, Z>), dim3(grid), dim3(256), lds,
                            s, E, dim, n, nrhs, (const uint16_t*)tabs, tab_stride, kinds, r, z,
-                           RoundBf16());
+                           RoundBf16(), axes);
     } else {
         size_t lds = 4 * nd * sizeof(float);
         hipLaunchKernelGGL((k_apply_generic<float, float, RoundBf16x2, Z>), dim3(grid), dim3(256), lds,
                            s, E, dim, n, nrhs, (const float*)tabs, tab_stride, kinds, r, z,
-                           RoundBf16x2());
+                           RoundBf16x2(), axes);
     }
+    return hipGetLastError();
+}
+
+// ------------------------------------------- split-axis choice (3D records)
+// out[k - 1][e] = record e with its axes relabelled so that axis k comes first
+// (orders y,x,z and z,x,y): the per-axis data (beta, the two face velocities
+// of each axis) permuted; the mass coefficient of the record,
+// 1 + alpha sin(pi x y z + phi), is symmetric in the axes
+__global__ void k_permute_records(int64_t E, const double* params, double* out) {
+    const int64_t count = 2 * E;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < count;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(q / E) + 1;
+        const int64_t e = q % E;
+        const double* src = params + e * kRecLen;
+        double* dst = out + q * kRecLen;
+        const int o[3] = {k, 0, k == 1 ? 2 : 1};
+        for (int i = 0; i < kRecLen; ++i) dst[i] = src[i];
+        for (int a = 0; a < 3; ++a) {
+            dst[a] = src[o[a]];
+            dst[8 + 2 * a] = src[8 + 2 * o[a]];
+            dst[9 + 2 * a] = src[9 + 2 * o[a]];
+        }
+    }
+}
+
+// per element, the axis whose stage-1 sigma_1 is largest (ties to the lowest);
+// axis 0's results are in place (factors, sigma, status), axes 1 and 2 in
+// fac[k - 1], sig[k - 1], st[k - 1]; the winner's are copied in place
+__global__ void __launch_bounds__(256) k_choose_axis(int64_t E, int64_t nfnn, const double* fac, const double* sig,
+                                                     const int32_t* st, double* factors, double* sigma,
+                                                     int32_t* status, int8_t* axis) {
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        const double s0 = sigma[e * 4], s1 = sig[e * 4], s2 = sig[(E + e) * 4];
+        int k = 0;
+        double best = s0;
+        if (s1 > best) { best = s1; k = 1; }
+        if (s2 > best) { best = s2; k = 2; }
+        if (k != 0) {
+            const int64_t base = (int64_t)(k - 1) * E + e;
+            for (int64_t t = threadIdx.x; t < nfnn; t += blockDim.x) factors[e * nfnn + t] = fac[base * nfnn + t];
+            if (threadIdx.x < 4) sigma[e * 4 + threadIdx.x] = sig[base * 4 + threadIdx.x];
+            if (threadIdx.x == 0) status[e] = st[base];
+        }
+        if (threadIdx.x == 0) axis[e] = (int8_t)k;
+    }
+}
+
+__global__ void k_fill_i8(int64_t count, int8_t* p, int8_t v) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x)
+        p[q] = v;
+}
+
+hipError_t launch_permute_records(hipStream_t s, int64_t E, const double* params, double* out) {
+    if (E <= 0) return hipSuccess;
+    int64_t g = (2 * E + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_permute_records, dim3((int)g), dim3(256), 0, s, E, params, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_choose_axis(hipStream_t s, int64_t E, int64_t nfnn, const double* fac, const double* sig,
+                              const int32_t* st, double* factors, double* sigma, int32_t* status, int8_t* axis) {
+    if (E <= 0) return hipSuccess;
+    const int grid = (int)(E < 65536 ? E : 65536);
+    hipLaunchKernelGGL(k_choose_axis, dim3(grid), dim3(256), 0, s, E, nfnn, fac, sig, st, factors, sigma, status,
+                       axis);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i8(hipStream_t s, int64_t count, int8_t* p, int8_t v) {
+    if (count <= 0) return hipSuccess;
+    int64_t g = (count + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_fill_i8, dim3((int)g), dim3(256), 0, s, count, p, v);
     return hipGetLastError();
 }
 
 hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
                                 const void* tabs, int64_t tab_stride, const int8_t* kinds,
-                                const double* r, double* z) {
-    return apply_generic(s, prec, E, dim, n, nrhs, tabs, tab_stride, kinds, r, z);
+                                const double* r, double* z, const int8_t* axes) {
+    return apply_generic(s, prec, E, dim, n, nrhs, tabs, tab_stride, kinds, r, z, axes);
 }
 
 hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
                                 const void* tabs, int64_t tab_stride, const int8_t* kinds,
-                                const double* r, float* z) {
+                                const double* r, float* z, const int8_t* axes) {
     if (prec == 0) return hipErrorInvalidValue;  // FP64 arithmetic: z stays FP64
-    return apply_generic(s, prec, E, dim, n, nrhs, tabs, tab_stride, kinds, r, z);
+    return apply_generic(s, prec, E, dim, n, nrhs, tabs, tab_stride, kinds, r, z, axes);
 }
 
 }  // namespace kp

@@ -120,6 +120,7 @@ kp_status kp_set_option(kp_ctx c, int32_t option, int64_t value) {
         case KP_OPT_APPLY_MFMA16: c->use_mfma16 = value != 0; return KP_OK;
         case KP_OPT_FGMRES_Z32: c->fgmres_z32 = value != 0; return KP_OK;
         case KP_OPT_OPERATOR_COLS: c->op_cols = value != 0; return KP_OK;
+        case KP_OPT_SPLIT_AXIS: c->split_axis = value != 0; return KP_OK;
         case KP_OPT_LEARNED_GUARD:
             if (value < 0 || value > 1000000) return KP_ERR_ARG;
             c->learned_guard = (double)value * 1e-6;
@@ -186,6 +187,8 @@ kp_status kp_setup(kp_ctx c, const kp_batch* b, int32_t rank, int32_t mode, void
     if (mode != KP_SETUP_SVD && mode != KP_SETUP_LEARNED && mode != KP_SETUP_LEARNED_WARM)
         return KP_ERR_ARG;
     if (b->dim == 3 && b->blocks && b->n * b->n > 64) return KP_ERR_UNSUPPORTED;
+    // the split-axis choice relabels element records (3D, records only)
+    if (c->split_axis && b->dim == 3 && b->blocks) return KP_ERR_UNSUPPORTED;
     if (mode != KP_SETUP_SVD) {
         // a model for this (dim, n), rank 2, records only, the judge's scratch in LDS
         if (!c->model || c->model_dim != b->dim || c->model_n != b->n) return KP_ERR_ARG;
@@ -206,7 +209,29 @@ kp_status kp_setup(kp_ctx c, const kp_batch* b, int32_t rank, int32_t mode, void
     double* factors = (double*)(pc + L.factors);
     double* sigma = (double*)(pc + L.sigma);
     int32_t* status = (int32_t*)(pc + L.status);
-    if (mode == KP_SETUP_SVD) {
+    int8_t* axis = (int8_t*)(pc + L.axis);
+    const bool choose_axis = c->split_axis && b->dim == 3;
+    if (choose_axis && mode != KP_SETUP_SVD) return KP_ERR_UNSUPPORTED;
+    if (!choose_axis) KP_HIP(launch_fill_i8(c->stream, E, axis, 0));
+    if (mode == KP_SETUP_SVD && choose_axis) {
+        // the two-stage KSVD split on each axis (records relabelled for y and
+        // z); per element the axis whose rank-1 stage keeps the most of ||A||_F
+        const size_t nfnn = (size_t)L.nf * b->n * b->n;
+        if ((st = ensure_ws(c, 2 * E * (kRecLen + nfnn + 4) * sizeof(double) + 2 * E * sizeof(int32_t) + 1024,
+                            &c->ks, &c->ks_bytes)) != KP_OK)
+            return st;
+        double* recs = (double*)c->ks;
+        double* fac = recs + 2 * E * kRecLen;
+        double* sig = fac + 2 * E * nfnn;
+        int32_t* st2 = (int32_t*)(sig + 2 * E * 4);
+        KP_HIP(launch_permute_records(c->stream, E, b->params, recs));
+        KP_HIP(launch_setup(c->stream, grid, E, b->dim, b->n, rank, T, b->params, nullptr, nullptr, factors,
+                            sigma, status, (double*)c->ws, wsd));
+        for (int k = 0; k < 2; ++k)
+            KP_HIP(launch_setup(c->stream, grid, E, b->dim, b->n, rank, T, recs + k * E * kRecLen, nullptr,
+                                nullptr, fac + k * E * nfnn, sig + k * E * 4, st2 + k * E, (double*)c->ws, wsd));
+        KP_HIP(launch_choose_axis(c->stream, E, nfnn, fac, sig, st2, factors, sigma, status, axis));
+    } else if (mode == KP_SETUP_SVD) {
         KP_HIP(launch_setup(c->stream, grid, E, b->dim, b->n, rank, T, b->params, b->blocks, nullptr,
                             factors, sigma, status, (double*)c->ws, wsd));
     } else {
@@ -258,6 +283,7 @@ kp_status kp_setup_noalloc(kp_ctx c, const kp_batch* b, int32_t rank, void* prec
     const int64_t E = b->num_elems;
     if (E == 0) return KP_OK;
     if (!c->scratch) return KP_ERR_HIP;
+    if (c->split_axis && b->dim == 3) return KP_ERR_UNSUPPORTED;
     // the tables were built by kp_create; nothing here allocates
     const Tables1D* T = c->d_tables[b->n];
     if (!T) return KP_ERR_HIP;
@@ -271,6 +297,7 @@ kp_status kp_setup_noalloc(kp_ctx c, const kp_batch* b, int32_t rank, void* prec
     int64_t grid = setup_slots(E);
     if (grid > cap) grid = cap;
     char* pc = (char*)precond;
+    KP_HIP(launch_fill_i8(c->stream, E, (int8_t*)(pc + L.axis), 0));
     KP_HIP(launch_setup(c->stream, (int)grid, E, b->dim, b->n, rank, T, b->params, b->blocks, nullptr,
                         (double*)(pc + L.factors), (double*)(pc + L.sigma), (int32_t*)(pc + L.status),
                         c->scratch, wsd));
@@ -315,6 +342,7 @@ kp_status kp_setup_from_factors(kp_ctx c, const kp_batch* b, int32_t rank, const
                           hipMemcpyDeviceToDevice, c->stream));
     KP_HIP(hipMemsetAsync(pc + L.sigma, 0, E * 4 * sizeof(double), c->stream));
     KP_HIP(hipMemsetAsync(pc + L.status, 0, E * sizeof(int32_t), c->stream));
+    KP_HIP(launch_fill_i8(c->stream, E, (int8_t*)(pc + L.axis), 0));
     if ((st = finish_tables(c, b, rank, pc, L)) != KP_OK) return st;
     return copy_status(c, b, pc, L, elem_status);
 }
@@ -340,6 +368,19 @@ kp_status kp_get_factors(kp_ctx c, const kp_batch* b, int32_t rank, const void* 
     return KP_OK;
 }
 
+kp_status kp_get_axes(kp_ctx c, const kp_batch* b, int32_t rank, const void* precond, int8_t* axes) {
+    if (!c) return KP_ERR_ARG;
+    kp_status st = check_batch(b, false);
+    if (st != KP_OK) return st;
+    PcLayout L;
+    if (!pc_layout(b->dim, b->n, rank, b->num_elems, &L)) return KP_ERR_ARG;
+    const int64_t E = b->num_elems;
+    if (E == 0) return KP_OK;
+    if (!precond || !axes) return KP_ERR_ARG;
+    KP_HIP(hipMemcpyAsync(axes, (const char*)precond + L.axis, E, hipMemcpyDeviceToDevice, c->stream));
+    return KP_OK;
+}
+
 }  // extern "C"
 
 // z = P^{-1} r, z FP64 (Z = double) or FP32 (Z = float; rank 2, prec not FP64)
@@ -362,6 +403,8 @@ static kp_status apply_impl(kp_ctx c, const kp_batch* b, int32_t rank, const voi
                        : prec == KP_FP32 ? (const void*)(pc + L.t32)
                        : prec == KP_BF16 ? (const void*)(pc + L.thi)
                                          : (const void*)(pc + L.t2);
+    // the elements' split axes are read under KP_OPT_SPLIT_AXIS (3D)
+    const int8_t* axes = (c->split_axis && b->dim == 3) ? (const int8_t*)(pc + L.axis) : nullptr;
     if (rank == 3) {
         // 2D only (pc_layout rejects rank 3 in 3D); FP64 z only (checked above)
         if constexpr (!z32)
@@ -373,10 +416,10 @@ static kp_status apply_impl(kp_ctx c, const kp_batch* b, int32_t rank, const voi
                             : prec == KP_BF16 ? (const void*)(pc + L.fbf)
                                               : (const void*)(pc + L.fbf3);
         KP_HIP(launch_apply16(c->stream, prec, E, b->dim, nrhs, tabs, L.ne, frags,
-                              (const int8_t*)(pc + L.kinds), r, z));
+                              (const int8_t*)(pc + L.kinds), r, z, axes));
     } else {
         KP_HIP(launch_apply_generic(c->stream, prec, E, b->dim, b->n, nrhs, tabs, L.ne,
-                                    (const int8_t*)(pc + L.kinds), r, z));
+                                    (const int8_t*)(pc + L.kinds), r, z, axes));
     }
     return KP_OK;
 }

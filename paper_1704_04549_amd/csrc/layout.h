@@ -5,6 +5,7 @@
 //   factors [E][nf][n][n]     double  (2D rank r: nf = 2r; 3D: nf = 5)
 //   status  [E]               int32
 //   kinds   [E][32]           int8    (block kinds of T2 for the Sylvester sweep)
+//   axis    [E]               int8    (3D: the axis of the rank-1 split, 0 = x)
 //   t64     [E][ne]           double  apply tables, ne = (7 + n) n^2
 //   t32     [E][ne]           float
 //   thi     [E][ne]           bf16    high part of the split bf16 tables
@@ -27,7 +28,7 @@
 namespace kp {
 
 struct PcLayout {
-    size_t sigma, factors, status, kinds, t64, t32, thi, tlo, t2, f64f, f32f, fbf, fbf3, total;
+    size_t sigma, factors, status, kinds, axis, t64, t32, thi, tlo, t2, f64f, f32f, fbf, fbf3, total;
     long nf, ne;
 };
 
@@ -51,6 +52,7 @@ inline bool pc_layout(int dim, int n, int rank, int64_t E, PcLayout* L) {
     L->factors = off; off = align256(off + E * L->nf * nn * sizeof(double));
     L->status = off; off = align256(off + E * sizeof(int32_t));
     L->kinds = off; off = align256(off + E * kMaxN);
+    L->axis = off; off = align256(off + E);
     L->t64 = off; off = align256(off + E * L->ne * sizeof(double));
     L->t32 = off; off = align256(off + E * L->ne * sizeof(float));
     L->thi = off; off = align256(off + E * L->ne * sizeof(uint16_t));

@@ -21,7 +21,7 @@ KP_FP64, KP_FP32, KP_BF16, KP_BF16X3 = 0, 1, 2, 3
 KP_SETUP_SVD, KP_SETUP_LEARNED, KP_SETUP_LEARNED_WARM = 0, 1, 2
 KP_PC_NONE, KP_PC_KSVD, KP_PC_BJ = 0, 1, 2
 KP_OPT_FGMRES_GRAPHS, KP_OPT_APPLY_MFMA16, KP_OPT_FGMRES_Z32, KP_OPT_OPERATOR_COLS = 1, 2, 3, 4
-KP_OPT_LEARNED_GUARD = 5
+KP_OPT_LEARNED_GUARD, KP_OPT_SPLIT_AXIS = 5, 6
 ELEM_LANCZOS_NOCONV, ELEM_SINGULAR_FACTOR, ELEM_SCHUR_NOCONV, ELEM_NONFINITE = 1, 2, 4, 8
 ELEM_LEARNED_REJECTED, ELEM_LEARNED_WARM = 16, 32
 REC_LEN = 16
@@ -61,6 +61,7 @@ def lib() -> ctypes.CDLL:
             "kp_setup": ([vp, bp, i32, i32, vp, vp], ctypes.c_int),
             "kp_setup_noalloc": ([vp, bp, i32, vp, vp], ctypes.c_int),
             "kp_learned_judge": ([vp, bp, i32, vp, vp, dbl, dbl, vp, vp], ctypes.c_int),
+            "kp_get_axes": ([vp, bp, i32, vp, vp], ctypes.c_int),
             "kp_setup_from_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_get_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_apply": ([vp, bp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
@@ -228,6 +229,11 @@ class Ctx:
         _check(lib().kp_get_factors(self.h, ctypes.byref(b.c), rank, _ptr(precond), _ptr(f), _ptr(s)),
                "kp_get_factors")
         return f, s
+
+    def get_axes(self, b: Batch, rank: int, precond):
+        ax = torch.empty(b.num_elems, dtype=torch.int8, device=self.device)
+        _check(lib().kp_get_axes(self.h, ctypes.byref(b.c), rank, _ptr(precond), _ptr(ax)), "kp_get_axes")
+        return ax
 
     def apply(self, b: Batch, rank: int, precond, prec, r: torch.Tensor, z=None):
         prec = PREC.get(prec, prec)
