@@ -112,6 +112,17 @@ def ksvd3d_best_axis(A: np.ndarray, n: int) -> dict:
     return fs[k]
 
 
+def ksvd3d_rearranged(R1: np.ndarray, n: int) -> dict:
+    """ksvd3d from the stage-1 rearranged matrix R(A) (n^2 x n^4) itself, for
+    blocks too large to form densely: the same full SVDs."""
+    U, s1, Vt = np.linalg.svd(R1, full_matrices=False)
+    sg = canonical_sign(U[:, 0])
+    A1 = np.sqrt(s1[0]) * sg * U[:, 0].reshape(n, n)
+    D1 = np.sqrt(s1[0]) * sg * Vt[0].reshape(n * n, n * n)
+    s2, Bs, Cs = ksvd(D1, n, n, n, n, 2)
+    return dict(dim=3, n=n, rank=2, sigma1=s1, sigma2=s2, A1=A1, D1=D1, B=Bs, C=Cs)
+
+
 def precond_matrix(f: dict) -> np.ndarray:
     """Dense P assembled from the factors (eqs. 2d-kron-sum, 3d-simple-precond),
     in the block's own axis order."""

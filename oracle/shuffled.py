@@ -205,3 +205,16 @@ def explicit_rearranged(el: dict, Q: dict) -> np.ndarray:
     if dim == 2:
         return rearrange(A, n, n, n, n)
     return rearrange(A, n, n, n * n, n * n)
+
+
+def rearranged_rows(el: dict, Q: dict) -> np.ndarray:
+    """R(A) (3D stage 1: n^2 x n^4) row by row, each row R(A)^T e_i by the
+    shuffled transpose product, without forming the block."""
+    n = el["n"]
+    m = n * n
+    rows = []
+    for i in range(m):
+        e = np.zeros(m)
+        e[i] = 1.0
+        rows.append(shuffled_rmatvec(el, Q, e))
+    return np.stack(rows)

@@ -151,3 +151,21 @@ def test_apply_operation_counts():
             # leading term, with the lower-order terms shrinking as 1/n
             assert abs(fc.count / (lead * n ** (dim + 1)) - 1.0) <= 1.0 / n, (dim, n, fc.count)
         assert abs(slope(ns, counts) - want) <= 0.15, (dim, counts)
+
+
+def test_rearranged_rows_and_ksvd_from_them():
+    """R(A) built row by row from the transpose products equals the explicit
+    rearrangement, and the KSVD taken from it equals the one of the dense
+    block (3D, n = 4, mu = 6)."""
+    from oracle.ksvd import ksvd3d, ksvd3d_rearranged, precond_matrix
+    n, mu = 4, 6
+    q = synth.quad_elements(2, 3, mu, seed=31)
+    Q = sh.quad_tables(n, mu)
+    el = synth.quad_element(q, 1, n)
+    R = sh.rearranged_rows(el, Q)
+    np.testing.assert_allclose(R, sh.explicit_rearranged(el, Q), atol=1e-13 * np.abs(R).max())
+    A = sh.element_block(el, Q)
+    f1 = ksvd3d_rearranged(R, n)
+    f2 = ksvd3d(A, n)
+    np.testing.assert_allclose(f1["sigma2"][:3], f2["sigma2"][:3], rtol=1e-12)
+    np.testing.assert_allclose(precond_matrix(f1), precond_matrix(f2), atol=1e-12 * np.abs(A).max())
