@@ -226,6 +226,44 @@ kp_status kp_learned_judge(kp_ctx ctx, const kp_batch* b, int32_t rank, const do
                            const void* precond, double factor, double guard, double* out,
                            int32_t* accept);
 
+/*
+ * A batch of general elements of one dimension and one degree, given by
+ * their coefficients at mu >= n Gauss-Legendre points per axis of [0,1]
+ * (non-collocated quadrature, Sec. 3.4.1): the data a DG code's linearisation
+ * hands over on curved elements.  All device pointers, C order, x slowest:
+ *   c  [E][mu^d]      mass coefficient (|det J| times the pointwise mass factor)
+ *   a  [E][d][mu^d]   flux-Jacobian component dF_i/du
+ *   nu [E][mu^d]      second-order coefficient
+ *   g  [E][2d][mu^(d-1)]  upwind face coefficient on face 2*axis + side, at the
+ *                         face's own points (the other axes in order)
+ * With the Lagrange basis phi on the n Gauss-Legendre nodes and weights w,
+ * element k's block (rows test, columns trial functions) is
+ *   sum_q w_q c_q phi_I phi_K - tau sum_i sum_q w_q a_i(q) (d_i phi_I) phi_K
+ *   + tau sum_i sum_q w_q nu_q (d_i phi_I)(d_i phi_K)
+ *   + tau sum_f sum_{q on f} w_q g_f(q) phi_I phi_K   (eq. jac-entries).
+ */
+typedef struct {
+    int64_t num_elems;
+    int32_t dim, n, mu, pad;
+    double tau;
+    const double* c;
+    const double* a;
+    const double* nu;
+    const double* g;
+} kp_quad_batch;
+
+/* Form the rank-2 preconditioner (2D: rank 2; 3D: the two-stage form) of a
+ * batch of general elements (Sec. 4.1, Sec. 4.3.1, with the products of
+ * Sec. 4.2.1 / 4.3.2).  Lanczos on R(A) R(A)^T in its Gram form: the
+ * rearranged block of every term is X_p^T F Y with X_p[alpha,(a,c)] =
+ * L_p[alpha,a] R_p[alpha,c], so R R^T x needs the coefficient tensors and the
+ * small Grams X_p X_q^T only (O(mu^3) per step in 3D; no vector of length
+ * n^4); the stage-1 right factor D1 stays in that factored form for stage 2.
+ * precond: kp_precond_bytes(dim, n, 2, E) bytes, used by kp_apply /
+ * kp_fgmres with a kp_batch of the same E, dim, n (params may be NULL there).
+ * 2 <= n <= mu <= 32.  elem_status as for kp_setup. */
+kp_status kp_setup_quad(kp_ctx ctx, const kp_quad_batch* q, void* precond, int32_t* elem_status);
+
 /* Build only the apply tables from given Kronecker factors
  * (factors: [E][nf][n][n] FP64, 2D rank r: A1,B1,A2,B2,...; 3D: A1,B1,C1,B2,C2). */
 kp_status kp_setup_from_factors(kp_ctx ctx, const kp_batch* b, int32_t rank,

@@ -22,8 +22,9 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libkp.so")
 HOSTCHECK = os.path.join(ROOT, "tests", "_native", "libkp_hostcheck.so")
 
-HIP_SOURCES = ["kernels.hip", "apply_mfma.hip", "rank3.hip", "learned.hip", "mixed.hip", "krylov.hip", "bj.hip", "mlp.hip"]
-CPP_SOURCES = ["kp_api.cpp", "mlp_api.cpp", "mixed_api.cpp", "tables.cpp"]
+HIP_SOURCES = ["kernels.hip", "apply_mfma.hip", "rank3.hip", "learned.hip", "mixed.hip", "krylov.hip", "bj.hip", "mlp.hip",
+               "quad.hip"]
+CPP_SOURCES = ["kp_api.cpp", "mlp_api.cpp", "mixed_api.cpp", "tables.cpp", "quad_tables.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -63,7 +64,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(os.path.dirname(HOSTCHECK), exist_ok=True)
     cxx = shutil.which("g++") or "g++"
     _run([cxx, "-O2", "-std=c++17", "-shared", "-fPIC", f"-I{CSRC}", "-o", HOSTCHECK + ".tmp",
-          os.path.join(CSRC, "hostcheck.cpp"), os.path.join(CSRC, "tables.cpp")])
+          os.path.join(CSRC, "hostcheck.cpp"), os.path.join(CSRC, "tables.cpp"),
+          os.path.join(CSRC, "quad_tables.cpp")])
     os.replace(HOSTCHECK + ".tmp", HOSTCHECK)
     if verbose:
         print("built", LIB, "and", HOSTCHECK)

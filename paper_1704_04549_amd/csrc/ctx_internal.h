@@ -47,6 +47,8 @@ struct kp_ctx_s {
     double* scratch = nullptr;
     // 3D split-axis choice (KP_OPT_SPLIT_AXIS)
     bool split_axis = false;
+    // tables of general elements per (n, mu), uploaded on first use
+    void* d_quad[kMaxN + 1][kMaxN + 1] = {};
     // spectral guard of the learned setup (KP_OPT_LEARNED_GUARD)
     double learned_guard = 0.01;
 };

@@ -11,6 +11,7 @@
 #include "elem_ops.h"
 #include "rank3.h"
 #include "learned.h"
+#include "quad.h"
 #include "tables.h"
 
 using namespace kp;
@@ -148,6 +149,21 @@ int kph_learned_judge(int dim, int n, const double* rec, const double* Fp, const
     return learned_judge(tm, dim, n, t, rec, Fp, Fs, tab.data(), kinds.data(), work.data(), factor, guard, out)
                ? 1
                : 0;
+}
+
+// setup of one general (quadrature-data) element: factors [5 or 4][n][n],
+// sigma[4]; returns the element status (or -1 for unsupported sizes)
+int kph_setup_quad(int dim, int n, int mu, double tau, const double* c, const double* a, const double* nu,
+                   const double* g, double* factors, double* sigma) {
+    static QuadTables Q;
+    if (!make_quad_tables(n, mu, &Q)) return -1;
+    HostTeam tm;
+    std::vector<double> work(quad_setup_doubles(n));
+    QuadScratch qs;
+    SetupWork W = carve_quad_setup(work.data(), n, &qs);
+    QuadElem el{dim, n, mu, tau, c, a, nu, g};
+    Term2 T2[kQuadGroups3];
+    return setup_quad_element(tm, el, Q, factors, sigma, W, qs, T2);
 }
 
 int kph_schur(int n, const double* C, double* T, double* Q) {

@@ -91,4 +91,12 @@ hipError_t launch_choose_axis(hipStream_t s, int64_t E, int64_t nfnn, const doub
                               const int32_t* st, double* factors, double* sigma, int32_t* status, int8_t* axis);
 hipError_t launch_fill_i8(hipStream_t s, int64_t count, int8_t* p, int8_t v);
 
+// setup of general elements (quad.h, quad.hip): one workgroup per element,
+// grid workspace slots of ws_stride = quad_setup_doubles(n) doubles
+struct QuadTables;
+hipError_t launch_setup_quad(hipStream_t s, int grid, int64_t E, int dim, int n, int mu, double tau,
+                             const QuadTables* qt, const double* c, const double* a, const double* nu,
+                             const double* g, double* factors, double* sigma, int32_t* status, double* ws,
+                             int64_t ws_stride);
+
 }  // namespace kp

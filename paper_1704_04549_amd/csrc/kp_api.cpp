@@ -15,6 +15,7 @@
 #include "kernels.h"
 #include "krylov.h"
 #include "layout.h"
+#include "quad.h"
 #include "tables.h"
 #include "ctx_internal.h"
 
@@ -103,6 +104,9 @@ kp_status kp_destroy(kp_ctx c) {
     hipStreamSynchronize(c->stream);
     for (int n = 0; n <= kMaxN; ++n)
         if (c->d_tables[n]) hipFree(c->d_tables[n]);
+    for (int n = 0; n <= kMaxN; ++n)
+        for (int m = 0; m <= kMaxN; ++m)
+            if (c->d_quad[n][m]) hipFree(c->d_quad[n][m]);
     if (c->ws) hipFree(c->ws);
     if (c->ks) hipFree(c->ks);
     if (c->strc) hipFree(c->strc);
@@ -324,6 +328,51 @@ kp_status kp_learned_judge(kp_ctx c, const kp_batch* b, int32_t rank, const doub
                                 (double*)(pc + L.factors), (const double*)(pc + L.t64), L.ne,
                                 (const int8_t*)(pc + L.kinds), factor, guard, out, accept, nullptr, false, 0));
     return KP_OK;
+}
+
+kp_status kp_setup_quad(kp_ctx c, const kp_quad_batch* q, void* precond, int32_t* elem_status) {
+    if (!c || !q) return KP_ERR_ARG;
+    if (q->num_elems < 0 || (q->dim != 2 && q->dim != 3)) return KP_ERR_ARG;
+    if (q->n < 2 || q->mu < q->n || q->mu > kQuadMaxMu) return KP_ERR_ARG;
+    PcLayout L;
+    if (!pc_layout(q->dim, q->n, 2, q->num_elems, &L)) return KP_ERR_ARG;
+    const int64_t E = q->num_elems;
+    if (E == 0) return KP_OK;
+    if (!precond || !q->c || !q->a || !q->nu || !q->g) return KP_ERR_ARG;
+    hipSetDevice(c->device);
+    if (!c->d_quad[q->n][q->mu]) {
+        QuadTables* h = new (std::nothrow) QuadTables;
+        if (!h) return KP_ERR_ALLOC;
+        if (!make_quad_tables(q->n, q->mu, h)) {
+            delete h;
+            return KP_ERR_ARG;
+        }
+        void* d = nullptr;
+        if (hipMalloc(&d, sizeof(QuadTables)) != hipSuccess) {
+            delete h;
+            return KP_ERR_ALLOC;
+        }
+        const hipError_t err = hipMemcpy(d, h, sizeof(QuadTables), hipMemcpyHostToDevice);
+        delete h;
+        if (err != hipSuccess) {
+            hipFree(d);
+            return KP_ERR_HIP;
+        }
+        c->d_quad[q->n][q->mu] = d;
+    }
+    const int64_t wsd = (quad_setup_doubles(q->n) + 31) / 32 * 32;
+    const int grid = (int)(E < 2048 ? E : 2048);
+    kp_status st;
+    if ((st = ensure_ws(c, (size_t)wsd * grid * sizeof(double), &c->ws, &c->ws_bytes)) != KP_OK) return st;
+    char* pc = (char*)precond;
+    KP_HIP(launch_fill_i8(c->stream, E, (int8_t*)(pc + L.axis), 0));
+    KP_HIP(launch_setup_quad(c->stream, grid, E, q->dim, q->n, q->mu, q->tau,
+                             (const QuadTables*)c->d_quad[q->n][q->mu], q->c, q->a, q->nu, q->g,
+                             (double*)(pc + L.factors), (double*)(pc + L.sigma), (int32_t*)(pc + L.status),
+                             (double*)c->ws, wsd));
+    kp_batch b{E, q->dim, q->n, nullptr, nullptr, nullptr};
+    if ((st = finish_tables(c, &b, 2, pc, L)) != KP_OK) return st;
+    return copy_status(c, &b, pc, L, elem_status);
 }
 
 kp_status kp_setup_from_factors(kp_ctx c, const kp_batch* b, int32_t rank, const double* factors,

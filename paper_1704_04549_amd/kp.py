@@ -39,6 +39,12 @@ class kp_batch(ctypes.Structure):
                 ("params", ctypes.c_void_p), ("blocks", ctypes.c_void_p), ("nbr", ctypes.c_void_p)]
 
 
+class kp_quad_batch(ctypes.Structure):
+    _fields_ = [("num_elems", ctypes.c_int64), ("dim", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("mu", ctypes.c_int32), ("pad", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("c", ctypes.c_void_p), ("a", ctypes.c_void_p), ("nu", ctypes.c_void_p), ("g", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -62,6 +68,7 @@ def lib() -> ctypes.CDLL:
             "kp_setup_noalloc": ([vp, bp, i32, vp, vp], ctypes.c_int),
             "kp_learned_judge": ([vp, bp, i32, vp, vp, dbl, dbl, vp, vp], ctypes.c_int),
             "kp_get_axes": ([vp, bp, i32, vp, vp], ctypes.c_int),
+            "kp_setup_quad": ([vp, ctypes.POINTER(kp_quad_batch), vp, vp], ctypes.c_int),
             "kp_setup_from_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_get_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_apply": ([vp, bp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
@@ -143,6 +150,29 @@ class Batch:
         return 2 * rank if self.dim == 2 else 5
 
 
+class QuadBatch:
+    """A batch of general elements (kp_quad_batch): coefficients at mu points
+    per axis; holds references to its tensors."""
+
+    def __init__(self, dim: int, n: int, mu: int, tau: float, c, a, nu, g):
+        for t in (c, a, nu, g):
+            if t.dtype != torch.float64 or not t.is_contiguous():
+                raise ValueError("quadrature data must be contiguous float64")
+        self.dim, self.n, self.mu = int(dim), int(n), int(mu)
+        self.num_elems = int(c.shape[0])
+        self._keep = (c, a, nu, g)
+        self.c = kp_quad_batch(self.num_elems, self.dim, self.n, self.mu, 0, float(tau), _ptr(c).value,
+                               _ptr(a).value, _ptr(nu).value, _ptr(g).value)
+
+    def batch(self):
+        """The uniform batch (no records) that kp_apply / kp_fgmres take for it."""
+        b = Batch.__new__(Batch)
+        b.params = b.blocks = b.nbr = None
+        b.dim, b.n, b.num_elems = self.dim, self.n, self.num_elems
+        b.c = kp_batch(self.num_elems, self.dim, self.n, None, None, None)
+        return b
+
+
 class Ctx:
     """kp_ctx bound to a device and (by default) torch's current stream."""
 
@@ -210,6 +240,15 @@ class Ctx:
         _check(lib().kp_learned_judge(self.h, ctypes.byref(b.c), 2, _ptr(pred_factors), _ptr(precond),
                                       float(factor), float(guard), _ptr(out), _ptr(acc)), "kp_learned_judge")
         return out, acc
+
+    def setup_quad(self, q: QuadBatch, precond=None, status=None):
+        nbytes = max(self.precond_bytes(q.dim, q.n, 2, q.num_elems), 1)
+        if precond is None:
+            precond = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if status is None:
+            status = torch.empty(q.num_elems, dtype=torch.int32, device=self.device)
+        _check(lib().kp_setup_quad(self.h, ctypes.byref(q.c), _ptr(precond), _ptr(status)), "kp_setup_quad")
+        return precond, status
 
     def setup_from_factors(self, b: Batch, rank: int, factors: torch.Tensor, precond=None, status=None):
         if self.precond_bytes(b.dim, b.n, rank, 1) == 0:

@@ -246,3 +246,30 @@ def test_learned_judge_matches_oracle_accept(lib, dim, n, face):
                 assert ok == int(ok_ref)
             seen.add(bool(ok))
     assert seen == {True, False}
+
+
+@pytest.mark.parametrize("dim,n,mu", [(2, 5, 7), (2, 8, 10), (3, 4, 6), (3, 5, 5), (3, 6, 8)])
+def test_quad_setup_matches_oracle(lib, dim, n, mu):
+    """Setup of general (non-collocated quadrature) elements in the Gram form
+    of the rearranged operator, host build, against the oracle's full SVD of
+    the dense block assembled by its quadrature definition: sigma and P within
+    1e-12."""
+    from oracle import shuffled
+    from oracle.ksvd import factors_from_array
+    q = synth.quad_elements(3, dim, mu, seed=77)
+    Q = shuffled.quad_tables(n, mu)
+    lib.kph_setup_quad.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] + [ctypes.c_void_p] * 6
+    for e in range(3):
+        el = synth.quad_element(q, e, n)
+        A = shuffled.element_block(el, Q)
+        f = ksvd2d(A, n, 2) if dim == 2 else ksvd3d(A, n)
+        so = f["sigma"][:2] if dim == 2 else np.r_[f["sigma1"][0], f["sigma2"][:2]]
+        F = np.zeros((4 if dim == 2 else 5, n, n))
+        sig = np.zeros(4)
+        arrs = [np.ascontiguousarray(q[k][e]) for k in ("c", "a", "nu", "g")]
+        st = lib.kph_setup_quad(dim, n, mu, q["tau"], *(P(x) for x in arrs), P(F), P(sig))
+        assert st == 0
+        assert np.max(np.abs(sig[:len(so)] / so - 1)) <= 1e-12
+        Pg = precond_matrix(factors_from_array(F, dim))
+        Po = precond_matrix(f)
+        assert np.linalg.norm(Pg - Po) <= 1e-12 * np.linalg.norm(Po)
