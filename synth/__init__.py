@@ -238,3 +238,38 @@ def quad_element(q: dict, e: int, n: int) -> dict:
     """Element e of a quad_elements batch as the oracle's element dict."""
     return dict(dim=q["dim"], n=n, mu=q["mu"], tau=q["tau"], c=q["c"][e], a=q["a"][e], nu=q["nu"][e],
                 g=q["g"][e])
+
+
+SYSTEMS_SEED = 1007
+
+
+def systems_elements(num_elems: int, nc: int, seed: int = SYSTEMS_SEED, tau: float = TAU,
+                     face: bool = True) -> dict:
+    """2D elements of an nc-component system (input data only): per element,
+    drawn in order, for each axis a flux Jacobian J_i = R diag(lam) R^-1 with
+    R = I + 0.3 G (G ~ N(0,1)) and lam ~ U[-1,1]^nc (real eigenvalues, as for
+    the Euler equations), then log10 nu ~ U[-3,-1], alpha ~ U[0,0.5],
+    phi ~ U[0,2pi).  Also handed over, as a DG code's upwind flux would, the
+    positive parts (J_i)^+ = R diag(max(lam,0)) R^-1 and (-J_i)^+ of each
+    axis (outflow through the high and the low face)."""
+    rng = np.random.default_rng(seed)
+    E = num_elems
+    J = np.zeros((E, 2, nc, nc))
+    Jp = np.zeros((E, 2, nc, nc))
+    Jm = np.zeros((E, 2, nc, nc))
+    nu = np.zeros(E)
+    alpha = np.zeros(E)
+    phi = np.zeros(E)
+    for e in range(E):
+        for ax in range(2):
+            R = np.eye(nc) + 0.3 * rng.standard_normal((nc, nc))
+            lam = 2.0 * rng.random(nc) - 1.0
+            Ri = np.linalg.inv(R)
+            J[e, ax] = R @ np.diag(lam) @ Ri
+            Jp[e, ax] = R @ np.diag(np.maximum(lam, 0.0)) @ Ri
+            Jm[e, ax] = R @ np.diag(np.maximum(-lam, 0.0)) @ Ri
+        u = rng.random(3)
+        nu[e] = 10.0 ** (-3.0 + 2.0 * u[0])
+        alpha[e] = 0.5 * u[1]
+        phi[e] = 2.0 * np.pi * u[2]
+    return dict(nc=nc, tau=tau, face=face, J=J, Jp=Jp, Jm=Jm, nu=nu, alpha=alpha, phi=phi)
