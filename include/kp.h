@@ -264,6 +264,53 @@ typedef struct {
  * 2 <= n <= mu <= 32.  elem_status as for kp_setup. */
 kp_status kp_setup_quad(kp_ctx ctx, const kp_quad_batch* q, void* precond, int32_t* elem_status);
 
+/* Explicit diagonal blocks of a 2D system of nc coupled components (Sec. 5.3,
+ * the Euler and Navier-Stokes experiments: blocks of size nc (p+1)^2).  Nodal
+ * vectors are ordered (component, x, y), component slowest, so the first
+ * Kronecker factor acts on the pair (component, x):
+ *   A_k ~ A1 (x) B1 + A2 (x) B2,  A_j: m x m with m = nc n,  B_j: n x n.
+ * blocks: device, [E][m n][m n] FP64 row-major.  1 <= nc, 2 <= n,
+ * nc n <= 32.  nc = 1 is the scalar 2D block. */
+typedef struct {
+    int64_t num_elems;
+    int32_t nc, n;
+    const double* blocks;
+} kp_sys_batch;
+
+/* Bytes of the preconditioner buffer of a systems batch (0 if nc, n are out
+ * of range).  It holds, per element, the factors [A1 m^2, B1 n^2, A2 m^2,
+ * B2 n^2] and sigma[4] in FP64, and the apply tables in FP64 and FP32. */
+size_t kp_sys_precond_bytes(int32_t nc, int32_t n, int64_t num_elems);
+
+/* Form the rank-2 preconditioner of a systems batch (Sec. 4.1 with m1 = n1 =
+ * nc n, m2 = n2 = n; Alg. 5): Lanczos (Alg. 2) on the n^2 x n^2 Gram
+ * R(A)^T R(A), left vectors u_j = R(A) v_j / sigma_j, each pair signed so that
+ * the largest-magnitude entry of A_j is positive; then C1 = A2^-1 A1,
+ * C2 = B1^-1 B2, their real Schur forms, and the Sylvester sweep's column
+ * inverses (TA + t_jj I)^-1 (for a 2 x 2 block of TB, ((TA + pI)^2 - qs I)^-1)
+ * in FP64, with an FP32 copy.  elem_status: [E] int32 device, or NULL; bits
+ * as for kp_setup (1 Lanczos not converged, 2 singular factor, 4 Schur not
+ * converged, 8 non-finite tables).  The setup workspace (about
+ * (n^4 + 6 m^2 + 64 n^2) doubles per workgroup, at most 2048 workgroups) is
+ * allocated on the context and kept. */
+kp_status kp_setup_sys(kp_ctx ctx, const kp_sys_batch* b, void* precond, int32_t* elem_status);
+
+/* z = P^{-1} r per element (Alg. 6 with an m x m first factor): for X the
+ * element's vector as an m x n matrix (rows (component, x), columns y),
+ * X -> QA^T A2^-1 X B1^-T QB, the quasi-triangular Sylvester sweep
+ * TA S + S TB^T = F over the columns of TB from the last, then QA S QB^T.
+ * r, z: device, [E][nrhs][m n] FP64.  prec KP_FP64 or KP_FP32 (tables and
+ * arithmetic); other precisions return KP_ERR_UNSUPPORTED.  b->blocks may be
+ * NULL. */
+kp_status kp_apply_sys(kp_ctx ctx, const kp_sys_batch* b, const void* precond, int32_t prec, int32_t nrhs,
+                       const double* r, double* z);
+
+/* Copy factors ([E][2 m^2 + 2 n^2] in the order above) and singular values
+ * ([E][4]: sigma_1, sigma_2, 0, 0) out of a systems preconditioner (device
+ * pointers; either may be NULL). */
+kp_status kp_get_factors_sys(kp_ctx ctx, const kp_sys_batch* b, const void* precond, double* factors,
+                             double* sigma);
+
 /* Build only the apply tables from given Kronecker factors
  * (factors: [E][nf][n][n] FP64, 2D rank r: A1,B1,A2,B2,...; 3D: A1,B1,C1,B2,C2). */
 kp_status kp_setup_from_factors(kp_ctx ctx, const kp_batch* b, int32_t rank,

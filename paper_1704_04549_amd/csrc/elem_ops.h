@@ -1880,18 +1880,16 @@ KP_HD int ksvd_stage(const Team& tm, const Op& op, const RightOp& rop, int n, in
         // right vector loses only a factor sigma_1 / sigma_j.
         double* B = Bout + j * sb;
         rop(tm, u, 1.0, B);
+        const int mr = sdim_right * sdim_right;  // right factor entries (m when both sides are n x n)
         double p = 0.0;
-        for (int i = tm.tid(); i < m; i += tm.size()) p += B[i] * B[i];
+        for (int i = tm.tid(); i < mr; i += tm.size()) p += B[i] * B[i];
         const double sg = sqrt(tm.sum(p));
         const double rs = sqrt(sg);
         const double inv = rs > 0.0 ? 1.0 / rs : 0.0;
         if (tm.leader()) sigma[j] = sg;
-        for (int i = tm.tid(); i < m; i += tm.size()) {
-            Aout[j * sa + i] = rs * u[i];
-            B[i] *= inv;
-        }
+        for (int i = tm.tid(); i < m; i += tm.size()) Aout[j * sa + i] = rs * u[i];
+        for (int i = tm.tid(); i < mr; i += tm.size()) B[i] *= inv;
         tm.sync();
-        (void)sdim_right;
     }
     tm.sync();
     return status;

@@ -12,6 +12,7 @@
 #include "rank3.h"
 #include "learned.h"
 #include "quad.h"
+#include "sys.h"
 #include "tables.h"
 
 using namespace kp;
@@ -164,6 +165,41 @@ int kph_setup_quad(int dim, int n, int mu, double tau, const double* c, const do
     QuadElem el{dim, n, mu, tau, c, a, nu, g};
     Term2 T2[kQuadGroups3];
     return setup_quad_element(tm, el, Q, factors, sigma, W, qs, T2);
+}
+
+// nc-component 2D system block (explicit, (m n)^2, m = nc n): factors
+// [A1 m^2, B1 n^2, A2 m^2, B2 n^2], sigma[4], tables (sys_tab_entries) and
+// kinds[n]; returns the status bits
+int kph_sys_setup(int nc, int n, const double* block, double* F, double* sigma, double* tab, int8_t* kinds) {
+    const int m = nc * n;
+    if (m > kSysMaxM) return -1;
+    HostTeam tm;
+    std::vector<double> work(sys_work_doubles(m, n));
+    double* tw = nullptr;
+    SetupWork W = carve_sys(work.data(), m, n, &tw);
+    double sh[kMaxN + 8];
+    int st = setup_sys_element(tm, m, n, block, F, sigma, W);
+    st |= tables_sys(tm, m, n, F, tab, kinds, tw, sh);
+    return st;
+}
+
+// z = P^{-1} r for a system element (prec 0: FP64, 1: FP32 tables and arithmetic)
+int kph_sys_apply(int nc, int n, int prec, const double* tab, const int8_t* kinds, const double* r, double* z) {
+    const int m = nc * n;
+    HostTeam tm;
+    const long md = (long)m * n, ne = sys_tab_entries(m, n);
+    if (prec == 0) {
+        std::vector<double> X(r, r + md), Y(md), H(2 * m);
+        apply_sys(tm, m, n, tab, kinds, X.data(), Y.data(), H.data());
+        memcpy(z, X.data(), md * sizeof(double));
+        return 0;
+    }
+    std::vector<float> tf(ne), X(md), Y(md), H(2 * m);
+    for (long i = 0; i < ne; ++i) tf[i] = (float)tab[i];
+    for (long i = 0; i < md; ++i) X[i] = (float)r[i];
+    apply_sys(tm, m, n, tf.data(), kinds, X.data(), Y.data(), H.data());
+    for (long i = 0; i < md; ++i) z[i] = X[i];
+    return 0;
 }
 
 int kph_schur(int n, const double* C, double* T, double* Q) {

@@ -99,4 +99,13 @@ hipError_t launch_setup_quad(hipStream_t s, int grid, int64_t E, int dim, int n,
                              const double* g, double* factors, double* sigma, int32_t* status, double* ws,
                              int64_t ws_stride);
 
+// systems blocks (sys.h, sys.hip): setup with one workgroup per element over
+// grid workspace slots of ws_stride doubles; apply with one workgroup per
+// (element, right-hand side) in FP64 (prec 0) or FP32 (prec 1) tables and
+// arithmetic
+hipError_t launch_setup_sys(hipStream_t s, int grid, int64_t E, int nc, int n, const double* blocks,
+                            char* precond, double* ws, int64_t ws_stride);
+hipError_t launch_apply_sys(hipStream_t s, int64_t E, int nc, int n, int prec, int nrhs, const char* precond,
+                            const double* r, double* z);
+
 }  // namespace kp

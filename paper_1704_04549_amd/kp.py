@@ -39,6 +39,11 @@ class kp_batch(ctypes.Structure):
                 ("params", ctypes.c_void_p), ("blocks", ctypes.c_void_p), ("nbr", ctypes.c_void_p)]
 
 
+class kp_sys_batch(ctypes.Structure):
+    _fields_ = [("num_elems", ctypes.c_int64), ("nc", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("blocks", ctypes.c_void_p)]
+
+
 class kp_quad_batch(ctypes.Structure):
     _fields_ = [("num_elems", ctypes.c_int64), ("dim", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("mu", ctypes.c_int32), ("pad", ctypes.c_int32), ("tau", ctypes.c_double),
@@ -69,6 +74,10 @@ def lib() -> ctypes.CDLL:
             "kp_learned_judge": ([vp, bp, i32, vp, vp, dbl, dbl, vp, vp], ctypes.c_int),
             "kp_get_axes": ([vp, bp, i32, vp, vp], ctypes.c_int),
             "kp_setup_quad": ([vp, ctypes.POINTER(kp_quad_batch), vp, vp], ctypes.c_int),
+            "kp_sys_precond_bytes": ([i32, i32, i64], ctypes.c_size_t),
+            "kp_setup_sys": ([vp, ctypes.POINTER(kp_sys_batch), vp, vp], ctypes.c_int),
+            "kp_apply_sys": ([vp, ctypes.POINTER(kp_sys_batch), vp, i32, i32, vp, vp], ctypes.c_int),
+            "kp_get_factors_sys": ([vp, ctypes.POINTER(kp_sys_batch), vp, vp, vp], ctypes.c_int),
             "kp_setup_from_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_get_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_apply": ([vp, bp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
@@ -148,6 +157,25 @@ class Batch:
 
     def nf(self, rank: int) -> int:
         return 2 * rank if self.dim == 2 else 5
+
+
+class SysBatch:
+    """A batch of explicit 2D blocks of nc-component systems (kp_sys_batch):
+    blocks [E, nc n^2, nc n^2] float64, order (component, x, y); holds a
+    reference to its tensor (None for apply-only use)."""
+
+    def __init__(self, nc: int, n: int, blocks=None, num_elems=None):
+        if blocks is not None:
+            if blocks.dtype != torch.float64 or not blocks.is_contiguous():
+                raise ValueError("blocks must be contiguous float64")
+            num_elems = int(blocks.shape[0])
+        self.nc, self.n, self.num_elems = int(nc), int(n), int(num_elems)
+        self.blocks = blocks
+        self.c = kp_sys_batch(self.num_elems, self.nc, self.n, _ptr(blocks).value if blocks is not None else None)
+
+    @property
+    def ndof(self) -> int:
+        return self.nc * self.n * self.n
 
 
 class QuadBatch:
@@ -249,6 +277,39 @@ class Ctx:
             status = torch.empty(q.num_elems, dtype=torch.int32, device=self.device)
         _check(lib().kp_setup_quad(self.h, ctypes.byref(q.c), _ptr(precond), _ptr(status)), "kp_setup_quad")
         return precond, status
+
+    def sys_precond_bytes(self, nc: int, n: int, num_elems: int) -> int:
+        return int(lib().kp_sys_precond_bytes(int(nc), int(n), int(num_elems)))
+
+    def setup_sys(self, s: "SysBatch", precond=None, status=None):
+        nbytes = self.sys_precond_bytes(s.nc, s.n, s.num_elems)
+        if nbytes == 0 and s.num_elems > 0:
+            raise KpError(KP_ERR_ARG, "kp_sys_precond_bytes")
+        if precond is None:
+            precond = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+        if status is None:
+            status = torch.empty(max(s.num_elems, 1), dtype=torch.int32, device=self.device)
+        _check(lib().kp_setup_sys(self.h, ctypes.byref(s.c), _ptr(precond), _ptr(status)), "kp_setup_sys")
+        return precond, status
+
+    def apply_sys(self, s: "SysBatch", precond, prec, r: torch.Tensor, z=None):
+        prec = PREC.get(prec, prec)
+        if r.dtype != torch.float64:
+            raise ValueError("r must be float64")
+        nrhs = r.numel() // (s.num_elems * s.ndof) if s.num_elems else 1
+        if z is None:
+            z = torch.empty_like(r)
+        _check(lib().kp_apply_sys(self.h, ctypes.byref(s.c), _ptr(precond), int(prec), int(nrhs), _ptr(r),
+                                  _ptr(z)), "kp_apply_sys")
+        return z
+
+    def get_factors_sys(self, s: "SysBatch", precond):
+        m, n = s.nc * s.n, s.n
+        f = torch.empty((s.num_elems, 2 * m * m + 2 * n * n), dtype=torch.float64, device=self.device)
+        sg = torch.empty((s.num_elems, 4), dtype=torch.float64, device=self.device)
+        _check(lib().kp_get_factors_sys(self.h, ctypes.byref(s.c), _ptr(precond), _ptr(f), _ptr(sg)),
+               "kp_get_factors_sys")
+        return f, sg
 
     def setup_from_factors(self, b: Batch, rank: int, factors: torch.Tensor, precond=None, status=None):
         if self.precond_bytes(b.dim, b.n, rank, 1) == 0:

@@ -4,7 +4,8 @@
 // element's data (a table row past the last N_j, a lane index >= n, a face
 // array past its end) is reported.  Covers table formation and the generic
 // apply for 2D n = 2..32 and 3D n = 2..16 in FP64, FP32 and split BF16, the
-// structured setup, the learned-setup judge, and the general-element setup.
+// structured setup, the learned-setup judge, the general-element setup, and
+// the systems blocks' setup, tables and apply (FP64, FP32).
 // Built and run by tests/test_bounds_asan.py (CPU only).
 #include <stdio.h>
 #include <stdlib.h>
@@ -15,6 +16,7 @@
 #include "elem_ops.h"
 #include "learned.h"
 #include "quad.h"
+#include "sys.h"
 #include "tables.h"
 
 using namespace kp;
@@ -113,6 +115,40 @@ int main() {
         Term2 T2[kQuadGroups3];
         setup_quad_element(tm, el, Q, F, sig, W, qs, T2);
         free(c); free(a); free(nu); free(g); free(F); free(sig);
+        ++checked;
+    }
+    // systems blocks: nc components, m = nc n first factors
+    const int scases[][2] = {{1, 2}, {2, 4}, {4, 4}, {3, 8}, {4, 8}, {2, 16}};
+    for (const auto& cs : scases) {
+        const int nc = cs[0], n = cs[1], m = nc * n;
+        const long N = (long)m * n, md = N;
+        double* A = exact<double>(N * N);
+        for (long t = 0; t < N * N; ++t) A[t] = 0.05 * nd01(rng) + ((t / N == t % N) ? 2.0 : 0.0);
+        double* ws = exact<double>(sys_work_doubles(m, n));
+        double* tw = nullptr;
+        SetupWork W = carve_sys(ws, m, n, &tw);
+        double* F = exact<double>(sys_factor_entries(m, n));
+        double* sig = exact<double>(4);
+        const long ne = sys_tab_entries(m, n);
+        double* tab = exact<double>(ne);
+        int8_t* kinds = exact<int8_t>(kMaxN);
+        double sh[kMaxN + 8];
+        setup_sys_element(tm, m, n, A, F, sig, W);
+        tables_sys(tm, m, n, F, tab, kinds, tw, sh);
+        double* X = exact<double>(md);
+        double* Y = exact<double>(md);
+        double* H = exact<double>(2 * m);
+        for (long t = 0; t < md; ++t) X[t] = nd01(rng);
+        apply_sys(tm, m, n, tab, kinds, X, Y, H);
+        float* tf = exact<float>(ne);
+        float* Xf = exact<float>(md);
+        float* Yf = exact<float>(md);
+        float* Hf = exact<float>(2 * m);
+        for (long t = 0; t < ne; ++t) tf[t] = (float)tab[t];
+        for (long t = 0; t < md; ++t) Xf[t] = (float)nd01(rng);
+        apply_sys(tm, m, n, tf, kinds, Xf, Yf, Hf);
+        free(A); free(ws); free(F); free(sig); free(tab); free(kinds); free(X); free(Y); free(H);
+        free(tf); free(Xf); free(Yf); free(Hf);
         ++checked;
     }
     printf("checked %d cases\n", checked);

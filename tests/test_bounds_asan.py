@@ -2,8 +2,9 @@
 UndefinedBehaviorSanitizer (tests/native/bounds_check.cpp): every array an
 element's routine reads sits in a heap buffer of exactly its layout size, for
 table formation and the generic apply (2D n = 2..32, 3D n = 2..16; FP64, FP32,
-BF16, split BF16), the structured setup, the learned-setup judge and the
-general-element setup.  CPU only; skipped where g++ lacks the sanitizers."""
+BF16, split BF16), the structured setup, the learned-setup judge, the
+general-element setup and the systems blocks (setup, tables, apply).  CPU
+only; skipped where g++ lacks the sanitizers."""
 import os
 import shutil
 import subprocess
