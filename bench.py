@@ -142,23 +142,37 @@ def cpu_baseline(sample, w, nrhs, N_iter):
                 host=dict(nproc=sample["nproc"], affinity_cpus=sample["affinity"], model=sample["model"]))
 
 
-def kernel_source_hash():
-    """sha256 of the matrix-core apply kernel's source (the dominant kernel)."""
+SETUP_SOURCES = ("kernels.hip", "elem_ops.h", "kp_common.h", "kp_api.cpp", "layout.h")
+
+
+def kernel_source_hash(names=("apply_mfma.hip", "kp_common.h")):
+    """sha256 of a kernel's sources (default: the matrix-core apply, the dominant kernel)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("apply_mfma.hip", "kp_common.h"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_1704_04549_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
 # HBM bytes per apply launch from the FETCH_SIZE / WRITE_SIZE counter runs
-# (scaled by the same counters on a plain 256 MiB copy), keyed by precision;
-# valid only for the kernel source they were taken on (profiles/ holds the
-# counter summary and the commands).
+# (scaled by the same counters on a plain 256 MiB copy), keyed by precision,
+# and the matrix cores' busy fraction from SQ_VALU_MFMA_BUSY_CYCLES over
+# GRBM_GUI_ACTIVE (the per-XCD maximum) times the 1024 SIMDs, with the
+# MFMA flops the SQ_INSTS_VALU_MFMA_MOPS counters report; valid only for the
+# kernel source they were taken on (profiles/ holds the counter summaries and
+# the commands).
 MEASURED_TRAFFIC = {
-    "source_sha256": "6b6ff706bf75b559b8809d6265051a2c3c767eb1aea45899127099ebfb1d19db",
-    "bytes": {"fp32": 308666647, "fp64": 462476142},
+    "source_sha256": "701c67988804d85b9abbe23eb6e22dc60145adbcb8e4bf4a80636eebfbc1d1aa",
+    "bytes": {"fp32": 308734063, "fp64": 462477992},
+    "mfma_busy_frac": {"fp32": 0.2858, "fp64": 0.2916},
+    "mfma_counted_flops": {"fp32": 3459645440, "fp64": 3459645440},
+}
+# HBM bytes of one 3D p = 15 setup (4096 elements, every setup kernel) from
+# the same counter runs, valid for the setup sources they were taken on
+MEASURED_SETUP_TRAFFIC = {
+    "source_sha256": "df85e81c99d18a046213524c13162d2c98c26c39ed81df4e2cc70af6a1e84304",
+    "bytes": 1848137199,
 }
 
 
@@ -404,9 +418,11 @@ def main():
     apply_bytes = ndof * nrhs * (8 + z_bytes)
     table_bytes = E * (7 + n) * n * n * tab_bytes
     achieved = apply_bytes / (t_apply * 1e-3) / 1e9
-    traffic = None
-    if MEASURED_TRAFFIC["source_sha256"] == kernel_source_hash() and dim == 3 and n == 16:
+    traffic = busy = counted = None
+    if MEASURED_TRAFFIC["source_sha256"] == kernel_source_hash() and dim == 3 and n == 16 and nrhs == 1:
         traffic = MEASURED_TRAFFIC["bytes"].get(args.prec)
+        busy = MEASURED_TRAFFIC["mfma_busy_frac"].get(args.prec)
+        counted = MEASURED_TRAFFIC["mfma_counted_flops"].get(args.prec)
     kname = ("k_apply16r3, n=16 3D matrix-core path" if (dim == 3 and n == 16)
              else "k_apply16, n=16 2D matrix-core path" if n == 16 else "k_apply_generic")
     roof = {"kernel": f"apply ({kname}, z stored in " + ("FP32)" if z_bytes == 4 else "FP64)"),
@@ -420,14 +436,22 @@ def main():
     mfma = {"flops_per_launch": int(flops), "achieved_tflops": round(tf, 2),
             "peak_tflops": MFMA_PEAK_TFLOPS[args.prec], "frac": round(tf / MFMA_PEAK_TFLOPS[args.prec], 4),
             "counting": "algorithmic Schur-route flops (2D 14 n^3, 3D 16 n^4 per element and right-hand "
-                        "side) over the measured launch time"}
+                        "side) over the measured launch time",
+            "counter_busy_frac": busy,
+            "counter_mfma_flops": counted}
     # setup: algorithmic bytes are the records read, the factors and the
     # paper's seven FP64 apply tables written (LU inverses, Q, T)
     nf = 2 * rank if dim == 2 else 5
     setup_bytes = E * (16 * 8 + nf * n * n * 8 + 7 * n * n * 8)
     setup_gbs = setup_bytes / (t_setup * 1e-3) / 1e9
+    setup_traffic = None
+    if (MEASURED_SETUP_TRAFFIC["source_sha256"] == kernel_source_hash(SETUP_SOURCES) and (dim, n, E) == (3, 16, 4096)
+            and args.setup == "svd"):
+        setup_traffic = MEASURED_SETUP_TRAFFIC["bytes"]
     setup_roof = {"bound": "hbm", "achieved": round(setup_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(setup_gbs / HBM_PEAK_GBS, 5), "algorithmic_bytes": int(setup_bytes),
+                  "traffic": setup_traffic,
+                  "traffic_gbs": round(setup_traffic / (t_setup * 1e-3) / 1e9, 1) if setup_traffic else None,
                   "ms": round(t_setup, 4),
                   "note": "the setup never forms the blocks (matrix-free, Gram form of the rearranged "
                           "operator): it is bound by dependent small-matrix chains, not by HBM"}
