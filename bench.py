@@ -176,6 +176,178 @@ MEASURED_SETUP_TRAFFIC = {
 }
 
 
+def _oracle_sys_element(args):
+    """Worker: the oracle's systems block, KSVD (full SVD of R(A)) and one
+    preconditioner solve of one element, single-threaded BLAS."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import systems
+    from oracle.apply import dense_solve
+
+    e, sd, rhs, n = args
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        A = systems.element_block(sd, 0, n)
+        f = systems.ksvd_system(A, sd["nc"], n, 2)
+        t1 = time.perf_counter()
+        dense_solve(f, rhs)
+        t2 = time.perf_counter()
+    return e, t1 - t0, t2 - t1
+
+
+def bench_systems(args):
+    """2D nc-component systems: kp_setup_sys + N kp_apply_sys per step (N =
+    the FGMRES(30) count of the applied precision on the block-diagonal
+    system), blocks formed by kp_build_sys_blocks before the timed region."""
+    import multiprocessing as mp
+
+    import synth
+    w = synth.systems_workload(args.workload)
+    nc, n, E = w["nc"], w["n"], w["num_elems"]
+    m, N = nc * n, nc * n * n
+    ndof = E * N
+    sample = None
+    if not args.no_cpu_baseline and args.fixed_iters == 0:
+        sd = w["sd"]
+
+        def one(e):
+            # the element's own slice of the drawn data (small to pass to a worker)
+            return {k: (v[e:e + 1] if isinstance(v, np.ndarray) else v) for k, v in sd.items()}
+        order = list(dict.fromkeys(np.linspace(0, E - 1, 2048).astype(int).tolist()))
+        try:
+            avail = len(os.sched_getaffinity(0))
+        except AttributeError:
+            avail = os.cpu_count() or 1
+        workers = max(1, min(16, avail))
+        done = []
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(workers) as pool:
+            for res in pool.imap_unordered(_oracle_sys_element,
+                                           ((e, one(e), w["rhs"][e, 0], n) for e in order)):
+                done.append(res)
+                if time.perf_counter() - t0 >= args.cpu_seconds and len(done) >= workers:
+                    break
+            pool.terminate()
+        sample = dict(done=done, workers=workers, wall=time.perf_counter() - t0, nproc=os.cpu_count(),
+                      affinity=avail)
+
+    import torch
+
+    from paper_1704_04549_amd import kp
+    dev = torch.device("cuda", 0)
+    ctx = kp.Ctx(0)
+    stream = ctx.stream
+    blocks = ctx.build_sys_blocks(nc, n, torch.from_numpy(w["recs"]).to(dev))
+    sb = kp.SysBatch(nc, n, blocks)
+    rhs = torch.from_numpy(np.ascontiguousarray(w["rhs"][:, 0, :])).to(dev)
+    z = torch.empty_like(rhs)
+    pc, st = ctx.setup_sys(sb)
+    if args.fixed_iters > 0:
+        n64 = nv = args.fixed_iters
+        valid = False
+        solve_ms = None
+    else:
+        out64 = ctx.fgmres_sys(sb, rhs.reshape(-1), pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec="fp64",
+                               restart=30, rtol=1e-10, maxit=3000)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter()
+        outv = ctx.fgmres_sys(sb, rhs.reshape(-1), pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec=args.prec,
+                              restart=30, rtol=1e-10, maxit=3000)
+        torch.cuda.synchronize()
+        solve_ms = (time.perf_counter() - t_solve) * 1e3
+        n64, nv = out64["iters"], outv["iters"]
+        valid = outv["converged"] and out64["converged"] and nv <= n64 + 1
+
+    def timed(prec, Nit, K, W):
+        for _ in range(W):
+            ctx.setup_sys(sb, pc, st)
+            for _ in range(Nit):
+                ctx.apply_sys(sb, pc, prec, rhs, z)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(K):
+            ev[k][0].record(stream)
+            ctx.setup_sys(sb, pc, st)
+            ev[k][1].record(stream)
+            for _ in range(Nit):
+                ctx.apply_sys(sb, pc, prec, rhs, z)
+            ev[k][2].record(stream)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / K
+        return (sec, sum(a.elapsed_time(b) for a, b, _ in ev) / K,
+                sum(b.elapsed_time(c) for _, b, c in ev) / (K * Nit))
+
+    sec, t_setup, t_apply = timed(args.prec, nv, args.steps, args.warmup)
+    sec64, t_setup64, t_apply64 = timed("fp64", n64, max(3, args.steps // 4), 1)
+    value = ndof * nv / sec
+    value64 = ndof * n64 / sec64
+    ne = 3 * m * m + 3 * n * n + n * m * m
+    tb = 4 if args.prec == "fp32" else 8
+    # the setup's kernels dominate the step; its bound is the dependent
+    # small-matrix chains (Lanczos steps, Gauss-Jordan, Francis QR), priced as
+    # FP64 arithmetic: the Gram R^T R (2 m^2 n^4 flops), two Gauss-Jordan
+    # inverses (2 (m^3 + n^3)), four m x m products (8 m^3) and the column
+    # inverses (n m^3 / 3 back substitution, m^3 per 2 x 2 block of TB
+    # counted as real: n m^3 / 3)
+    setup_flops = E * (2.0 * m * m * n ** 4 + 2.0 * (m ** 3 + n ** 3) + 8.0 * m ** 3 + n * m ** 3 / 3.0)
+    setup_tf = setup_flops / (t_setup * 1e-3) / 1e12
+    apply_bytes = ndof * 16
+    tab_bytes = E * ne * tb
+    achieved = (apply_bytes + tab_bytes) / (t_apply * 1e-3) / 1e9
+    block_bytes = E * N * N * 8
+    line = {
+        "metric": "systems precond setup+apply DOF/s at equal FGMRES iterations, 2D nc=4 p=7",
+        "value": value if valid else None,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"2D nc={nc} p={n - 1} (n={n}; first factors {m} x {m}), {E} elements, "
+                               "upwind-closed explicit blocks (block-diagonal system), tau 0.01, rank-2 KSVD "
+                               f"(Lanczos on the right Gram), {args.prec} apply, FP64 FGMRES(30) to 1e-10",
+                   "elements": E, "dof": ndof, "nc": nc, "precision": args.prec,
+                   "fgmres_iters": nv, "fgmres_iters_fp64": n64, "valid": valid,
+                   "fixed_iters": args.fixed_iters or None},
+        "fp64_value": value64,
+        "speedup_vs_fp64": value / value64 if valid else None,
+        "setup_ms": t_setup,
+        "apply_ms": t_apply,
+        "apply_ms_fp64": t_apply64,
+        "fgmres_solve_ms": solve_ms,
+        "roofline": {"kernel": "setup (k_sys_ksvd + k_sys_tables: Gram, Lanczos, factors, inverses, "
+                               "Schur forms, column inverses)",
+                     "bound": "alu", "achieved": round(setup_tf, 3), "peak": 78.6, "unit": "TFLOP/s",
+                     "frac": round(setup_tf / 78.6, 5), "traffic": None,
+                     "algorithmic_flops": setup_flops, "block_bytes_read": block_bytes,
+                     "block_read_gbs": round(block_bytes / (t_setup * 1e-3) / 1e9, 1)},
+        "apply_roofline": {"kernel": "k_apply_sys", "bound": "hbm", "achieved": round(achieved, 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "algorithmic_bytes": int(apply_bytes), "table_bytes": int(tab_bytes),
+                           "ms_per_launch": round(t_apply, 5)},
+    }
+    if sample is not None:
+        done = sample["done"]
+        k = len(done)
+        t_el = sum(ts + nv * ta for _, ts, ta in done) / k
+        line["cpu_baseline"] = dict(
+            value=N * nv / t_el * sample["workers"], unit="DOF/s", cores=sample["workers"], kind="oracle",
+            sample=f"{k} elements evenly spread over the batch, {sample['workers']} worker processes with one "
+                   f"BLAS thread each for {sample['wall']:.1f} s: per element the block, the KSVD by full SVD "
+                   f"(mean {sum(d[1] for d in done) / k * 1e3:.1f} ms) and one dense solve of P (mean "
+                   f"{sum(d[2] for d in done) / k * 1e3:.2f} ms), scaled to {nv} applies per element",
+            host=dict(nproc=sample["nproc"], affinity_cpus=sample["affinity"]))
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def bench_mixed(args):
     """The mixed batch: 50000 2D elements (p 3..30) and 2000 3D elements
     (p 3..15), block-diagonal, one persistent launch per stage, autotuned
@@ -301,6 +473,11 @@ def main():
         sys.exit(2)
     if args.workload == "c5_mixed":
         bench_mixed(args)
+        return
+    if args.workload.startswith("sys_"):
+        if args.prec not in ("fp32", "fp64"):
+            raise SystemExit("the systems apply runs in fp64 or fp32")
+        bench_systems(args)
         return
     import synth
 

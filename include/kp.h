@@ -311,6 +311,39 @@ kp_status kp_apply_sys(kp_ctx ctx, const kp_sys_batch* b, const void* precond, i
 kp_status kp_get_factors_sys(kp_ctx ctx, const kp_sys_batch* b, const void* precond, double* factors,
                              double* sigma);
 
+/* Element records of a systems batch, for kp_build_sys_blocks:
+ * [E][6 nc^2 + 5] FP64 = Jx, Jy, Jx+, Jy+, Jx-, Jy- (nc x nc flux Jacobians,
+ * row-major; J+ = (J)^+ the outflow part of the upwind flux through the high
+ * face of that axis, J- = (-J)^+ through the low face), nu, alpha, phi, tau,
+ * face flag.  Element k's block (Sec. 3.4, eq. adv-kron with the advection
+ * velocity replaced by the Jacobians; collocated Gauss-Legendre quadrature):
+ *   I (x) diag(w (x) w * c) + tau [-Jx (x) S (x) W - Jy (x) W (x) S
+ *     + nu I (x) (K (x) W + W (x) K)]
+ *   + tau [Jx+ (x) l1 l1^T (x) W + Jx- (x) l0 l0^T (x) W
+ *     + Jy+ (x) W (x) l1 l1^T + Jy- (x) W (x) l0 l0^T]   (if face != 0),
+ * c = 1 + alpha sin(pi x y + phi).  blocks: [E][nc n^2][nc n^2] FP64. */
+kp_status kp_build_sys_blocks(kp_ctx ctx, int64_t num_elems, int32_t nc, int32_t n, const double* recs,
+                              double* blocks);
+
+/* y = blockdiag(A_k) x for a systems batch (no coupling between elements).
+ * x, y: [E][nc n^2]. */
+kp_status kp_sys_operator_apply(kp_ctx ctx, const kp_sys_batch* b, const double* x, double* y);
+
+/* Exact block Jacobi of a systems batch: LU with partial pivoting of every
+ * (nc n^2) x (nc n^2) block (the blocked kernel of kp_blockjacobi_exact).
+ * lu: [E][N][N], piv: [E][N] (N = nc n^2); elem_status as there. */
+kp_status kp_sys_blockjacobi_exact(kp_ctx ctx, const kp_sys_batch* b, double* lu, int32_t* piv,
+                                   int32_t* elem_status);
+
+/* FGMRES(restart) on blockdiag(A_k) x = rhs from x = 0, as kp_fgmres:
+ * pc_kind KP_PC_KSVD (pc_data = kp_setup_sys buffer, applied in pc_prec
+ * KP_FP64 or KP_FP32), KP_PC_BJ (pc_data = lu, pc_aux = piv from
+ * kp_sys_blockjacobi_exact) or KP_PC_NONE.  Same stopping rule, workspace
+ * and synchronisation as kp_fgmres; iters_h, relres_h host scalars. */
+kp_status kp_fgmres_sys(kp_ctx ctx, const kp_sys_batch* b, int32_t pc_kind, const void* pc_data,
+                        const void* pc_aux, int32_t pc_prec, const double* rhs, double* x, int32_t restart,
+                        double rtol, int32_t maxit, int32_t* iters_h, double* relres_h);
+
 /* Build only the apply tables from given Kronecker factors
  * (factors: [E][nf][n][n] FP64, 2D rank r: A1,B1,A2,B2,...; 3D: A1,B1,C1,B2,C2). */
 kp_status kp_setup_from_factors(kp_ctx ctx, const kp_batch* b, int32_t rank,

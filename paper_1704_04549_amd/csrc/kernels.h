@@ -105,6 +105,9 @@ hipError_t launch_setup_quad(hipStream_t s, int grid, int64_t E, int dim, int n,
 // arithmetic
 hipError_t launch_setup_sys(hipStream_t s, int grid, int64_t E, int nc, int n, const double* blocks,
                             char* precond, double* ws, int64_t ws_stride);
+hipError_t launch_build_sys_blocks(hipStream_t s, int64_t E, int nc, int n, const Tables1D* tab, const double* recs,
+                                   double* out);
+hipError_t launch_sys_operator(hipStream_t s, int64_t E, int N, const double* blocks, const double* x, double* y);
 hipError_t launch_apply_sys(hipStream_t s, int64_t E, int nc, int n, int prec, int nrhs, const char* precond,
                             const double* r, double* z);
 

@@ -6,15 +6,18 @@
 // is explicit, (m n) x (m n) row-major with m = nc n.  Its rearrangement R(A)
 // is m^2 x n^2 (rows: pairs of (component, x) indices; columns: pairs of y
 // indices).  Setup: Lanczos (Alg. 2) on the smaller Gram R^T R, then
-// A_j = sqrt(sigma_j) u_j (m x m), B_j = sqrt(sigma_j) v_j (n x n).  Inversion data (Alg. 5): C1 =
-// A2^-1 A1 (m x m), C2 = B1^-1 B2 (n x n), real Schur forms C1 = QA TA QA^T,
-// C2 = QB TB QB^T, LA = QA^T A2^-1, LB = QB^T B1^-1, and the column inverses
-// N_j = (TA + t_jj I)^-1 (m x m) of the quasi-triangular Sylvester sweep over
-// the n columns of TB (for a 2 x 2 block of TB, ((TA + pI)^2 - qs I)^-1).
+// A_j = sqrt(sigma_j) u_j (m x m), B_j = sqrt(sigma_j) v_j (n x n).
+// Inversion data (Alg. 5): C1 = A2^-1 A1 (m x m), C2 = B1^-1 B2 (n x n), real
+// Schur forms C1 = QA TA QA^T, C2 = QB TB QB^T, LA = QA^T A2^-1,
+// LB = QB^T B1^-1, and the column inverses of the quasi-triangular Sylvester
+// sweep over the n columns of TB: N_j = (TA + t_jj I)^-1 (m x m) for a real
+// eigenvalue t_jj; for a 2 x 2 block of TB the real and imaginary parts of one
+// complex inverse (TA + (p - i w) I)^-1 (see tables_sys).
 // Apply: X (m x n) -> LA X LB^T -> Sylvester TA Y + Y TB^T = F -> QA Y QB^T.
 #pragma once
 
 #include "elem_ops.h"
+#include "tables.h"
 
 namespace kp {
 
@@ -62,17 +65,62 @@ KP_INLINE bool sys_layout(int nc, int n, long E, SysLayout* L) {
     return true;
 }
 
+// Element record of a systems batch: [Jx, Jy, Jx+, Jy+, Jx-, Jy-] (nc x nc
+// row-major each; J+ = (J)^+ the outflow part through the high face,
+// J- = (-J)^+ through the low face), then nu, alpha, phi, tau, face.
+KP_INLINE long sys_rec_len(int nc) { return 6L * nc * nc + 5; }
+
+// Entry (I, J) of the explicit block of one element (rows test, columns trial
+// functions; nodal order (component, x, y)): the scalar weak form of
+// Sec. 3.4 (eq. adv-kron) with the advection velocity replaced by the flux
+// Jacobians, collocated Gauss-Legendre quadrature on [0,1]^2:
+//   I (x) diag(w (x) w * c) + tau [-Jx (x) S (x) W - Jy (x) W (x) S
+//   + nu I (x) (K (x) W + W (x) K)] + tau [Jx+ (x) l1 l1^T (x) W
+//   + Jx- (x) l0 l0^T (x) W + Jy+ (x) W (x) l1 l1^T + Jy- (x) W (x) l0 l0^T]
+// (faces only if face != 0), c = 1 + alpha sin(pi x y + phi) at the nodes.
+KP_INLINE double sys_block_entry(int nc, int n, long I, long J, const double* rec, const Tables1D& T) {
+    const int nn = n * n, q = nc * nc;
+    const int ci = (int)(I / nn), i = (int)((I / n) % n), j = (int)(I % n);
+    const int cj = (int)(J / nn), k = (int)((J / n) % n), l = (int)(J % n);
+    const double nu = rec[6 * q], alpha = rec[6 * q + 1], phi = rec[6 * q + 2], tau = rec[6 * q + 3];
+    const bool face = rec[6 * q + 4] != 0.0;
+    const int cc = ci * nc + cj;
+    const double Jx = rec[cc], Jy = rec[q + cc];
+    double v = 0.0;
+    if (ci == cj && i == k && j == l) {
+        const double c = 1.0 + alpha * sin(3.14159265358979323846 * T.x[i] * T.x[j] + phi);
+        v += T.w[i] * T.w[j] * c;
+    }
+    double t = 0.0;
+    if (j == l) t -= Jx * T.S[i * n + k] * T.w[j];
+    if (i == k) t -= Jy * T.w[i] * T.S[j * n + l];
+    if (ci == cj) {
+        if (j == l) t += nu * T.K[i * n + k] * T.w[j];
+        if (i == k) t += nu * T.w[i] * T.K[j * n + l];
+    }
+    if (face) {
+        const double Jxp = rec[2 * q + cc], Jyp = rec[3 * q + cc], Jxm = rec[4 * q + cc], Jym = rec[5 * q + cc];
+        if (j == l) t += (Jxp * T.l1[i] * T.l1[k] + Jxm * T.l0[i] * T.l0[k]) * T.w[j];
+        if (i == k) t += T.w[i] * (Jyp * T.l1[j] * T.l1[l] + Jym * T.l0[j] * T.l0[l]);
+    }
+    return v + tau * t;
+}
+
 KP_INLINE int sys_kmax(int n) {
     const int k = 64;
     return k < n * n ? k : n * n;
 }
 
+// work of the tables (tables_sys): six m x m matrices, kMaxN doubles and the
+// rotated factors (2 m^2 + 2 n^2)
+KP_INLINE long sys_tables_work_doubles(int m, int n) { return 8L * m * m + 2L * n * n + kMaxN; }
+
 // per-element work: Lanczos (n^2 space), the Gram R^T R, the Ritz vectors,
-// and six m x m matrices and kMaxN doubles for the tables
+// and the tables' work
 KP_INLINE long sys_work_doubles(int m, int n) {
-    const long nn = (long)n * n, mm = (long)m * m, k = sys_kmax(n);
+    const long nn = (long)n * n, k = sys_kmax(n);
     return (k + 1) * nn + nn + (k + 2) + 2 * (k + 1) + 2 * k + k * k + 3 * k + 3 + 8 + 2 * k + 4 + nn * nn +
-           3 * nn + 6 * mm + kMaxN + 8;
+           3 * nn + sys_tables_work_doubles(m, n) + 8;
 }
 KP_INLINE SetupWork carve_sys(double* p, int m, int n, double** tabwork) {
     const long nn = (long)n * n, k = sys_kmax(n);
@@ -101,7 +149,7 @@ KP_INLINE SetupWork carve_sys(double* p, int m, int n, double** tabwork) {
 // G = R(A)^T R(A) of an explicit (m n) x (m n) block:
 // G[(K,K'),(L,L')] = sum_{a,a'} A[a n + K, a' n + K'] A[a n + L, a' n + L']
 template <class Team>
-KP_HD void sys_right_gram(const Team& tm, int m, int n, const double* A, double* G) {
+KP_HD void sys_right_gram_generic(const Team& tm, int m, int n, const double* A, double* G) {
     const int q2 = n * n;
     const long N = (long)m * n;
     for (int idx = tm.tid(); idx < q2 * q2; idx += tm.size()) {
@@ -119,6 +167,65 @@ KP_HD void sys_right_gram(const Team& tm, int m, int n, const double* A, double*
     }
     tm.sync();
 }
+
+template <class Team>
+KP_HD void sys_right_gram(const Team& tm, int m, int n, const double* A, double* G) {
+    sys_right_gram_generic(tm, m, n, A, G);
+}
+#if defined(__HIPCC__)
+// workgroup form for n^2 <= 64 and 256 threads: rows of R(A) staged in LDS
+// 32 at a time (for a fixed a, the rows (a, a0..a0+31) are n runs of 32 n
+// consecutive block entries: coalesced loads), every thread accumulating a
+// 4 x 4 tile of G in registers
+__device__ inline void sys_right_gram(const BlockTeam& tm, int m, int n, const double* A, double* G) {
+    const int q2 = n * n;
+    if (q2 > 64 || blockDim.x != 256) {
+        sys_right_gram_generic(tm, m, n, A, G);
+        return;
+    }
+    __shared__ double Rc[32 * 64];
+    const int t = (int)threadIdx.x, ti = t >> 4, tj = t & 15;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    const long N = (long)m * n;
+    for (int a = 0; a < m; ++a)
+        for (int a0 = 0; a0 < m; a0 += 32) {
+            const int kc = m - a0 < 32 ? m - a0 : 32;
+            const int span = kc * n;
+            const double* base = A + (long)a * n * N + (long)a0 * n;
+            for (int idx = t; idx < n * span; idx += 256) {
+                const int K = idx / span, rem = idx % span;
+                Rc[(rem / n) * q2 + K * n + rem % n] = base[(long)K * N + rem];
+            }
+            __syncthreads();
+            for (int kk = 0; kk < kc; ++kk) {
+                const double* row = Rc + kk * q2;
+                double ri[4], cj[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    ri[i] = 4 * ti + i < q2 ? row[4 * ti + i] : 0.0;
+                    cj[i] = 4 * tj + i < q2 ? row[4 * tj + i] : 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] += ri[i] * cj[j];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = 4 * ti + i, c = 4 * tj + j;
+            if (r < q2 && c < q2) G[r * q2 + c] = acc[i][j];
+        }
+    __syncthreads();
+}
+#endif
 
 // B = sc R(A) x for a right vector x (n x n), B a left vector (m x m)
 struct SysLeftOp {
@@ -166,15 +273,115 @@ KP_HD int setup_sys_element(const Team& tm, int m, int n, const double* block, d
     return status;
 }
 
-// inversion data of one element.  work: 6 m^2 + kMaxN doubles; sh: kMaxN + 8
-// shared doubles.  Returns the element status bits (2 singular factor, 4
-// Schur not converged, 8 non-finite tables).
+// Column c of (M + shift I)^{-1} for M quasi-upper-triangular (m x m
+// row-major; a 2 x 2 diagonal block at rows i - 1, i where M[i][i - 1] != 0),
+// by back substitution on e_c; written to out[i m + c].  Returns false on a
+// zero pivot or a singular 2 x 2 block.
+KP_INLINE bool qt_inverse_col(int m, const double* M, double shift, int c, double* out) {
+    int i = m - 1;
+    bool ok = true;
+    while (i >= 0) {
+        if (i >= 1 && M[i * m + i - 1] != 0.0) {
+            double r1 = (i - 1 == c) ? 1.0 : 0.0, r2 = (i == c) ? 1.0 : 0.0;
+            for (int k = i + 1; k < m; ++k) {
+                const double xk = out[k * m + c];
+                r1 -= M[(i - 1) * m + k] * xk;
+                r2 -= M[i * m + k] * xk;
+            }
+            const double a = M[(i - 1) * m + i - 1] + shift, b = M[(i - 1) * m + i];
+            const double cc = M[i * m + i - 1], d = M[i * m + i] + shift;
+            const double det = a * d - b * cc;
+            if (det == 0.0) {
+                ok = false;
+                out[(i - 1) * m + c] = 0.0;
+                out[i * m + c] = 0.0;
+            } else {
+                out[(i - 1) * m + c] = (d * r1 - b * r2) / det;
+                out[i * m + c] = (a * r2 - cc * r1) / det;
+            }
+            i -= 2;
+        } else {
+            double r = (i == c) ? 1.0 : 0.0;
+            for (int k = i + 1; k < m; ++k) r -= M[i * m + k] * out[k * m + c];
+            const double piv = M[i * m + i] + shift;
+            if (piv == 0.0) {
+                ok = false;
+                out[i * m + c] = 0.0;
+            } else {
+                out[i * m + c] = r / piv;
+            }
+            i -= 1;
+        }
+    }
+    return ok;
+}
+
+// Column c of (M + (sr + i si) I)^{-1} for M quasi-upper-triangular as
+// above, in complex arithmetic: real parts to outr[i m + c], imaginary parts
+// to outi[i m + c].  Returns false on a zero pivot or a singular 2 x 2 block.
+KP_INLINE bool qt_inverse_col_c(int m, const double* M, double sr, double si, int c, double* outr, double* outi) {
+    // (a + ib) / (x + iy)
+    auto cdiv = [](double a, double b, double x, double y, double* re, double* im) {
+        const double d = x * x + y * y;
+        *re = (a * x + b * y) / d;
+        *im = (b * x - a * y) / d;
+    };
+    int i = m - 1;
+    bool ok = true;
+    while (i >= 0) {
+        if (i >= 1 && M[i * m + i - 1] != 0.0) {
+            double r1 = (i - 1 == c) ? 1.0 : 0.0, r1i = 0.0, r2 = (i == c) ? 1.0 : 0.0, r2i = 0.0;
+            for (int k = i + 1; k < m; ++k) {
+                const double xr = outr[k * m + c], xi = outi[k * m + c];
+                const double m1 = M[(i - 1) * m + k], m2 = M[i * m + k];
+                r1 -= m1 * xr;
+                r1i -= m1 * xi;
+                r2 -= m2 * xr;
+                r2i -= m2 * xi;
+            }
+            const double ar = M[(i - 1) * m + i - 1] + sr, b = M[(i - 1) * m + i];
+            const double cc = M[i * m + i - 1], dr = M[i * m + i] + sr;
+            // det = (a + i si)(d + i si) - b cc
+            const double detr = ar * dr - si * si - b * cc, deti = si * (ar + dr);
+            if (detr == 0.0 && deti == 0.0) {
+                ok = false;
+                outr[(i - 1) * m + c] = outi[(i - 1) * m + c] = 0.0;
+                outr[i * m + c] = outi[i * m + c] = 0.0;
+            } else {
+                // x1 = ((d + i si) r1 - b r2) / det, x2 = ((a + i si) r2 - cc r1) / det
+                const double n1r = dr * r1 - si * r1i - b * r2, n1i = dr * r1i + si * r1 - b * r2i;
+                const double n2r = ar * r2 - si * r2i - cc * r1, n2i = ar * r2i + si * r2 - cc * r1i;
+                cdiv(n1r, n1i, detr, deti, &outr[(i - 1) * m + c], &outi[(i - 1) * m + c]);
+                cdiv(n2r, n2i, detr, deti, &outr[i * m + c], &outi[i * m + c]);
+            }
+            i -= 2;
+        } else {
+            double r = (i == c) ? 1.0 : 0.0, ri = 0.0;
+            for (int k = i + 1; k < m; ++k) {
+                r -= M[i * m + k] * outr[k * m + c];
+                ri -= M[i * m + k] * outi[k * m + c];
+            }
+            const double pr = M[i * m + i] + sr;
+            if (pr == 0.0 && si == 0.0) {
+                ok = false;
+                outr[i * m + c] = outi[i * m + c] = 0.0;
+            } else {
+                cdiv(r, ri, pr, si, &outr[i * m + c], &outi[i * m + c]);
+            }
+            i -= 1;
+        }
+    }
+    return ok;
+}
+
+// inversion data of one element.  work: sys_tables_work_doubles(m, n)
+// doubles; sh: kMaxN + 8 shared doubles.  Returns the element status bits
+// (2 singular factor, 4 Schur not converged, 8 non-finite tables).
 template <class Team>
 KP_HD int tables_sys(const Team& tm, int m, int n, const double* F, double* tab, int8_t* kinds, double* work,
                      double* sh) {
     const long ma = (long)m * m, nb = (long)n * n;
     const SysTab o = sys_tab(m, n);
-    const double *A1 = F, *B1 = F + ma, *A2 = F + ma + nb, *B2 = F + 2 * ma + nb;
     double* W0 = work;
     double* W1 = W0 + ma;
     double* W2 = W1 + ma;
@@ -183,6 +390,70 @@ KP_HD int tables_sys(const Team& tm, int m, int n, const double* F, double* tab,
     double* W5 = W4 + ma;
     double* mult = W5 + ma;
     int status = 0;
+    // Pair rotation before inversion: A1 (x) B1 + A2 (x) B2 is unchanged when
+    // (A1, A2) and (B1, B2) are rotated by the same angle after balancing the
+    // norms within each term.  The route inverts A2 and B1, which can be
+    // nearly singular while P is well conditioned, so the angle (one of 8 in
+    // [0, pi)) that minimises kappa_1(A2') kappa_1(B1') is used.  The stored
+    // factors stay the KSVD's.
+    double* A1 = mult + kMaxN;
+    double* A2 = A1 + ma;
+    double* B1 = A2 + ma;
+    double* B2 = B1 + nb;
+    {
+        const double *F1 = F, *G1 = F + ma, *F2 = F + ma + nb, *G2 = F + 2 * ma + nb;
+        double p1 = 0.0, p2 = 0.0;
+        for (long t = tm.tid(); t < ma; t += tm.size()) {
+            p1 += F1[t] * F1[t];
+            p2 += F2[t] * F2[t];
+        }
+        const double s1 = sqrt(tm.sum(p1)), s2 = sqrt(tm.sum(p2));
+        const double a1 = s1 > 0.0 ? s1 : 1.0, a2 = s2 > 0.0 ? s2 : 1.0;
+        for (long t = tm.tid(); t < ma; t += tm.size()) {
+            A1[t] = F1[t] / a1;
+            A2[t] = F2[t] / a2;
+        }
+        for (long t = tm.tid(); t < nb; t += tm.size()) {
+            B1[t] = G1[t] * a1;
+            B2[t] = G2[t] * a2;
+        }
+        tm.sync();
+        const double pi = 3.14159265358979323846;
+        double best = -1.0;
+        int bestk = 0;
+        for (int k = 0; k < 8; ++k) {
+            const double c = cos(pi * k / 8.0), sn = sin(pi * k / 8.0);
+            for (long t = tm.tid(); t < ma; t += tm.size()) W0[t] = -sn * A1[t] + c * A2[t];
+            for (long t = tm.tid(); t < nb; t += tm.size()) W2[t] = c * B1[t] + sn * B2[t];
+            tm.sync();
+            double score = 1.0;
+            for (int q = 0; q < 2; ++q) {
+                const int sz = q == 0 ? m : n;
+                double* M = q == 0 ? W0 : W2;
+                const double nm = norm1(tm, sz, M, sh);
+                const bool ok = invert(tm, sz, M, W1, nullptr, mult);
+                const double ni = norm1(tm, sz, W1, sh);
+                score *= ok ? nm * ni : 1e300;
+            }
+            if (!(score == score)) score = 1e300;
+            if (best < 0.0 || score < best) {
+                best = score;
+                bestk = k;
+            }
+        }
+        const double c = cos(pi * bestk / 8.0), sn = sin(pi * bestk / 8.0);
+        for (long t = tm.tid(); t < ma; t += tm.size()) {
+            const double l1 = A1[t], l2 = A2[t];
+            A1[t] = c * l1 + sn * l2;
+            A2[t] = -sn * l1 + c * l2;
+        }
+        for (long t = tm.tid(); t < nb; t += tm.size()) {
+            const double r1 = B1[t], r2 = B2[t];
+            B1[t] = c * r1 + sn * r2;
+            B2[t] = -sn * r1 + c * r2;
+        }
+        tm.sync();
+    }
     // (size, inverted factor, other factor, L, Q, T) for the two sides
     for (int side = 0; side < 2; ++side) {
         const int s = side == 0 ? m : n;
@@ -214,35 +485,74 @@ KP_HD int tables_sys(const Team& tm, int m, int n, const double* F, double* tab,
         kinds[j] = (int8_t)kd;
     }
     tm.sync();
+    // column inverses of the sweep.  Every matrix inverted here is TA plus a
+    // (real or complex) multiple of I, quasi-upper-triangular with the 2 x 2
+    // diagonal blocks of TA, so each column of the inverse is one back
+    // substitution, independent of the others.
     double* N = tab + o.N;
-    for (int j = 0; j < n; ++j) {
-        const int kd = kinds[j];
-        if (kd == 1) continue;  // filled with its partner
-        if (kd == 0) {
-            const double tj = TB[j * n + j];
-            for (long t = tm.tid(); t < ma; t += tm.size()) W0[t] = TA[t] + ((t / m == t % m) ? tj : 0.0);
-            tm.sync();
-        } else {
-            const double p = TB[j * n + j], q = TB[(j - 1) * n + j], sv = TB[j * n + j - 1];
-            for (long t = tm.tid(); t < ma; t += tm.size()) W4[t] = TA[t] + ((t / m == t % m) ? p : 0.0);
-            tm.sync();
-            mm(tm, m, W4, W4, W5);
-            for (long t = tm.tid(); t < ma; t += tm.size()) W0[t] = W5[t] - ((t / m == t % m) ? q * sv : 0.0);
-            tm.sync();
-        }
-        if (!invert(tm, m, W0, W1, nullptr, mult)) status |= 2;
-        for (long t = tm.tid(); t < ma; t += tm.size()) {
-            N[(long)j * ma + t] = W1[t];
-            if (kd == 2) N[(long)(j - 1) * ma + t] = W1[t];
-        }
-        tm.sync();
+    double* TAw = W5;
+    for (long t = tm.tid(); t < ma; t += tm.size()) TAw[t] = TA[t];
+    tm.sync();
+    double sing = 0.0;
+    for (int t = tm.tid(); t < n * m; t += tm.size()) {
+        const int j = t / m, c = t % m;
+        if (kinds[j] != 0) continue;
+        if (!qt_inverse_col(m, TAw, TB[j * n + j], c, N + (long)j * ma)) sing = 1.0;
     }
+    tm.sync();
+    // a 2 x 2 block of TB at (j - 1, j), [[p, q], [sv, p]] with q sv < 0: its
+    // two columns solve (TA + pI) y1 + q y2 = f1, sv y1 + (TA + pI) y2 = f2,
+    // i.e. (TA + (p - i w) I) (y1 + i y2 / g) = f1 + i f2 / g with
+    // w = sqrt(-q sv), g = w / q.  The complex inverse K = Kr + i Ki goes to
+    // the N slots j - 1 (Kr) and j (Ki); its conditioning is that of the
+    // shifted TA itself.
+    for (int t = tm.tid(); t < n * m; t += tm.size()) {
+        const int j = t / m, c = t % m;
+        if (kinds[j] != 2) continue;
+        const double p = TB[j * n + j], qs = TB[(j - 1) * n + j] * TB[j * n + j - 1];
+        if (!(qs < 0.0)) {
+            sing = 1.0;
+            continue;
+        }
+        if (!qt_inverse_col_c(m, TAw, p, -sqrt(-qs), c, N + (long)(j - 1) * ma, N + (long)j * ma)) sing = 1.0;
+    }
+    tm.sync();
+    if (tm.max(sing) != 0.0) status |= 2;
     double bad = 0.0;
     for (long t = tm.tid(); t < sys_tab_entries(m, n); t += tm.size())
         if (!(fabs(tab[t]) < 1e300)) bad = 1.0;
     if (tm.max(bad) != 0.0) status |= 8;
     return status;
 }
+
+// out[i os] = sum_a M[i m + a] x[a xs] for i < m (M m x m row-major)
+template <class Team, typename T, typename TT>
+KP_HD void sys_matvec(const Team& tm, int m, const TT* M, const T* x, int xs, T* out, int os) {
+    for (int i = tm.tid(); i < m; i += tm.size()) {
+        T acc = (T)0;
+        for (int a = 0; a < m; ++a) acc += (T)M[i * m + a] * x[a * xs];
+        out[i * os] = acc;
+    }
+    tm.sync();
+}
+#if defined(__HIPCC__)
+// workgroup form: g consecutive lanes per row (g a power of two, g m <= the
+// workgroup size), lane p of a row reading M[i m + p + g q], so that the g
+// lanes of a row read g consecutive entries per step; the partial sums are
+// combined across the g lanes by shuffles
+template <typename T, typename TT>
+__device__ void sys_matvec(const BlockTeam& tm, int m, const TT* M, const T* x, int xs, T* out, int os) {
+    int g = 64;
+    while (g > 1 && g * m > (int)blockDim.x) g >>= 1;
+    const int t = (int)threadIdx.x, i = t / g, p = t % g;
+    T acc = (T)0;
+    if (i < m)
+        for (int a = p; a < m; a += g) acc += (T)M[i * m + a] * x[a * xs];
+    for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (i < m && p == 0) out[i * os] = acc;
+    tm.sync();
+}
+#endif
 
 // X (m x n, row-major) <- P^{-1} X.  Y: m n scratch, Hs: 2 m scratch.
 template <class Team, typename T, typename TT>
@@ -278,13 +588,7 @@ KP_HD void apply_sys(const Team& tm, int m, int n, const TT* tab, const int8_t* 
     while (j >= 0) {
         const int kd = kinds[j];
         if (kd != 2) {
-            const TT* Nj = N + (long)j * mm;
-            for (int i = tm.tid(); i < m; i += tm.size()) {
-                T acc = (T)0;
-                for (int a = 0; a < m; ++a) acc += (T)Nj[i * m + a] * F[a * n + j];
-                S[i * n + j] = acc;
-            }
-            tm.sync();
+            sys_matvec(tm, m, N + (long)j * mm, F + j, n, S + j, n);
             for (int t = tm.tid(); t < m * j; t += tm.size()) {
                 const int k = t % j, i = t / j;
                 F[i * n + k] -= (T)TB[k * n + j] * S[i * n + j];
@@ -292,26 +596,20 @@ KP_HD void apply_sys(const Team& tm, int m, int n, const TT* tab, const int8_t* 
             tm.sync();
             --j;
         } else {
+            // y1 = Kr f1 - Ki f2 / g, y2 = g Ki f1 + Kr f2 (K the complex inverse
+            // of the block, g = w / q)
             const int j1 = j - 1;
-            const T p = (T)TB[j * n + j], q = (T)TB[j1 * n + j], sv = (T)TB[j * n + j1];
-            const TT* Nj = N + (long)j * mm;
+            const T q = (T)TB[j1 * n + j], sv = (T)TB[j * n + j1];
+            const T g = sqrt(-q * sv) / q;
+            const TT* Kr = N + (long)j1 * mm;
+            const TT* Ki = N + (long)j * mm;
+            sys_matvec(tm, m, Kr, F + j1, n, S + j1, n);
+            sys_matvec(tm, m, Kr, F + j, n, S + j, n);
+            sys_matvec(tm, m, Ki, F + j, n, Hs, 1);
+            sys_matvec(tm, m, Ki, F + j1, n, Hs + m, 1);
             for (int i = tm.tid(); i < m; i += tm.size()) {
-                T a1 = (T)0, a2 = (T)0;
-                for (int a = 0; a < m; ++a) {
-                    const T ta = (T)TA[i * m + a];
-                    a1 += ta * F[a * n + j1];
-                    a2 += ta * F[a * n + j];
-                }
-                const T g1 = F[i * n + j1], g2 = F[i * n + j];
-                Hs[i] = a1 + p * g1 - q * g2;
-                Hs[m + i] = a2 + p * g2 - sv * g1;
-            }
-            tm.sync();
-            for (int t = tm.tid(); t < 2 * m; t += tm.size()) {
-                const int h = t / m, i = t % m;
-                T acc = (T)0;
-                for (int a = 0; a < m; ++a) acc += (T)Nj[i * m + a] * Hs[h * m + a];
-                S[i * n + (h ? j : j1)] = acc;
+                S[i * n + j1] -= Hs[i] / g;
+                S[i * n + j] += g * Hs[m + i];
             }
             tm.sync();
             for (int t = tm.tid(); t < m * j1; t += tm.size()) {

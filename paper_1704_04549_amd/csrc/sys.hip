@@ -1,7 +1,8 @@
-// Kernels of the systems blocks (sys.h): the setup runs one workgroup per
-// element in a persistent grid, its Lanczos work, Gram and table scratch in a
-// per-workgroup slot of global workspace; the apply runs one workgroup per
-// (element, right-hand side) with the element's vector in LDS.
+// Kernels of the systems blocks (sys.h): the KSVD runs one workgroup per
+// element in a persistent grid, its Lanczos work and Gram in a per-workgroup
+// slot of global workspace; the tables run one workgroup per element with
+// their work matrices in LDS; the apply runs one workgroup per (element,
+// right-hand side) with the element's vector in LDS.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -9,10 +10,9 @@
 
 namespace kp {
 
-__global__ void __launch_bounds__(256) k_setup_sys(int64_t E, int nc, int n, const double* blocks, char* pc,
-                                                   SysLayout L, double* ws, int64_t ws_stride) {
+__global__ void __launch_bounds__(256) k_sys_ksvd(int64_t E, int nc, int n, const double* blocks, char* pc,
+                                                  SysLayout L, double* ws, int64_t ws_stride) {
     __shared__ double red[4 * kMaxReduce];
-    __shared__ double sh[kMaxN + 8];
     BlockTeam tm{red};
     const int m = nc * n;
     const long bsz = (long)m * n * m * n;
@@ -21,17 +21,32 @@ __global__ void __launch_bounds__(256) k_setup_sys(int64_t E, int nc, int n, con
     double* factors = (double*)(pc + L.factors);
     double* sigma = (double*)(pc + L.sigma);
     int32_t* status = (int32_t*)(pc + L.status);
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        const int st = setup_sys_element(tm, m, n, blocks + e * bsz, factors + e * L.nf, sigma + e * 4, W);
+        if (threadIdx.x == 0) status[e] = st;
+        __syncthreads();
+    }
+}
+
+// inversion data with its work matrices in LDS (sys_tables_work_doubles
+// doubles of dynamic LDS), then the FP32 copy of the element's tables
+__global__ void __launch_bounds__(256) k_sys_tables(int64_t E, int nc, int n, char* pc, SysLayout L) {
+    extern __shared__ double lds[];
+    __shared__ double red[4 * kMaxReduce];
+    __shared__ double sh[kMaxN + 8];
+    BlockTeam tm{red};
+    const int m = nc * n;
+    const double* factors = (const double*)(pc + L.factors);
+    int32_t* status = (int32_t*)(pc + L.status);
     double* tab64 = (double*)(pc + L.tab64);
     float* tab32 = (float*)(pc + L.tab32);
     int8_t* kinds = (int8_t*)(pc + L.kinds);
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
-        double* F = factors + e * L.nf;
         double* tab = tab64 + e * L.ne;
-        int st = setup_sys_element(tm, m, n, blocks + e * bsz, F, sigma + e * 4, W);
-        st |= tables_sys(tm, m, n, F, tab, kinds + e * kMaxN, tw, sh);
+        const int st = tables_sys(tm, m, n, factors + e * L.nf, tab, kinds + e * kMaxN, lds, sh);
         float* t32 = tab32 + e * L.ne;
         for (long t = threadIdx.x; t < L.ne; t += blockDim.x) t32[t] = (float)tab[t];
-        if (threadIdx.x == 0) status[e] = st;
+        if (threadIdx.x == 0) status[e] |= st;
         __syncthreads();
     }
 }
@@ -57,12 +72,67 @@ __global__ void __launch_bounds__(256) k_apply_sys(int64_t E, int nc, int n, int
     for (int t = threadIdx.x; t < md; t += blockDim.x) zv[t] = (double)X[t];
 }
 
+// one workgroup per element, the (m n)^2 entries row by row (coalesced stores)
+__global__ void __launch_bounds__(256) k_build_sys_blocks(int64_t E, int nc, int n, const Tables1D* tab,
+                                                          const double* recs, double* out) {
+    const long N = (long)nc * n * n;
+    const long rl = sys_rec_len(nc);
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        const double* rec = recs + e * rl;
+        double* A = out + e * N * N;
+        for (long t = threadIdx.x; t < N * N; t += blockDim.x) A[t] = sys_block_entry(nc, n, t / N, t % N, rec, *tab);
+    }
+}
+
+// y = blockdiag(A_e) x: one workgroup per element, x in LDS, one wave per row
+// (its 64 lanes read 64 consecutive entries per step), four rows at a time
+__global__ void __launch_bounds__(256) k_sys_operator(int64_t E, int N, const double* blocks, const double* x,
+                                                      double* y) {
+    extern __shared__ double xs[];
+    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        const double* xe = x + e * N;
+        for (int t = threadIdx.x; t < N; t += blockDim.x) xs[t] = xe[t];
+        __syncthreads();
+        const double* A = blocks + e * (int64_t)N * N;
+        for (int i = wv; i < N; i += 4) {
+            const double* row = A + (int64_t)i * N;
+            double acc = 0.0;
+            for (int a = lane; a < N; a += 64) acc += row[a] * xs[a];
+            acc = wave_sum(acc);
+            if (lane == 0) y[e * N + i] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_build_sys_blocks(hipStream_t s, int64_t E, int nc, int n, const Tables1D* tab, const double* recs,
+                                   double* out) {
+    if (E <= 0) return hipSuccess;
+    const int grid = (int)(E < 65536 ? E : 65536);
+    hipLaunchKernelGGL(k_build_sys_blocks, dim3(grid), dim3(256), 0, s, E, nc, n, tab, recs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sys_operator(hipStream_t s, int64_t E, int N, const double* blocks, const double* x, double* y) {
+    if (E <= 0) return hipSuccess;
+    const int grid = (int)(E < 65536 ? E : 65536);
+    hipLaunchKernelGGL(k_sys_operator, dim3(grid), dim3(256), N * sizeof(double), s, E, N, blocks, x, y);
+    return hipGetLastError();
+}
+
 hipError_t launch_setup_sys(hipStream_t s, int grid, int64_t E, int nc, int n, const double* blocks,
                             char* precond, double* ws, int64_t ws_stride) {
     if (E <= 0) return hipSuccess;
     SysLayout L;
     if (!sys_layout(nc, n, E, &L)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_setup_sys, dim3(grid), dim3(256), 0, s, E, nc, n, blocks, precond, L, ws, ws_stride);
+    hipLaunchKernelGGL(k_sys_ksvd, dim3(grid), dim3(256), 0, s, E, nc, n, blocks, precond, L, ws, ws_stride);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int m = nc * n;
+    const size_t lds = (size_t)sys_tables_work_doubles(m, n) * sizeof(double);
+    const int g2 = (int)(E < 65536 ? E : 65536);
+    hipLaunchKernelGGL(k_sys_tables, dim3(g2), dim3(256), lds, s, E, nc, n, precond, L);
     return hipGetLastError();
 }
 

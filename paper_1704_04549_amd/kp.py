@@ -78,6 +78,11 @@ def lib() -> ctypes.CDLL:
             "kp_setup_sys": ([vp, ctypes.POINTER(kp_sys_batch), vp, vp], ctypes.c_int),
             "kp_apply_sys": ([vp, ctypes.POINTER(kp_sys_batch), vp, i32, i32, vp, vp], ctypes.c_int),
             "kp_get_factors_sys": ([vp, ctypes.POINTER(kp_sys_batch), vp, vp, vp], ctypes.c_int),
+            "kp_build_sys_blocks": ([vp, i64, i32, i32, vp, vp], ctypes.c_int),
+            "kp_sys_operator_apply": ([vp, ctypes.POINTER(kp_sys_batch), vp, vp], ctypes.c_int),
+            "kp_sys_blockjacobi_exact": ([vp, ctypes.POINTER(kp_sys_batch), vp, vp, vp], ctypes.c_int),
+            "kp_fgmres_sys": ([vp, ctypes.POINTER(kp_sys_batch), i32, vp, vp, i32, vp, vp, i32, dbl, i32,
+                               ctypes.POINTER(i32), ctypes.POINTER(dbl)], ctypes.c_int),
             "kp_setup_from_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_get_factors": ([vp, bp, i32, vp, vp, vp], ctypes.c_int),
             "kp_apply": ([vp, bp, i32, vp, i32, i32, vp, vp], ctypes.c_int),
@@ -310,6 +315,46 @@ class Ctx:
         _check(lib().kp_get_factors_sys(self.h, ctypes.byref(s.c), _ptr(precond), _ptr(f), _ptr(sg)),
                "kp_get_factors_sys")
         return f, sg
+
+    def build_sys_blocks(self, nc: int, n: int, recs: torch.Tensor, out=None):
+        E = int(recs.shape[0]) if recs.numel() else 0
+        N = nc * n * n
+        if out is None:
+            out = torch.empty((E, N, N), dtype=torch.float64, device=self.device)
+        _check(lib().kp_build_sys_blocks(self.h, E, int(nc), int(n), _ptr(recs), _ptr(out)), "kp_build_sys_blocks")
+        return out
+
+    def sys_operator_apply(self, s: "SysBatch", x, y=None):
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().kp_sys_operator_apply(self.h, ctypes.byref(s.c), _ptr(x), _ptr(y)), "kp_sys_operator_apply")
+        return y
+
+    def sys_blockjacobi_exact(self, s: "SysBatch", lu=None, piv=None, status=None):
+        N = s.ndof
+        if lu is None:
+            lu = torch.empty((s.num_elems, N, N), dtype=torch.float64, device=self.device)
+        if piv is None:
+            piv = torch.empty((s.num_elems, N), dtype=torch.int32, device=self.device)
+        if status is None:
+            status = torch.empty(max(s.num_elems, 1), dtype=torch.int32, device=self.device)
+        _check(lib().kp_sys_blockjacobi_exact(self.h, ctypes.byref(s.c), _ptr(lu), _ptr(piv), _ptr(status)),
+               "kp_sys_blockjacobi_exact")
+        return lu, piv, status
+
+    def fgmres_sys(self, s: "SysBatch", rhs, pc_kind=KP_PC_KSVD, pc_data=None, pc_aux=None, pc_prec=KP_FP64,
+                   x=None, restart=30, rtol=1e-10, maxit=3000):
+        pc_prec = PREC.get(pc_prec, pc_prec)
+        if x is None:
+            x = torch.empty_like(rhs)
+        it = ctypes.c_int32(0)
+        rr = ctypes.c_double(0.0)
+        st = lib().kp_fgmres_sys(self.h, ctypes.byref(s.c), int(pc_kind), _ptr(pc_data), _ptr(pc_aux), int(pc_prec),
+                                 _ptr(rhs), _ptr(x), int(restart), float(rtol), int(maxit), ctypes.byref(it),
+                                 ctypes.byref(rr))
+        if st not in (KP_OK, KP_ERR_NOCONV):
+            raise KpError(st, "kp_fgmres_sys")
+        return dict(x=x, iters=it.value, relres=rr.value, converged=(st == KP_OK))
 
     def setup_from_factors(self, b: Batch, rank: int, factors: torch.Tensor, precond=None, status=None):
         if self.precond_bytes(b.dim, b.n, rank, 1) == 0:

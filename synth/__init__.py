@@ -247,11 +247,13 @@ def systems_elements(num_elems: int, nc: int, seed: int = SYSTEMS_SEED, tau: flo
                      face: bool = True) -> dict:
     """2D elements of an nc-component system (input data only): per element,
     drawn in order, for each axis a flux Jacobian J_i = R diag(lam) R^-1 with
-    R = I + 0.3 G (G ~ N(0,1)) and lam ~ U[-1,1]^nc (real eigenvalues, as for
-    the Euler equations), then log10 nu ~ U[-3,-1], alpha ~ U[0,0.5],
-    phi ~ U[0,2pi).  Also handed over, as a DG code's upwind flux would, the
-    positive parts (J_i)^+ = R diag(max(lam,0)) R^-1 and (-J_i)^+ of each
-    axis (outflow through the high and the low face)."""
+    R = I + 0.3 G (G ~ N(0,1), drawn again while cond(R) > 10: the Euler
+    Jacobians' eigenvector matrices are well conditioned) and
+    lam ~ U[-1,1]^nc (real eigenvalues, as for the Euler equations), then
+    log10 nu ~ U[-3,-1], alpha ~ U[0,0.5], phi ~ U[0,2pi).  Also handed over,
+    as a DG code's upwind flux would, the positive parts
+    (J_i)^+ = R diag(max(lam,0)) R^-1 and (-J_i)^+ of each axis (outflow
+    through the high and the low face)."""
     rng = np.random.default_rng(seed)
     E = num_elems
     J = np.zeros((E, 2, nc, nc))
@@ -263,6 +265,8 @@ def systems_elements(num_elems: int, nc: int, seed: int = SYSTEMS_SEED, tau: flo
     for e in range(E):
         for ax in range(2):
             R = np.eye(nc) + 0.3 * rng.standard_normal((nc, nc))
+            while np.linalg.cond(R) > 10.0:
+                R = np.eye(nc) + 0.3 * rng.standard_normal((nc, nc))
             lam = 2.0 * rng.random(nc) - 1.0
             Ri = np.linalg.inv(R)
             J[e, ax] = R @ np.diag(lam) @ Ri
@@ -273,3 +277,37 @@ def systems_elements(num_elems: int, nc: int, seed: int = SYSTEMS_SEED, tau: flo
         alpha[e] = 0.5 * u[1]
         phi[e] = 2.0 * np.pi * u[2]
     return dict(nc=nc, tau=tau, face=face, J=J, Jp=Jp, Jm=Jm, nu=nu, alpha=alpha, phi=phi)
+
+
+def systems_records(sd: dict) -> np.ndarray:
+    """The drawn systems elements packed as records [E][6 nc^2 + 5]: Jx, Jy,
+    (Jx)^+, (Jy)^+, (-Jx)^+, (-Jy)^+ (nc x nc row-major each), nu, alpha,
+    phi, tau, face flag (the layout the library's systems block builder reads)."""
+    E, nc = sd["J"].shape[0], sd["nc"]
+    q = nc * nc
+    rec = np.zeros((E, 6 * q + 5))
+    for e in range(E):
+        mats = (sd["J"][e, 0], sd["J"][e, 1], sd["Jp"][e, 0], sd["Jp"][e, 1], sd["Jm"][e, 0], sd["Jm"][e, 1])
+        for k, M in enumerate(mats):
+            rec[e, k * q:(k + 1) * q] = M.ravel()
+        rec[e, 6 * q:] = (sd["nu"][e], sd["alpha"][e], sd["phi"][e], sd["tau"], 1.0 if sd["face"] else 0.0)
+    return rec
+
+
+SYSTEMS_RHS_SEED = 2007
+
+
+def systems_workload(name: str = "sys_kh_p7", num_elems: int | None = None) -> dict:
+    """The systems workload: 2D, nc = 4 components (the 2D Euler equations'
+    count), p = 7 (n = 8: first factors 32 x 32, the largest nc n <= 32),
+    128 x 128 = 16384 elements (the size of the paper's 2D Kelvin-Helmholtz
+    mesh), each element closed by its own upwind faces (block-diagonal
+    system), tau = 0.01 (the smaller of the paper's two Euler time steps);
+    one N(0,1) right-hand side per element."""
+    if name != "sys_kh_p7":
+        raise KeyError(name)
+    nc, n = 4, 8
+    E = 16384 if num_elems is None else num_elems
+    sd = systems_elements(E, nc, seed=SYSTEMS_SEED, tau=0.01)
+    return dict(name=name, nc=nc, n=n, num_elems=E, sd=sd, recs=systems_records(sd),
+                rhs=draw_rhs(E, 1, nc * n * n, SYSTEMS_RHS_SEED))

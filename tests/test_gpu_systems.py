@@ -8,7 +8,9 @@ and 5e-5 (FP32) of the oracle's dense solve of P, two right-hand sides, ragged
 batch sizes that span several workgroups of the persistent setup grid.  The
 "small" variant (the nc diagonal component blocks, Sec. 5.6) runs through
 the scalar explicit-block setup and apply against the oracle's KSVD of each
-component block.
+component block.  The block builder against the oracle's assembly (1e-14),
+the block-diagonal operator and exact block Jacobi against numpy, and
+FGMRES(30) iteration counts against the oracle's FGMRES (within one).
 """
 import numpy as np
 import pytest
@@ -110,3 +112,70 @@ def test_small_component_blocks_through_scalar_setup(ctx, nc, n):
         for j in range(2):
             assert rel(align_sign(F[i, 2 * j], f["A"][j]), f["A"][j]) <= 1e-10
         assert rel(z[i], dense_solve(f, r[i])) <= 1e-12
+
+
+@pytest.mark.parametrize("nc,n,E", [(2, 4, 5), (4, 8, 3), (3, 5, 4), (1, 6, 2)])
+def test_build_sys_blocks_matches_oracle(ctx, nc, n, E):
+    """kp_build_sys_blocks from the packed records against the oracle's
+    assembly of the same weak form (faces on and off)."""
+    from tests.gpu_util import to_dev
+    print(f"systems blocks nc={nc} n={n} E={E}", flush=True)
+    for face in (True, False):
+        sd = synth.systems_elements(E, nc, seed=70 + nc + n, face=face)
+        recs = synth.systems_records(sd)
+        A = ctx.build_sys_blocks(nc, n, to_dev(recs)).cpu().numpy()
+        for e in range(E):
+            Ar = systems.element_block(sd, e, n)
+            assert np.max(np.abs(A[e] - Ar)) <= 1e-14 * np.abs(Ar).max()
+
+
+def test_sys_operator_and_block_jacobi(ctx):
+    from paper_1704_04549_amd import kp
+    from tests.gpu_util import rel, to_dev
+    nc, n, E = 4, 6, 5
+    A = sys_blocks(nc, n, E, seed=81)
+    sb = kp.SysBatch(nc, n, to_dev(A))
+    x = np.random.default_rng(2).standard_normal((E, nc * n * n))
+    y = ctx.sys_operator_apply(sb, to_dev(x)).cpu().numpy()
+    assert rel(y, np.einsum("eij,ej->ei", A, x)) <= 1e-14
+    lu, piv, st = ctx.sys_blockjacobi_exact(sb)
+    assert int(st[:E].abs().sum()) == 0
+    r = to_dev(x)
+    out = ctx.fgmres_sys(sb, r, pc_kind=kp.KP_PC_BJ, pc_data=lu, pc_aux=piv, rtol=1e-12)
+    zr = np.stack([np.linalg.solve(A[e], x[e]) for e in range(E)])
+    assert out["converged"] and out["iters"] <= 2
+    assert rel(out["x"].cpu().numpy(), zr) <= 1e-10
+
+
+@pytest.mark.parametrize("nc,n,E,face", [(4, 6, 6, True), (4, 8, 4, True), (2, 8, 5, False)])
+def test_sys_fgmres_iterations_match_oracle(ctx, nc, n, E, face):
+    """FGMRES(30) to 1e-10 on the block-diagonal systems operator with the
+    systems KSVD preconditioner: the GPU's FP64 count within one of the
+    oracle's FGMRES with the oracle's preconditioner (dense solve of P), the
+    FP32 apply within one of the FP64 count, the solution against a dense
+    solve."""
+    from oracle.krylov import fgmres
+    from paper_1704_04549_amd import kp
+    from tests.gpu_util import rel, to_dev
+    print(f"systems fgmres nc={nc} n={n} E={E} face={face}", flush=True)
+    sd = synth.systems_elements(E, nc, seed=90 + n, face=face)
+    A = np.stack([systems.element_block(sd, e, n) for e in range(E)])
+    N = nc * n * n
+    rhs = np.random.default_rng(n).standard_normal(E * N)
+    fs = [systems.ksvd_system(A[e], nc, n, 2) for e in range(E)]
+    Aop = lambda v: np.einsum("eij,ej->ei", A, v.reshape(E, N)).ravel()
+    Mop = lambda v: np.concatenate([dense_solve(fs[e], v.reshape(E, N)[e]) for e in range(E)])
+    _, it_ref, _, conv = fgmres(Aop, Mop, rhs, m=30, rtol=1e-10)
+    assert conv
+    sb = kp.SysBatch(nc, n, to_dev(A))
+    pc, st = ctx.setup_sys(sb)
+    assert int(st.abs().sum()) == 0
+    r = to_dev(rhs)
+    o64 = ctx.fgmres_sys(sb, r, pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec="fp64")
+    o32 = ctx.fgmres_sys(sb, r, pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec="fp32")
+    print(f"  iters oracle {it_ref} fp64 {o64['iters']} fp32 {o32['iters']}", flush=True)
+    assert o64["converged"] and o32["converged"]
+    assert abs(o64["iters"] - it_ref) <= 1
+    assert o32["iters"] <= o64["iters"] + 1
+    xr = np.concatenate([np.linalg.solve(A[e], rhs.reshape(E, N)[e]) for e in range(E)])
+    assert rel(o64["x"].cpu().numpy(), xr) <= 1e-8
