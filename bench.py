@@ -213,7 +213,7 @@ def bench_systems(args):
         def one(e):
             # the element's own slice of the drawn data (small to pass to a worker)
             return {k: (v[e:e + 1] if isinstance(v, np.ndarray) else v) for k, v in sd.items()}
-        order = list(dict.fromkeys(np.linspace(0, E - 1, 2048).astype(int).tolist()))
+        order = list(dict.fromkeys(np.linspace(0, E - 1, E).astype(int).tolist()))
         try:
             avail = len(os.sched_getaffinity(0))
         except AttributeError:
@@ -322,8 +322,8 @@ def bench_systems(args):
         "apply_ms": t_apply,
         "apply_ms_fp64": t_apply64,
         "fgmres_solve_ms": solve_ms,
-        "roofline": {"kernel": "setup (k_sys_ksvd + k_sys_tables: Gram, Lanczos, factors, inverses, "
-                               "Schur forms, column inverses)",
+        "roofline": {"kernel": "setup (k_sys_ksvd, k_sys_rotation, k_sys_tables: Gram, Lanczos, factors, "
+                               "pair rotation, inverses, Schur forms, column inverses)",
                      "bound": "alu", "achieved": round(setup_tf, 3), "peak": 78.6, "unit": "TFLOP/s",
                      "frac": round(setup_tf / 78.6, 5), "traffic": None,
                      "algorithmic_flops": setup_flops, "block_bytes_read": block_bytes,

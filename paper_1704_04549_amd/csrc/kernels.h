@@ -100,11 +100,12 @@ hipError_t launch_setup_quad(hipStream_t s, int grid, int64_t E, int dim, int n,
                              int64_t ws_stride);
 
 // systems blocks (sys.h, sys.hip): setup with one workgroup per element over
-// grid workspace slots of ws_stride doubles; apply with one workgroup per
+// grid workspace slots of ws_stride doubles (angle: E int32 scratch for the
+// pair rotations); apply with one workgroup per
 // (element, right-hand side) in FP64 (prec 0) or FP32 (prec 1) tables and
 // arithmetic
 hipError_t launch_setup_sys(hipStream_t s, int grid, int64_t E, int nc, int n, const double* blocks,
-                            char* precond, double* ws, int64_t ws_stride);
+                            char* precond, double* ws, int64_t ws_stride, int32_t* angle);
 hipError_t launch_build_sys_blocks(hipStream_t s, int64_t E, int nc, int n, const Tables1D* tab, const double* recs,
                                    double* out);
 hipError_t launch_sys_operator(hipStream_t s, int64_t E, int N, const double* blocks, const double* x, double* y);

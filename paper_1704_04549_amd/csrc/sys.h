@@ -374,12 +374,170 @@ KP_INLINE bool qt_inverse_col_c(int m, const double* M, double sr, double si, in
     return ok;
 }
 
+// The angle index k (angle pi k / 8, k < 8) minimising
+// kappa_1(-s A1 + c A2) kappa_1(c B1 + s B2) (lowest k on ties); W0, W1, W2:
+// m x m scratch, mult: kMaxN doubles.
+template <class Team>
+KP_HD int sys_rotation_angle(const Team& tm, int m, int n, const double* A1, const double* A2, const double* B1,
+                             const double* B2, double* W0, double* W1, double* W2, double* mult, double* sh) {
+    const long ma = (long)m * m, nb = (long)n * n;
+    const double pi = 3.14159265358979323846;
+    double best = -1.0;
+    int bestk = 0;
+    for (int k = 0; k < 8; ++k) {
+        const double c = cos(pi * k / 8.0), sn = sin(pi * k / 8.0);
+        for (long t = tm.tid(); t < ma; t += tm.size()) W0[t] = -sn * A1[t] + c * A2[t];
+        for (long t = tm.tid(); t < nb; t += tm.size()) W2[t] = c * B1[t] + sn * B2[t];
+        tm.sync();
+        double score = 1.0;
+        for (int q = 0; q < 2; ++q) {
+            const int sz = q == 0 ? m : n;
+            double* M = q == 0 ? W0 : W2;
+            const double nm = norm1(tm, sz, M, sh);
+            const bool ok = invert(tm, sz, M, W1, nullptr, mult);
+            const double ni = norm1(tm, sz, W1, sh);
+            score *= ok ? nm * ni : 1e300;
+        }
+        if (!(score == score)) score = 1e300;
+        if (best < 0.0 || score < best) {
+            best = score;
+            bestk = k;
+        }
+    }
+    return bestk;
+}
+#if defined(__HIPCC__)
+// kappa_1 = ||M||_1 ||M^-1||_1 of the sz x sz matrix (sz <= 32) whose row i
+// lane i of the calling 32-lane group holds in a[]: Gauss-Jordan in place
+// with partial pivoting in registers (one row per lane, the pivot row
+// broadcast through the group's LDS slot of 32 doubles).  The rows are never
+// swapped, so a[] ends as M^-1 with its rows and columns permuted, which
+// leaves the largest column sum unchanged.  The same value on every lane of
+// the group, 1e300 if a pivot column is zero.
+// largest column sum of |row| over the 32-lane group (lane i holding row i,
+// inactive lanes zero) for columns < sz: a halving exchange leaves lane l
+// with the sum of column l (each step sends the half the partner keeps),
+// then a maximum over the lanes.
+__device__ __forceinline__ double grp32_max_colsum(const double (&a)[32], bool act, int sz) {
+    const int lane = (int)(threadIdx.x & 31);
+    double v[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) v[j] = act ? fabs(a[j]) : 0.0;
+#pragma unroll
+    for (int h = 16; h > 0; h >>= 1) {
+        const bool up = (lane & h) != 0;
+#pragma unroll
+        for (int t = 0; t < h; ++t) {
+            const double send = up ? v[t] : v[h + t];
+            const double keep = up ? v[h + t] : v[t];
+            v[t] = keep + __shfl_xor(send, h, 32);
+        }
+    }
+    double mx = lane < sz ? v[0] : 0.0;
+    for (int off = 16; off > 0; off >>= 1) {
+        const double o = __shfl_xor(mx, off, 32);
+        mx = o > mx ? o : mx;
+    }
+    return mx;
+}
+
+__device__ __forceinline__ double grp32_kappa1(int sz, double (&a)[32], double* sl) {
+    const int i = (int)(threadIdx.x & 31);
+    const bool act = i < sz;
+    const double nm = grp32_max_colsum(a, act, sz);
+    bool used = false, ok = true;
+#pragma unroll 1
+    for (int k = 0; k < sz; ++k) {
+        double ak = 0.0;
+#pragma unroll
+        for (int j = 0; j < 32; ++j)
+            if (j == k) ak = a[j];
+        double v = (act && !used) ? fabs(ak) : -1.0;
+        int p = i;
+        for (int off = 16; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(v, off, 32);
+            const int op = __shfl_xor(p, off, 32);
+            if (ov > v || (ov == v && op < p)) {
+                v = ov;
+                p = op;
+            }
+        }
+        const bool sing = !(v > 0.0);
+        if (sing) ok = false;
+        const bool piv = act && !sing && i == p;
+        if (piv) {
+            // the pivot row: column k becomes 1 / pivot, the rest scaled by it
+            const double inv = 1.0 / ak;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                a[j] = (j == k) ? inv : a[j] * inv;
+                sl[j] = a[j];
+            }
+            used = true;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (act && !sing && !piv) {
+            // every other row: subtract its multiple; column k becomes -f / pivot
+#pragma unroll
+            for (int j = 0; j < 32; ++j) a[j] = (j == k) ? -ak * sl[j] : a[j] - ak * sl[j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    const double ni = grp32_max_colsum(a, act, sz);
+    const double kap = nm * ni;
+    return (ok && kap == kap) ? kap : 1e300;
+}
+
+// The angle search of tables_sys for one element's factors F (as stored:
+// A1, B1, A2, B2) by a workgroup of 256 threads: the eight angles at once, one
+// 32-lane group each, the balanced rotated factors built in registers and
+// each candidate inverted there.  Returns the angle index on every thread.
+__device__ inline int sys_angle_search_grp(const BlockTeam& tm, int m, int n, const double* F) {
+    __shared__ double slots[8 * 32];
+    __shared__ double score[8];
+    const long ma = (long)m * m, nb = (long)n * n;
+    const double *F1 = F, *G1 = F + ma, *F2 = F + ma + nb, *G2 = F + 2 * ma + nb;
+    double p1 = 0.0, p2 = 0.0;
+    for (long t = threadIdx.x; t < ma; t += blockDim.x) {
+        p1 += F1[t] * F1[t];
+        p2 += F2[t] * F2[t];
+    }
+    const double s1 = sqrt(tm.sum(p1)), s2 = sqrt(tm.sum(p2));
+    const double a1 = s1 > 0.0 ? s1 : 1.0, a2 = s2 > 0.0 ? s2 : 1.0;
+    const int g = (int)(threadIdx.x >> 5), i = (int)(threadIdx.x & 31);
+    const double pi = 3.14159265358979323846;
+    const double c = cos(pi * g / 8.0), sn = sin(pi * g / 8.0);
+    double a[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+        a[j] = (i < m && j < m) ? -sn * (F1[i * m + j] / a1) + c * (F2[i * m + j] / a2) : 0.0;
+    const double kl = grp32_kappa1(m, a, slots + g * 32);
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+        a[j] = (i < n && j < n) ? c * (G1[i * n + j] * a1) + sn * (G2[i * n + j] * a2) : 0.0;
+    const double kr = grp32_kappa1(n, a, slots + g * 32);
+    double sc = kl * kr;
+    if (!(sc == sc) || kl >= 1e300 || kr >= 1e300) sc = 1e300;
+    if (i == 0) score[g] = sc;
+    tm.sync();
+    int bestk = 0;
+    for (int k = 1; k < 8; ++k)
+        if (score[k] < score[bestk]) bestk = k;
+    tm.sync();
+    return bestk;
+}
+#endif
+
 // inversion data of one element.  work: sys_tables_work_doubles(m, n)
-// doubles; sh: kMaxN + 8 shared doubles.  Returns the element status bits
-// (2 singular factor, 4 Schur not converged, 8 non-finite tables).
+// doubles; sh: kMaxN + 8 shared doubles; rot_k: the pair rotation's angle
+// index if already chosen (sys_angle_search_grp), else -1 (searched here).
+// Returns the element status bits (2 singular factor, 4 Schur not
+// converged, 8 non-finite tables).
 template <class Team>
 KP_HD int tables_sys(const Team& tm, int m, int n, const double* F, double* tab, int8_t* kinds, double* work,
-                     double* sh) {
+                     double* sh, int rot_k = -1) {
     const long ma = (long)m * m, nb = (long)n * n;
     const SysTab o = sys_tab(m, n);
     double* W0 = work;
@@ -419,28 +577,7 @@ KP_HD int tables_sys(const Team& tm, int m, int n, const double* F, double* tab,
         }
         tm.sync();
         const double pi = 3.14159265358979323846;
-        double best = -1.0;
-        int bestk = 0;
-        for (int k = 0; k < 8; ++k) {
-            const double c = cos(pi * k / 8.0), sn = sin(pi * k / 8.0);
-            for (long t = tm.tid(); t < ma; t += tm.size()) W0[t] = -sn * A1[t] + c * A2[t];
-            for (long t = tm.tid(); t < nb; t += tm.size()) W2[t] = c * B1[t] + sn * B2[t];
-            tm.sync();
-            double score = 1.0;
-            for (int q = 0; q < 2; ++q) {
-                const int sz = q == 0 ? m : n;
-                double* M = q == 0 ? W0 : W2;
-                const double nm = norm1(tm, sz, M, sh);
-                const bool ok = invert(tm, sz, M, W1, nullptr, mult);
-                const double ni = norm1(tm, sz, W1, sh);
-                score *= ok ? nm * ni : 1e300;
-            }
-            if (!(score == score)) score = 1e300;
-            if (best < 0.0 || score < best) {
-                best = score;
-                bestk = k;
-            }
-        }
+        const int bestk = rot_k >= 0 ? rot_k : sys_rotation_angle(tm, m, n, A1, A2, B1, B2, W0, W1, W2, mult, sh);
         const double c = cos(pi * bestk / 8.0), sn = sin(pi * bestk / 8.0);
         for (long t = tm.tid(); t < ma; t += tm.size()) {
             const double l1 = A1[t], l2 = A2[t];

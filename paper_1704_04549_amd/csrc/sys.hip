@@ -28,9 +28,24 @@ __global__ void __launch_bounds__(256) k_sys_ksvd(int64_t E, int nc, int n, cons
     }
 }
 
+// the pair rotation's angle of every element (sys_angle_search_grp)
+__global__ void __launch_bounds__(256) k_sys_rotation(int64_t E, int nc, int n, const char* pc, SysLayout L,
+                                                      int32_t* angle) {
+    __shared__ double red[4 * kMaxReduce];
+    BlockTeam tm{red};
+    const int m = nc * n;
+    const double* factors = (const double*)(pc + L.factors);
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        const int k = sys_angle_search_grp(tm, m, n, factors + e * L.nf);
+        if (threadIdx.x == 0) angle[e] = k;
+        __syncthreads();
+    }
+}
+
 // inversion data with its work matrices in LDS (sys_tables_work_doubles
 // doubles of dynamic LDS), then the FP32 copy of the element's tables
-__global__ void __launch_bounds__(256) k_sys_tables(int64_t E, int nc, int n, char* pc, SysLayout L) {
+__global__ void __launch_bounds__(256) k_sys_tables(int64_t E, int nc, int n, char* pc, SysLayout L,
+                                                    const int32_t* angle) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
     __shared__ double sh[kMaxN + 8];
@@ -43,7 +58,7 @@ __global__ void __launch_bounds__(256) k_sys_tables(int64_t E, int nc, int n, ch
     int8_t* kinds = (int8_t*)(pc + L.kinds);
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         double* tab = tab64 + e * L.ne;
-        const int st = tables_sys(tm, m, n, factors + e * L.nf, tab, kinds + e * kMaxN, lds, sh);
+        const int st = tables_sys(tm, m, n, factors + e * L.nf, tab, kinds + e * kMaxN, lds, sh, angle[e]);
         float* t32 = tab32 + e * L.ne;
         for (long t = threadIdx.x; t < L.ne; t += blockDim.x) t32[t] = (float)tab[t];
         if (threadIdx.x == 0) status[e] |= st;
@@ -122,17 +137,19 @@ hipError_t launch_sys_operator(hipStream_t s, int64_t E, int N, const double* bl
 }
 
 hipError_t launch_setup_sys(hipStream_t s, int grid, int64_t E, int nc, int n, const double* blocks,
-                            char* precond, double* ws, int64_t ws_stride) {
+                            char* precond, double* ws, int64_t ws_stride, int32_t* angle) {
     if (E <= 0) return hipSuccess;
     SysLayout L;
     if (!sys_layout(nc, n, E, &L)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sys_ksvd, dim3(grid), dim3(256), 0, s, E, nc, n, blocks, precond, L, ws, ws_stride);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
+    const int g2 = (int)(E < 65536 ? E : 65536);
+    hipLaunchKernelGGL(k_sys_rotation, dim3(g2), dim3(256), 0, s, E, nc, n, precond, L, angle);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
     const int m = nc * n;
     const size_t lds = (size_t)sys_tables_work_doubles(m, n) * sizeof(double);
-    const int g2 = (int)(E < 65536 ? E : 65536);
-    hipLaunchKernelGGL(k_sys_tables, dim3(g2), dim3(256), lds, s, E, nc, n, precond, L);
+    hipLaunchKernelGGL(k_sys_tables, dim3(g2), dim3(256), lds, s, E, nc, n, precond, L, angle);
     return hipGetLastError();
 }
 

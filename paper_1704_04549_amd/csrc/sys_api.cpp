@@ -34,9 +34,12 @@ kp_status kp_setup_sys(kp_ctx c, const kp_sys_batch* b, void* precond, int32_t* 
     const int m = b->nc * b->n;
     const int64_t wsd = (sys_work_doubles(m, b->n) + 31) / 32 * 32;
     const int grid = (int)(E < 2048 ? E : 2048);
-    if ((st = ensure_ws(c, (size_t)wsd * grid * sizeof(double), &c->ws, &c->ws_bytes)) != KP_OK) return st;
+    if ((st = ensure_ws(c, (size_t)wsd * grid * sizeof(double) + (size_t)E * sizeof(int32_t), &c->ws,
+                        &c->ws_bytes)) != KP_OK)
+        return st;
     char* pc = (char*)precond;
-    KP_HIP(launch_setup_sys(c->stream, grid, E, b->nc, b->n, b->blocks, pc, (double*)c->ws, wsd));
+    KP_HIP(launch_setup_sys(c->stream, grid, E, b->nc, b->n, b->blocks, pc, (double*)c->ws, wsd,
+                            (int32_t*)((double*)c->ws + (size_t)wsd * grid)));
     if (elem_status)
         KP_HIP(hipMemcpyAsync(elem_status, pc + L.status, E * sizeof(int32_t), hipMemcpyDeviceToDevice,
                               c->stream));
