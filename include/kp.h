@@ -18,7 +18,8 @@
  *   and the static scratch array of kp_setup_noalloc.
  * - Work is enqueued on the context's HIP stream; only kp_fgmres and
  *   kp_blockjacobi_exact synchronise (kp_fgmres once per Arnoldi step to read
- *   the Givens residual, kp_blockjacobi_exact never except on error).
+ *   the Givens residual, or once per restart cycle under KP_OPT_FGMRES_GRAPHS;
+ *   kp_blockjacobi_exact never except on error).
  * - Nodal vectors are C-ordered with x slowest: u[(i*n + j)*n + k].  The
  *   first Kronecker factor acts on x.
  * - Argument errors (null pointers, n outside [2,32], dim not 2 or 3, rank
@@ -110,12 +111,17 @@ kp_status kp_destroy(kp_ctx ctx);
 kp_status kp_set_stream(kp_ctx ctx, void* stream);
 
 /* Context options (kp_set_option):
- *   KP_OPT_FGMRES_GRAPHS (default 0): run every Arnoldi step of kp_fgmres /
- *     kp_mixed_fgmres as a HIP graph (preconditioner, operator, both
- *     Gram-Schmidt passes, the norm and the copies of the projections into
- *     pinned host memory), captured once per solve on a private stream and
- *     replayed every restart cycle; the same kernels in the same order as
- *     without graphs.  A step that cannot be captured runs without graphs.
+ *   KP_OPT_FGMRES_GRAPHS (default 0): run every restart cycle of kp_fgmres /
+ *     kp_mixed_fgmres / kp_fgmres_sys as one HIP graph (per Arnoldi step the
+ *     preconditioner, the operator, both Gram-Schmidt passes, the norm and the
+ *     normalisation of the next basis vector on the device; then one copy of
+ *     the cycle's projections into pinned host memory), captured once per
+ *     solve on a private stream and replayed every cycle, with one
+ *     synchronisation per cycle instead of one per step.  The host applies the
+ *     Givens rotations to the cycle's columns afterwards and stops at the same
+ *     column as without graphs, so iterations and solution are the same; the
+ *     last cycle's steps after that column run without effect.  A cycle that
+ *     cannot be captured runs without graphs.
  *   KP_OPT_APPLY_MFMA16 (default 1): the matrix-core apply for n = 16; 0
  *     selects the generic per-element kernel.
  *   KP_OPT_FGMRES_Z32 (default 1): kp_fgmres keeps the preconditioned basis
@@ -410,10 +416,11 @@ kp_status kp_operator_apply(kp_ctx ctx, const kp_batch* b, const double* x, doub
  * when the residual estimate is <= rtol*||rhs|| and the true residual
  * recomputed at the restart confirms it, or after maxit Arnoldi steps (then
  * KP_ERR_NOCONV; x holds the last iterate).  Synchronises once per Arnoldi
- * step.  iters_h, relres_h: host scalars (final true relative residual);
- * hist_h: host array of hist_len per-step relative residual estimates, or
- * NULL.  Workspace: (2*restart + 3) * E * n^d doubles (the basis Z in FP32
- * under KP_OPT_FGMRES_Z32: restart/2 fewer), owned by ctx. */
+ * step (once per cycle under KP_OPT_FGMRES_GRAPHS).  iters_h, relres_h: host
+ * scalars (final true relative residual); hist_h: host array of hist_len
+ * per-step relative residual estimates, or NULL.  Workspace:
+ * (2*restart + 3) * E * n^d doubles (the basis Z in FP32 under
+ * KP_OPT_FGMRES_Z32: restart/2 fewer), owned by ctx. */
 kp_status kp_fgmres(kp_ctx ctx, const kp_batch* b, int32_t pc_kind, int32_t rank,
                     const void* pc_data, const void* pc_aux, int32_t pc_prec, const double* rhs,
                     double* x, int32_t restart, double rtol, int32_t maxit, int32_t* iters_h,

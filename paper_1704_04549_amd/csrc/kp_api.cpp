@@ -584,11 +584,13 @@ kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, con
     if (relres_h) *relres_h = 0.0;
     if (N == 0) return KP_OK;
     // workspace: V (m+1) N, Z m N (FP64, or FP32 with z32), w N, r N,
-    // partial, h (2 (m+2)), y (m)
+    // partial, h (2 (m+2)), y (m), and per step of a cycle its projection
+    // slots (2 (m+2) each, used by the cycle graph)
     const size_t vec = (size_t)N + (N & 1);  // vector stride: even, so every vector is 16-byte aligned
     const size_t part = (size_t)kVecBlocks * (m + 2);
     const size_t zd = z32 ? ((size_t)m * vec + 1) / 2 : (size_t)m * vec;  // Z in doubles
-    const size_t need = ((m + 3) * vec + zd + part + 3 * (size_t)(m + 2)) * sizeof(double);
+    const size_t pslot = 2 * (size_t)(m + 2);
+    const size_t need = ((m + 3) * vec + zd + part + 3 * (size_t)(m + 2) + (size_t)m * pslot) * sizeof(double);
     if ((st = ensure_ws(c, need, &c->ks, &c->ks_bytes)) != KP_OK) return st;
     double* V = (double*)c->ks;
     double* Z = V + (m + 1) * vec;
@@ -599,39 +601,41 @@ kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, con
     double* hd = partial + part;   // m + 2
     double* h2 = hd + (m + 2);     // m + 2
     double* yd = h2 + (m + 2);     // m + 2
+    double* proj = yd + (m + 2);   // m slots of 2 (m + 2)
     hipStream_t s = c->stream;
     // host Hessenberg and Givens state
     double H[201 * 200], cs[200], sn[200], g[201], hh_local[202];
     double* hh = hh_local;
-    // graph mode: step j (preconditioner, operator, both Gram-Schmidt passes,
-    // the norm and the copies of the projections) is captured once per solve
-    // into graphs[j] and replayed every restart cycle
+    // graph mode: a whole restart cycle (m Arnoldi steps: preconditioner,
+    // operator, both Gram-Schmidt passes, the norm, the normalisation of the
+    // next basis vector on the device, each step's projections in its own
+    // slot, then one copy of all of them into pinned host memory) is captured
+    // once per solve and replayed every cycle; the host then runs the Givens
+    // rotations over the cycle's columns exactly as the step-by-step solve
+    // does and stops at the same column, so the iterate is the same.  Steps
+    // after that column (in the last cycle only) run without effect on it.
     bool graphs = c->use_graphs;
-    std::vector<hipGraphExec_t> execs;
+    hipGraphExec_t exec = nullptr;
     if (graphs) {
+        const size_t pin = (size_t)m * pslot;
         if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
             graphs = false;
-        if (graphs && c->pinned_doubles < 202) {
+        if (graphs && c->pinned_doubles < pin) {
             if (c->pinned) hipHostFree(c->pinned);
             c->pinned = nullptr;
             c->pinned_doubles = 0;
-            if (hipHostMalloc((void**)&c->pinned, 202 * sizeof(double)) == hipSuccess)
-                c->pinned_doubles = 202;
+            if (hipHostMalloc((void**)&c->pinned, pin * sizeof(double)) == hipSuccess)
+                c->pinned_doubles = pin;
             else
                 graphs = false;
         }
-        if (graphs) {
-            hh = c->pinned;
-            execs.assign(m, nullptr);
-        }
     }
     struct ExecGuard {
-        std::vector<hipGraphExec_t>* v;
+        hipGraphExec_t* e;
         ~ExecGuard() {
-            for (auto& e : *v)
-                if (e) hipGraphExecDestroy(e);
+            if (*e) hipGraphExecDestroy(*e);
         }
-    } guard{&execs};
+    } guard{&exec};
     double nb2 = 0.0;
     KP_HIP(launch_mdot(s, rhs, 0, 1, rhs, N, partial, hd, 0));
     KP_HIP(hipMemcpyAsync(&nb2, hd, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -643,86 +647,107 @@ kp_status fgmres_core(kp_ctx c, int64_t N, const VecFn& op, const VecFn& pc, con
     double beta = nb;
     int iters = 0;
     bool converged = false;
+    // step j's device work on c->stream: z_j = M v_j, w = A z_j, CGS2 (the
+    // first pass's projections in pa, the second's and then ||w||^2 in pb)
+    auto step = [&](int j, double* pa, double* pb) -> kp_status {
+        kp_status s2;
+        hipStream_t q = c->stream;
+        double* vj = V + j * vec;
+        if (z32) {
+            float* zj32 = Z32 + j * vec;
+            if ((s2 = z32->pc(vj, zj32)) != KP_OK) return s2;
+            if ((s2 = z32->op(zj32, w)) != KP_OK) return s2;
+        } else {
+            double* zj = Z + j * vec;
+            if ((s2 = pc(vj, zj)) != KP_OK) return s2;
+            if ((s2 = op(zj, w)) != KP_OK) return s2;
+        }
+        KP_HIP(launch_mdot(q, V, vec, j + 1, w, N, partial, pa, 0));
+        KP_HIP(launch_mgs_update(q, V, vec, j + 1, pa, w, N));
+        KP_HIP(launch_mdot(q, V, vec, j + 1, w, N, partial, pb, 0));
+        KP_HIP(launch_mgs_update(q, V, vec, j + 1, pb, w, N));
+        KP_HIP(launch_mdot(q, w, 0, 1, w, N, partial, pb + j + 1, 0));
+        return KP_OK;
+    };
+    // column j from the two passes' projections and the norm: Givens
+    // rotations, residual estimate; returns true where the cycle stops
+    int k = 0;
+    double hn = 0.0;
+    auto column = [&](int j, const double* pa, const double* pb) -> bool {
+        double* col = H + j * (m + 1);
+        for (int i = 0; i <= j; ++i) col[i] = pa[i] + pb[i];
+        hn = sqrt(fmax(pb[j + 1], 0.0));
+        col[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+            const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+            col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+            col[i] = t;
+        }
+        const double den = hypot(col[j], col[j + 1]);
+        cs[j] = den > 0.0 ? col[j] / den : 1.0;
+        sn[j] = den > 0.0 ? col[j + 1] / den : 0.0;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++iters;
+        k = j + 1;
+        if (hist_h && iters <= hist_len) hist_h[iters - 1] = fabs(g[j + 1]) / nb;
+        return fabs(g[j + 1]) <= rtol * nb || iters >= maxit || hn == 0.0;
+    };
     while (true) {
         KP_HIP(launch_axpby(s, V, r, 1.0 / beta, nullptr, 0.0, N));
         for (int i = 0; i <= m; ++i) g[i] = 0.0;
         g[0] = beta;
-        int k = 0;
-        for (int j = 0; j < m; ++j) {
-            double* vj = V + j * vec;
-            double* zj = Z + j * vec;
-            float* zj32 = Z32 + j * vec;
-            // the step's device work, enqueued on c->stream
-            auto step = [&]() -> kp_status {
-                kp_status s2;
-                hipStream_t q = c->stream;
-                if (z32) {
-                    if ((s2 = z32->pc(vj, zj32)) != KP_OK) return s2;
-                    if ((s2 = z32->op(zj32, w)) != KP_OK) return s2;
-                } else {
-                    if ((s2 = pc(vj, zj)) != KP_OK) return s2;
-                    if ((s2 = op(zj, w)) != KP_OK) return s2;
-                }
-                // classical Gram-Schmidt, twice
-                KP_HIP(launch_mdot(q, V, vec, j + 1, w, N, partial, hd, 0));
-                KP_HIP(launch_mgs_update(q, V, vec, j + 1, hd, w, N));
-                KP_HIP(launch_mdot(q, V, vec, j + 1, w, N, partial, h2, 0));
-                KP_HIP(launch_mgs_update(q, V, vec, j + 1, h2, w, N));
-                KP_HIP(launch_mdot(q, w, 0, 1, w, N, partial, h2 + j + 1, 0));
-                KP_HIP(hipMemcpyAsync(hh, hd, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, q));
-                KP_HIP(hipMemcpyAsync(hh + j + 1, h2, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, q));
-                return KP_OK;
-            };
-            if (graphs && !execs[j]) {
-                // capture on the private stream (nothing runs during capture)
-                c->stream = c->cap_stream;
-                hipGraph_t graph = nullptr;
-                bool ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-                const kp_status cst = ok ? step() : KP_ERR_HIP;
-                ok = (hipStreamEndCapture(c->cap_stream, &graph) == hipSuccess) && ok && cst == KP_OK;
-                c->stream = s;
-                if (ok && hipGraphInstantiate(&execs[j], graph, nullptr, nullptr, 0) != hipSuccess) {
-                    execs[j] = nullptr;
-                    ok = false;
-                }
-                if (graph) hipGraphDestroy(graph);
-                if (!ok) {
-                    hipGetLastError();
-                    graphs = false;  // this solve continues without graphs
-                    hh = hh_local;
-                }
+        k = 0;
+        if (graphs && !exec) {
+            // capture the cycle on the private stream (nothing runs during capture)
+            c->stream = c->cap_stream;
+            hipGraph_t graph = nullptr;
+            bool ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            kp_status cst = ok ? KP_OK : KP_ERR_HIP;
+            for (int j = 0; j < m && cst == KP_OK; ++j) {
+                double* pa = proj + j * pslot;
+                double* pb = pa + (m + 2);
+                cst = step(j, pa, pb);
+                if (cst == KP_OK && launch_normalize(c->cap_stream, pb + j + 1, w, V + (j + 1) * vec, N) != hipSuccess)
+                    cst = KP_ERR_HIP;
             }
-            if (graphs) {
-                KP_HIP(hipGraphLaunch(execs[j], s));
-            } else if ((st = step()) != KP_OK) {
-                return st;
+            if (cst == KP_OK && hipMemcpyAsync(c->pinned, proj, (size_t)m * pslot * sizeof(double),
+                                               hipMemcpyDeviceToHost, c->cap_stream) != hipSuccess)
+                cst = KP_ERR_HIP;
+            ok = (hipStreamEndCapture(c->cap_stream, &graph) == hipSuccess) && ok && cst == KP_OK;
+            c->stream = s;
+            if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                exec = nullptr;
+                ok = false;
             }
+            if (graph) hipGraphDestroy(graph);
+            if (!ok) {
+                hipGetLastError();
+                graphs = false;  // this solve continues without graphs
+            }
+        }
+        if (graphs) {
+            KP_HIP(hipGraphLaunch(exec, s));
             KP_HIP(hipStreamSynchronize(s));
-            // column j: projections of both passes, then the norm
-            double* col = H + j * (m + 1);
-            for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[j + 1 + i];
-            const double hn = sqrt(fmax(hh[2 * j + 2], 0.0));
-            col[j + 1] = hn;
-            if (hn > 0.0) {
-                double* vn = V + (j + 1) * vec;
-                KP_HIP(launch_axpby(s, vn, w, 1.0 / hn, nullptr, 0.0, N));
+            for (int j = 0; j < m; ++j) {
+                const double* pa = c->pinned + j * pslot;
+                if (column(j, pa, pa + (m + 2))) break;
             }
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-                col[i] = t;
+        } else {
+            for (int j = 0; j < m; ++j) {
+                if ((st = step(j, hd, h2)) != KP_OK) return st;
+                KP_HIP(hipMemcpyAsync(hh, hd, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+                KP_HIP(hipMemcpyAsync(hh + j + 1, h2, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+                KP_HIP(hipStreamSynchronize(s));
+                const bool stop = column(j, hh, hh + j + 1);
+                if (hn > 0.0 && !stop) {
+                    double* vn = V + (j + 1) * vec;
+                    KP_HIP(launch_axpby(s, vn, w, 1.0 / hn, nullptr, 0.0, N));
+                }
+                if (stop) break;
             }
-            const double den = hypot(col[j], col[j + 1]);
-            cs[j] = den > 0.0 ? col[j] / den : 1.0;
-            sn[j] = den > 0.0 ? col[j + 1] / den : 0.0;
-            col[j] = den;
-            col[j + 1] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            ++iters;
-            k = j + 1;
-            if (hist_h && iters <= hist_len) hist_h[iters - 1] = fabs(g[j + 1]) / nb;
-            if (fabs(g[j + 1]) <= rtol * nb || iters >= maxit || hn == 0.0) break;
         }
         // y = H(0:k,0:k)^{-1} g, x += Z y
         double y[200];

@@ -34,6 +34,9 @@ hipError_t launch_combine(hipStream_t s, const float* Z, int64_t ldz, int k, con
                           double* x, int64_t N);
 hipError_t launch_axpby(hipStream_t s, double* dst, const double* src, double a, const double* other,
                         double b, int64_t N);
+// vn = w / sqrt(max(*nrm2, 0)) with the norm read on the device (zeros for a
+// zero norm)
+hipError_t launch_normalize(hipStream_t s, const double* nrm2, const double* w, double* vn, int64_t N);
 hipError_t launch_bj_factor(hipStream_t s, int64_t E, int N, const double* blocks, double* lu,
                             int32_t* piv, int32_t* status);
 hipError_t launch_bj_solve(hipStream_t s, int64_t E, int N, int nrhs, const double* lu,

@@ -387,6 +387,16 @@ __global__ void k_axpby(double* dst, const double* src, double a, const double* 
         dst[t] = a * src[t] + (other ? b * other[t] : 0.0);
 }
 
+// vn = w / sqrt(max(nrm2[0], 0)) (the same arithmetic as k_axpby with
+// a = 1 / sqrt(...) computed on the host); zeros where the norm is zero
+__global__ void k_normalize(const double* nrm2, const double* w, double* vn, int64_t N) {
+    const double hn = sqrt(fmax(nrm2[0], 0.0));
+    const double a = hn > 0.0 ? 1.0 / hn : 0.0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N;
+         t += (int64_t)gridDim.x * blockDim.x)
+        vn[t] = a * w[t] + 0.0;
+}
+
 // ------------------------------------------------------------ launchers
 template <class X>
 static hipError_t operator_any(hipStream_t s, int64_t E, int dim, int n, const Tables1D* tab,
@@ -501,6 +511,11 @@ hipError_t launch_combine(hipStream_t s, const float* Z, int64_t ldz, int k, con
 hipError_t launch_axpby(hipStream_t s, double* dst, const double* src, double a, const double* other,
                         double b, int64_t N) {
     hipLaunchKernelGGL(k_axpby, dim3(vec_grid(N)), dim3(256), 0, s, dst, src, a, other, b, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(hipStream_t s, const double* nrm2, const double* w, double* vn, int64_t N) {
+    hipLaunchKernelGGL(k_normalize, dim3(vec_grid(N)), dim3(256), 0, s, nrm2, w, vn, N);
     return hipGetLastError();
 }
 

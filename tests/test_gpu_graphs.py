@@ -1,11 +1,13 @@
-"""FGMRES with every Arnoldi step replayed as a HIP graph.
+"""FGMRES with every restart cycle replayed as one HIP graph.
 
-The graphs hold the same kernels in the same order as the eager solve, so
-the iteration count and the solution must be bit-identical; each step's
-graph is replayed once per restart cycle, with the driver's own eager work
-and synchronisations in between, and the restart lengths below force many
-cycles.  Covers the uniform coupled operator (KSVD and block-Jacobi
-preconditioners) and a mixed batch.
+The cycle's graph holds the eager solve's kernels for each Arnoldi step in
+the same order (the next basis vector normalised on the device with the same
+arithmetic), and the host stops at the same column, so the iteration count
+and the solution must be bit-identical; the graph is replayed once per
+restart cycle, with the driver's own eager work and synchronisations in
+between, and the restart lengths below force many cycles.  Covers the
+uniform coupled operator (KSVD and block-Jacobi preconditioners), a mixed
+batch and a systems batch.
 """
 import time
 
@@ -78,3 +80,23 @@ def test_graph_fgmres_mixed_batch(ctx):
     assert e["converged"] and e["iters"] == g["iters"]
     assert np.array_equal(e["x"].cpu().numpy(), g["x"].cpu().numpy())
     plan.close()
+
+
+def test_graph_fgmres_systems(ctx):
+    from oracle import systems
+    from paper_1704_04549_amd import kp
+    from tests.gpu_util import to_dev
+    nc, n, E = 4, 6, 40
+    sd = synth.systems_elements(E, nc, seed=12)
+    A = to_dev(np.stack([systems.element_block(sd, e, n) for e in range(E)]))
+    sb = kp.SysBatch(nc, n, A)
+    pc, _ = ctx.setup_sys(sb)
+    rhs = to_dev(np.random.default_rng(8).standard_normal(E * nc * n * n))
+    f = lambda: ctx.fgmres_sys(sb, rhs, pc_kind=kp.KP_PC_KSVD, pc_data=pc, pc_prec="fp32", restart=4)
+    e, te = run(ctx, False, f)
+    g, tg = run(ctx, True, f)
+    print(f"  systems: iters {e['iters']} / {g['iters']}, eager {te * 1e3:.1f} ms, graphs {tg * 1e3:.1f} ms",
+          flush=True)
+    assert e["converged"] and e["iters"] == g["iters"] and e["iters"] > 8
+    assert np.array_equal(e["x"].cpu().numpy(), g["x"].cpu().numpy())
+
