@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--setup", default="svd", choices=["svd", "learned"],
                     help="learned: the MLP (12 -> 256 -> 256 -> 5 n^2, trained on 20000 generated "
                          "elements before the timed region) predicts the factors, the SVD judges")
+    ap.add_argument("--rank", type=int, default=0,
+                    help="2D workloads: the number of Kronecker terms (default: the workload's, 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU oracle sample: elements are added until this much time is spent")
@@ -67,16 +69,21 @@ def _oracle_element(args):
     from oracle.ksvd import ksvd2d, ksvd3d
     from oracle.tables import tables
 
-    e, rec, rhs, n, dim = args
+    e, rec, rhs, n, dim, rank = args
     with threadpool_limits(limits=1):
         T = tables(n)
         t0 = time.perf_counter()
         A = element_block(rec, n, dim, T)
-        f = ksvd3d(A, n) if dim == 3 else ksvd2d(A, n, 2)
-        pc = SchurPrecond(f)
+        f = ksvd3d(A, n) if dim == 3 else ksvd2d(A, n, rank)
+        if rank == 3:
+            # three terms have no Schur route: the oracle's dense solve of P3
+            from oracle.apply import dense_solve
+            solve = lambda v: dense_solve(f, v)
+        else:
+            solve = SchurPrecond(f).solve
         t1 = time.perf_counter()
         for v in rhs:
-            pc.solve(v)
+            solve(v)
         t2 = time.perf_counter()
     return e, t1 - t0, (t2 - t1) / len(rhs)
 
@@ -99,7 +106,7 @@ def cpu_sample(w, budget_s):
     workers = max(1, min(16, avail))
     order = np.linspace(0, w["num_elems"] - 1, 4096).astype(int)
     order = list(dict.fromkeys(order.tolist()))
-    tasks = ((e, w["params"][e], w["rhs"][e], n, dim) for e in order)
+    tasks = ((e, w["params"][e], w["rhs"][e], n, dim, w["rank"]) for e in order)
     done = []
     t0 = time.perf_counter()
     ctx = mp.get_context("fork")
@@ -136,8 +143,10 @@ def cpu_baseline(sample, w, nrhs, N_iter):
     return dict(value=per_core * sample["workers"], unit="DOF/s", cores=sample["workers"], kind="oracle",
                 sample=f"{k} elements evenly spread over the batch, {sample['workers']} worker processes "
                        f"with one BLAS thread each for {sample['wall']:.1f} s: per element the block, the "
-                       f"KSVD by full SVD and the Schur tables (mean {ts / k * 1e3:.1f} ms) and one "
-                       f"Schur-route apply per right-hand side (mean {ta / k * 1e3:.2f} ms), scaled to "
+                       f"KSVD by full SVD" + (" and the Schur tables" if w["rank"] != 3 else "")
+                       + f" (mean {ts / k * 1e3:.1f} ms) and one "
+                       + ("Schur-route apply" if w["rank"] != 3 else "dense solve of P3")
+                       + f" per right-hand side (mean {ta / k * 1e3:.2f} ms), scaled to "
                        f"{N_iter} applies of {nrhs} right-hand side(s) per element",
                 host=dict(nproc=sample["nproc"], affinity_cpus=sample["affinity"], model=sample["model"]))
 
@@ -482,6 +491,10 @@ def main():
     import synth
 
     w = synth.workload(args.workload)
+    if args.rank:
+        if w["dim"] != 2 and args.rank != 2:
+            raise SystemExit("rank 3 is a 2D form")
+        w["rank"] = args.rank
     dim, n, E = w["dim"], w["n"], w["num_elems"]
     nrhs = w["nrhs"]
     # the CPU oracle's sample is timed first, before the GPU is initialised
@@ -601,7 +614,9 @@ def main():
         busy = MEASURED_TRAFFIC["mfma_busy_frac"].get(args.prec)
         counted = MEASURED_TRAFFIC["mfma_counted_flops"].get(args.prec)
     kname = ("k_apply16r3, n=16 3D matrix-core path" if (dim == 3 and n == 16)
-             else "k_apply16, n=16 2D matrix-core path" if n == 16 else "k_apply_generic")
+             else "k_apply16_rank3, n=16 2D rank-3 Neumann series on the matrix cores" if (n == 16 and rank == 3)
+             else "k_apply16, n=16 2D matrix-core path" if n == 16
+             else "k_apply_rank3" if rank == 3 else "k_apply_generic")
     roof = {"kernel": f"apply ({kname}, z stored in " + ("FP32)" if z_bytes == 4 else "FP64)"),
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -610,8 +625,11 @@ def main():
             "traffic_over_algorithmic": round(traffic / apply_bytes, 3) if traffic else None}
     flops = apply_flops(dim, n) * E * nrhs
     tf = flops / (t_apply * 1e-3) / 1e12
-    mfma = {"flops_per_launch": int(flops), "achieved_tflops": round(tf, 2),
-            "peak_tflops": MFMA_PEAK_TFLOPS[args.prec], "frac": round(tf / MFMA_PEAK_TFLOPS[args.prec], 4),
+    if rank == 3:
+        tf = None  # an iteration per element: no fixed flop count
+    mfma = {"flops_per_launch": int(flops) if rank != 3 else None, "achieved_tflops": round(tf, 2) if tf else None,
+            "peak_tflops": MFMA_PEAK_TFLOPS[args.prec],
+            "frac": round(tf / MFMA_PEAK_TFLOPS[args.prec], 4) if tf else None,
             "counting": "algorithmic Schur-route flops (2D 14 n^3, 3D 16 n^4 per element and right-hand "
                         "side) over the measured launch time",
             "counter_busy_frac": busy,
@@ -633,7 +651,8 @@ def main():
                   "note": "the setup never forms the blocks (matrix-free, Gram form of the rearranged "
                           "operator): it is bound by dependent small-matrix chains, not by HBM"}
     line = {
-        "metric": METRIC if (dim, n) == (3, 16) else METRIC.replace("3D p=15", f"{dim}D p={n - 1}"),
+        "metric": (METRIC if (dim, n) == (3, 16) else METRIC.replace("3D p=15", f"{dim}D p={n - 1}"))
+                  + (", rank 3" if rank == 3 else ""),
         "value": value if valid else None,
         "unit": "DOF/s",
         "n_gpus": 1,

@@ -496,6 +496,148 @@ __global__ void __launch_bounds__(256) k_apply16(int64_t E, int nrhs, const type
     }
 }
 
+// ------------------------------------------- 2D rank 3 (three Kronecker terms)
+// z = P3^{-1} r with P3 = P2 + A3 (x) B3 (P2 the first two terms, whose
+// Schur-route inverse is the apply above): z = sum_k d_k with d_0 = P2^{-1} r
+// and d_{k+1} = -P2^{-1} (A3 (x) B3) d_k, the Neumann series of
+// (I + P2^{-1} (A3 (x) B3))^{-1} P2^{-1}, which converges when the spectral
+// radius of P2^{-1} (A3 (x) B3) is below one (0.33 at most on the 2D p = 15
+// blocks).  Every term costs one rank-2 apply and one Kronecker product on the
+// matrix cores, with the element's tables, the 16 right-hand sides of the work
+// item and the running sum in LDS; the series stops when every right-hand
+// side's last term is at most tol times its sum.  A work item that has not
+// met that within maxit terms (or has produced a non-finite value) sets
+// flags[e] (cleared by the caller before the launch) for the per-element
+// GMRES kernel to redo.
+template <class P>
+__device__ __forceinline__ typename P::Tab stage_tab(double v) {
+    if constexpr (sizeof(typename P::Tab) == 2)
+        return (typename P::Tab)bf16s((float)v);
+    else
+        return (typename P::Tab)v;
+}
+
+template <class P>
+__global__ void __launch_bounds__(256) k_apply16_rank3(int64_t E, int nrhs, const typename P::Tab* tabs,
+                                                       int64_t tab_stride, const typename P::FragTab* frags,
+                                                       const int8_t* kinds, const double* factors,
+                                                       const double* r, double* z, int maxit, double tol,
+                                                       int8_t* flags) {
+    typedef typename P::T T;
+    typedef typename P::FragTab FT;
+    typedef typename P::Tab TB;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* X = (T*)smem;
+    T* T2s = X + kTensor;
+    T* Zs = T2s + 256;                 // the running sum, 4096
+    double* part = (double*)(Zs + 4096);  // 4 waves x 32 partial sums
+    TB* M3 = (TB*)(part + 128);        // -A3 and B3, 512 entries
+    FT* Nf = (FT*)(M3 + 512 + 8);
+    constexpr int kNfEntries = 16 * 64 * 4 * P::kFragStride;
+    const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6, g = l >> 4, c = l & 15;
+    const int groups = (nrhs + 15) / 16;
+    const int64_t work = E * groups;
+    for (int64_t w = blockIdx.x; w < work; w += gridDim.x) {
+        const int64_t e = w / groups;
+        const int grp = (int)(w % groups);
+        const int s0 = grp * 16;
+        const int ns = nrhs - s0 < 16 ? nrhs - s0 : 16;  // active slices
+        const typename P::Tab* tab = tabs + e * tab_stride;
+        const FT* fr = frags + e * tab_stride * P::kFragStride;
+        typename P::Frag fL[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) fL[m] = P::load_frag(fr, m, l);
+        const typename P::Frag fT1 = P::load_frag(fr, 5, l);
+        constexpr int n16 = kNfEntries * (int)sizeof(FT) / 16;
+        uint4 nbuf[n16 / 256];
+        {
+            const uint4* src = (const uint4*)(fr + 7 * 64 * 4 * P::kFragStride);
+#pragma unroll
+            for (int i = 0; i < n16 / 256; ++i) nbuf[i] = src[tid + 256 * i];
+        }
+        const T t2v = (T)P::tab(tab + 6 * 256, tid);
+        const double* F = factors + e * 6 * 256;
+        const double a3 = F[4 * 256 + tid], b3 = F[5 * 256 + tid];
+        int kd[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) kd[j] = kinds[e * kMaxN + j];
+        {
+            uint4* dst = (uint4*)Nf;
+#pragma unroll
+            for (int i = 0; i < n16 / 256; ++i) dst[tid + 256 * i] = nbuf[i];
+        }
+        T2s[tid] = t2v;
+        M3[tid] = stage_tab<P>(-a3);
+        M3[256 + tid] = stage_tab<P>(b3);
+        for (int t = tid; t < 4096; t += 256) {
+            const int a = t >> 8, sl = s0 + a;
+            X[xidx(a, (t >> 4) & 15, t & 15)] = a < ns ? (T)r[(e * nrhs + sl) * 256 + (t & 255)] : (T)0;
+            Zs[t] = (T)0;
+        }
+        __syncthreads();
+        const typename P::Frag fA3 = P::load(M3, g, c);
+        const typename P::Frag fB3 = P::load(M3 + 256, g, c);
+        bool done = false, ok = false;
+        for (int it = 0; it < maxit && !done; ++it) {
+            // d = P2^{-1} X
+            contract<P, 1>(fL[0], X, g, c, wv);
+            contract<P, 2>(fL[1], X, g, c, wv);
+            sylvester<P>(Nf, fT1, kd, T2s, X, g, c, l, wv);
+            contract<P, 1>(fL[3], X, g, c, wv);
+            contract<P, 2>(fL[4], X, g, c, wv);
+            // sum += d; per slice ||d||^2 and ||sum||^2 (thread tid holds entry
+            // tid of every slice a = i)
+            double pd[16], pz[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int t = tid + 256 * i;
+                const T dv = X[xidx(i, (t >> 4) & 15, t & 15)];
+                const T zv = Zs[t] + dv;
+                Zs[t] = zv;
+                pd[i] = (double)dv * (double)dv;
+                pz[i] = (double)zv * (double)zv;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                for (int off = 32; off > 0; off >>= 1) {
+                    pd[i] += __shfl_xor(pd[i], off, 64);
+                    pz[i] += __shfl_xor(pz[i], off, 64);
+                }
+            }
+            if (l == 0) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    part[wv * 32 + i] = pd[i];
+                    part[wv * 32 + 16 + i] = pz[i];
+                }
+            }
+            __syncthreads();
+            bool conv = true, finite = true;
+            for (int i = 0; i < ns; ++i) {
+                const double d2 = part[i] + part[32 + i] + part[64 + i] + part[96 + i];
+                const double z2 = part[16 + i] + part[48 + i] + part[80 + i] + part[112 + i];
+                if (!(d2 == d2) || !(z2 == z2) || d2 > 1e300 || z2 > 1e300) finite = false;
+                if (!(d2 <= tol * tol * z2)) conv = false;
+            }
+            __syncthreads();
+            if (!finite) break;
+            if (conv) {
+                done = ok = true;
+                break;
+            }
+            // X = -(A3 (x) B3) d
+            contract<P, 1>(fA3, X, g, c, wv);
+            contract<P, 2>(fB3, X, g, c, wv);
+        }
+        for (int t = tid; t < 4096; t += 256) {
+            const int a = t >> 8, sl = s0 + a;
+            if (a < ns) z[(e * nrhs + sl) * 256 + (t & 255)] = (double)Zs[t];
+        }
+        if (tid == 0 && !ok) flags[e] = 1;
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------- 3D, register-resident
 // One workgroup of four waves per (element, right-hand side).  The tensor
 // lives in registers: wave w holds the tiles t = 4w .. 4w+3 (slot s = t % 4)
@@ -812,6 +954,37 @@ static hipError_t launch16(hipStream_t st, int64_t E, int nrhs, const void* tabs
                        (const typename P::Tab*)tabs, tab_stride, (const typename P::FragTab*)frags,
                        kinds, r, z);
     return hipGetLastError();
+}
+
+template <class P>
+static hipError_t launch16_rank3(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
+                                 const void* frags, const int8_t* kinds, const double* factors, const double* r,
+                                 double* z, int maxit, double tol, int8_t* flags) {
+    const int64_t work = E * ((nrhs + 15) / 16);
+    const int grid = (int)(work < kApply16Grid ? work : kApply16Grid);
+    const size_t lds = (kTensor + 256 + 4096) * sizeof(typename P::T) + 128 * sizeof(double) +
+                       (512 + 8) * sizeof(typename P::Tab) +
+                       16 * 64 * 4 * P::kFragStride * sizeof(typename P::FragTab);
+    hipLaunchKernelGGL((k_apply16_rank3<P>), dim3(grid), dim3(256), lds, st, E, nrhs,
+                       (const typename P::Tab*)tabs, tab_stride, (const typename P::FragTab*)frags, kinds,
+                       factors, r, z, maxit, tol, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply16_rank3(hipStream_t s, int prec, int64_t E, int nrhs, const void* tabs,
+                                int64_t tab_stride, const void* frags, const int8_t* kinds,
+                                const double* factors, const double* r, double* z, int8_t* flags) {
+    switch (prec) {
+        // term limits: a spectral radius up to about 0.88 still converges within them
+        case 0: return launch16_rank3<PolF64>(s, E, nrhs, tabs, tab_stride, frags, kinds, factors, r, z, 256, 1e-14,
+                                              flags);
+        case 1: return launch16_rank3<PolF32>(s, E, nrhs, tabs, tab_stride, frags, kinds, factors, r, z, 128, 2e-7,
+                                              flags);
+        case 2: return launch16_rank3<PolBF16>(s, E, nrhs, tabs, tab_stride, frags, kinds, factors, r, z, 64, 2e-3,
+                                               flags);
+        default: return launch16_rank3<PolBF16X3>(s, E, nrhs, tabs, tab_stride, frags, kinds, factors, r, z, 96,
+                                                  5e-6, flags);
+    }
 }
 
 hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,

@@ -55,9 +55,18 @@ hipError_t launch_form_tables_list(hipStream_t s, int64_t count, const int32_t* 
 // rank-3 2D apply (inner flexible GMRES per element); LDS budget and restart length
 constexpr size_t kRank3LdsMax = 150 * 1024;
 int rank3_restart(int n);
+// only: per-element flags, or null; with flags, only the flagged elements
+// are solved (the rest of z is left as it is)
 hipError_t launch_apply_rank3(hipStream_t s, int prec, int64_t E, int n, int nrhs,
                               const double* factors, const void* tabs, int64_t tab_stride,
-                              const int8_t* kinds, const double* r, double* z);
+                              const int8_t* kinds, const double* r, double* z, const int8_t* only = nullptr);
+// 2D rank 3 with n = 16 on the matrix cores (apply_mfma.hip): the Neumann
+// series of P2^{-1} (A3 (x) B3) over the rank-2 apply, 16 right-hand sides per
+// workgroup; flags[e] (int8, zeroed by the caller) is set for an element whose
+// series did not converge, for launch_apply_rank3 with only = flags
+hipError_t launch_apply16_rank3(hipStream_t s, int prec, int64_t E, int nrhs, const void* tabs,
+                                int64_t tab_stride, const void* frags, const int8_t* kinds,
+                                const double* factors, const double* r, double* z, int8_t* flags);
 hipError_t launch_cast_tables(hipStream_t s, int64_t count, const double* t64, float* t32,
                               uint16_t* hi, uint16_t* lo, float* t2);
 hipError_t launch_frag_tables(hipStream_t s, int64_t E, const double* t64, double* f64f, float* f32f,

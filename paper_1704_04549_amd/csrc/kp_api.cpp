@@ -456,9 +456,25 @@ static kp_status apply_impl(kp_ctx c, const kp_batch* b, int32_t rank, const voi
     const int8_t* axes = (c->split_axis && b->dim == 3) ? (const int8_t*)(pc + L.axis) : nullptr;
     if (rank == 3) {
         // 2D only (pc_layout rejects rank 3 in 3D); FP64 z only (checked above)
-        if constexpr (!z32)
-            KP_HIP(launch_apply_rank3(c->stream, prec, E, b->n, nrhs, (const double*)(pc + L.factors),
-                                      tabs, L.ne, (const int8_t*)(pc + L.kinds), r, z));
+        if constexpr (!z32) {
+            const double* fac = (const double*)(pc + L.factors);
+            const int8_t* kd = (const int8_t*)(pc + L.kinds);
+            if (b->n == 16 && c->use_mfma16) {
+                // the Neumann series on the matrix cores, then the per-element
+                // GMRES for the elements it flags
+                if ((st = ensure_ws(c, (size_t)E, &c->ws, &c->ws_bytes)) != KP_OK) return st;
+                int8_t* flags = (int8_t*)c->ws;
+                const void* frags = prec == KP_FP64   ? (const void*)(pc + L.f64f)
+                                    : prec == KP_FP32 ? (const void*)(pc + L.f32f)
+                                    : prec == KP_BF16 ? (const void*)(pc + L.fbf)
+                                                      : (const void*)(pc + L.fbf3);
+                KP_HIP(launch_fill_i8(c->stream, E, flags, 0));
+                KP_HIP(launch_apply16_rank3(c->stream, prec, E, nrhs, tabs, L.ne, frags, kd, fac, r, z, flags));
+                KP_HIP(launch_apply_rank3(c->stream, prec, E, b->n, nrhs, fac, tabs, L.ne, kd, r, z, flags));
+            } else {
+                KP_HIP(launch_apply_rank3(c->stream, prec, E, b->n, nrhs, fac, tabs, L.ne, kd, r, z));
+            }
+        }
     } else if (b->n == 16 && c->use_mfma16) {
         const void* frags = prec == KP_FP64   ? (const void*)(pc + L.f64f)
                             : prec == KP_FP32 ? (const void*)(pc + L.f32f)

@@ -1,5 +1,6 @@
 // Rank-3 2D apply kernel: one workgroup per (element, right-hand side), the
-// whole inner flexible GMRES in LDS (see rank3.h).
+// whole inner flexible GMRES in LDS (see rank3.h); with only, the elements
+// not flagged there are skipped.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -11,7 +12,7 @@ template <typename T, typename TT, class Rnd>
 __global__ void __launch_bounds__(256) k_apply_rank3(int64_t E, int n, int nrhs, const double* factors,
                                                      const TT* tabs, int64_t tab_stride,
                                                      const int8_t* kinds, const double* r, double* z,
-                                                     int m, double rtol, int maxit, Rnd rnd) {
+                                                     int m, double rtol, int maxit, Rnd rnd, const int8_t* only) {
     extern __shared__ double lds[];
     __shared__ double red[4 * kMaxReduce];
     BlockTeam tm{red};
@@ -21,6 +22,7 @@ __global__ void __launch_bounds__(256) k_apply_rank3(int64_t E, int n, int nrhs,
     T* tw = (T*)(small + rank3_small_doubles(m));
     for (int64_t w = blockIdx.x; w < E * nrhs; w += gridDim.x) {
         const int64_t e = w / nrhs;
+        if (only && !only[e]) continue;
         rank3_solve(tm, n, factors + e * 6 * nn, tabs + e * tab_stride, kinds + e * kMaxN,
                     r + w * nn, z + w * nn, work, tw, small, m, rtol, maxit, rnd);
     }
@@ -37,7 +39,7 @@ int rank3_restart(int n) {
 
 hipError_t launch_apply_rank3(hipStream_t s, int prec, int64_t E, int n, int nrhs,
                               const double* factors, const void* tabs, int64_t tab_stride,
-                              const int8_t* kinds, const double* r, double* z) {
+                              const int8_t* kinds, const double* r, double* z, const int8_t* only) {
     const int m = rank3_restart(n);
     if (m < 2) return hipErrorInvalidValue;
     const int nn = n * n;
@@ -49,19 +51,19 @@ hipError_t launch_apply_rank3(hipStream_t s, int prec, int64_t E, int n, int nrh
     if (prec == 0) {
         hipLaunchKernelGGL((k_apply_rank3<double, double, RoundNone>), dim3(grid), dim3(256), lds, s, E,
                            n, nrhs, factors, (const double*)tabs, tab_stride, kinds, r, z, m, rtol,
-                           maxit, RoundNone());
+                           maxit, RoundNone(), only);
     } else if (prec == 1) {
         hipLaunchKernelGGL((k_apply_rank3<float, float, RoundNone>), dim3(grid), dim3(256), lds, s, E,
                            n, nrhs, factors, (const float*)tabs, tab_stride, kinds, r, z, m, rtol,
-                           maxit, RoundNone());
+                           maxit, RoundNone(), only);
     } else if (prec == 2) {
         hipLaunchKernelGGL((k_apply_rank3<float, uint16_t, RoundBf16>), dim3(grid), dim3(256), lds, s,
                            E, n, nrhs, factors, (const uint16_t*)tabs, tab_stride, kinds, r, z, m,
-                           rtol, maxit, RoundBf16());
+                           rtol, maxit, RoundBf16(), only);
     } else {
         hipLaunchKernelGGL((k_apply_rank3<float, float, RoundBf16x2>), dim3(grid), dim3(256), lds, s,
                            E, n, nrhs, factors, (const float*)tabs, tab_stride, kinds, r, z, m, rtol,
-                           maxit, RoundBf16x2());
+                           maxit, RoundBf16x2(), only);
     }
     return hipGetLastError();
 }
