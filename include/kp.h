@@ -153,14 +153,19 @@ kp_status kp_set_stream(kp_ctx ctx, void* stream);
  *     so the relabelled block is that of the record with its per-axis data
  *     permuted); explicit 3D blocks, the learned modes and kp_setup_noalloc
  *     return KP_ERR_UNSUPPORTED.  A preconditioner formed with the option on
- *     must be applied with it on.  Three times the Lanczos work of the setup. */
+ *     must be applied with it on.  Three times the Lanczos work of the setup.
+ *   KP_OPT_APPLY_SMALL3 (default 1): the 3D apply for n <= 8 runs one wave
+ *     per (element, right-hand side) with the tensor held as register fibres
+ *     (the arithmetic of the generic apply); 0 selects the generic
+ *     per-element kernel. */
 typedef enum {
     KP_OPT_FGMRES_GRAPHS = 1,
     KP_OPT_APPLY_MFMA16 = 2,
     KP_OPT_FGMRES_Z32 = 3,
     KP_OPT_OPERATOR_COLS = 4,
     KP_OPT_LEARNED_GUARD = 5,
-    KP_OPT_SPLIT_AXIS = 6
+    KP_OPT_SPLIT_AXIS = 6,
+    KP_OPT_APPLY_SMALL3 = 7
 } kp_option;
 kp_status kp_set_option(kp_ctx ctx, int32_t option, int64_t value);
 const char* kp_status_string(kp_status s);

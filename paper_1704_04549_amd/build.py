@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libkp.so")
 HOSTCHECK = os.path.join(ROOT, "tests", "_native", "libkp_hostcheck.so")
 
 HIP_SOURCES = ["kernels.hip", "apply_mfma.hip", "rank3.hip", "learned.hip", "mixed.hip", "krylov.hip", "bj.hip", "mlp.hip",
-               "quad.hip", "sys.hip"]
+               "quad.hip", "sys.hip", "apply_small.hip"]
 CPP_SOURCES = ["kp_api.cpp", "mlp_api.cpp", "mixed_api.cpp", "tables.cpp", "quad_tables.cpp", "sys_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

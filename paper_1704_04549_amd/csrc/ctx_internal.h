@@ -49,6 +49,8 @@ struct kp_ctx_s {
     bool split_axis = false;
     // tables of general elements per (n, mu), uploaded on first use
     void* d_quad[kMaxN + 1][kMaxN + 1] = {};
+    // 3D n <= 8 apply with one wave per element (KP_OPT_APPLY_SMALL3)
+    bool use_small3 = true;
     // spectral guard of the learned setup (KP_OPT_LEARNED_GUARD)
     double learned_guard = 0.01;
 };

@@ -108,6 +108,15 @@ hipError_t launch_setup_quad(hipStream_t s, int grid, int64_t E, int dim, int n,
                              const double* g, double* factors, double* sigma, int32_t* status, double* ws,
                              int64_t ws_stride);
 
+// 3D elements with n <= 8 (apply_small.hip): one wave per (element, rhs),
+// the tensor as register fibres; the arithmetic of the generic apply
+hipError_t launch_apply_small3(hipStream_t s, int prec, int64_t E, int n, int nrhs, const void* tabs,
+                               int64_t tab_stride, const int8_t* kinds, const double* r, double* z,
+                               const int8_t* axes);
+hipError_t launch_apply_small3(hipStream_t s, int prec, int64_t E, int n, int nrhs, const void* tabs,
+                               int64_t tab_stride, const int8_t* kinds, const double* r, float* z,
+                               const int8_t* axes);
+
 // systems blocks (sys.h, sys.hip): setup with one workgroup per element over
 // grid workspace slots of ws_stride doubles (angle: E int32 scratch for the
 // pair rotations); apply with one workgroup per

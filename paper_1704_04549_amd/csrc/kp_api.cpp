@@ -125,6 +125,7 @@ kp_status kp_set_option(kp_ctx c, int32_t option, int64_t value) {
         case KP_OPT_FGMRES_Z32: c->fgmres_z32 = value != 0; return KP_OK;
         case KP_OPT_OPERATOR_COLS: c->op_cols = value != 0; return KP_OK;
         case KP_OPT_SPLIT_AXIS: c->split_axis = value != 0; return KP_OK;
+        case KP_OPT_APPLY_SMALL3: c->use_small3 = value != 0; return KP_OK;
         case KP_OPT_LEARNED_GUARD:
             if (value < 0 || value > 1000000) return KP_ERR_ARG;
             c->learned_guard = (double)value * 1e-6;
@@ -482,6 +483,9 @@ static kp_status apply_impl(kp_ctx c, const kp_batch* b, int32_t rank, const voi
                                               : (const void*)(pc + L.fbf3);
         KP_HIP(launch_apply16(c->stream, prec, E, b->dim, nrhs, tabs, L.ne, frags,
                               (const int8_t*)(pc + L.kinds), r, z, axes));
+    } else if (b->dim == 3 && b->n <= 8 && c->use_small3) {
+        KP_HIP(launch_apply_small3(c->stream, prec, E, b->n, nrhs, tabs, L.ne, (const int8_t*)(pc + L.kinds), r, z,
+                                   axes));
     } else {
         KP_HIP(launch_apply_generic(c->stream, prec, E, b->dim, b->n, nrhs, tabs, L.ne,
                                     (const int8_t*)(pc + L.kinds), r, z, axes));

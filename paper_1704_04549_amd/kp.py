@@ -21,7 +21,7 @@ KP_FP64, KP_FP32, KP_BF16, KP_BF16X3 = 0, 1, 2, 3
 KP_SETUP_SVD, KP_SETUP_LEARNED, KP_SETUP_LEARNED_WARM = 0, 1, 2
 KP_PC_NONE, KP_PC_KSVD, KP_PC_BJ = 0, 1, 2
 KP_OPT_FGMRES_GRAPHS, KP_OPT_APPLY_MFMA16, KP_OPT_FGMRES_Z32, KP_OPT_OPERATOR_COLS = 1, 2, 3, 4
-KP_OPT_LEARNED_GUARD, KP_OPT_SPLIT_AXIS = 5, 6
+KP_OPT_LEARNED_GUARD, KP_OPT_SPLIT_AXIS, KP_OPT_APPLY_SMALL3 = 5, 6, 7
 ELEM_LANCZOS_NOCONV, ELEM_SINGULAR_FACTOR, ELEM_SCHUR_NOCONV, ELEM_NONFINITE = 1, 2, 4, 8
 ELEM_LEARNED_REJECTED, ELEM_LEARNED_WARM = 16, 32
 REC_LEN = 16
