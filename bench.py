@@ -357,6 +357,132 @@ def bench_systems(args):
     ctx.close()
 
 
+def _oracle_quad_element(args):
+    """Worker: the oracle's two-stage KSVD of one general element (R(A) row by
+    row from the shuffled transpose products, full SVDs), single-threaded BLAS."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import shuffled
+    from oracle.ksvd import ksvd3d_rearranged
+
+    e, el, n, mu = args
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        Q = shuffled.quad_tables(n, mu)
+        ksvd3d_rearranged(shuffled.rearranged_rows(el, Q), n)
+        return e, time.perf_counter() - t0
+
+
+def bench_quad(args):
+    """General (non-collocated quadrature) 3D elements: the setup of
+    kp_setup_quad (the Gram form of the rearranged operator from per-point
+    coefficients), timed alone, as setup DOF/s; one apply of the resulting
+    preconditioner (the same kernel as the default workload) is timed beside."""
+    import multiprocessing as mp
+
+    import synth
+    n, mu, E = 16, 17, 4096
+    q = synth.quad_elements(E, 3, mu)
+    ndof = E * n ** 3
+    sample = None
+    if not args.no_cpu_baseline and args.fixed_iters == 0:
+        try:
+            avail = len(os.sched_getaffinity(0))
+        except AttributeError:
+            avail = os.cpu_count() or 1
+        workers = max(1, min(16, avail))
+        order = list(dict.fromkeys(np.linspace(0, E - 1, 256).astype(int).tolist()))
+        done = []
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(workers) as pool:
+            for res in pool.imap_unordered(_oracle_quad_element,
+                                           ((e, synth.quad_element(q, e, n), n, mu) for e in order)):
+                done.append(res)
+                if time.perf_counter() - t0 >= args.cpu_seconds and len(done) >= workers:
+                    break
+            pool.terminate()
+        sample = dict(done=done, workers=workers, wall=time.perf_counter() - t0, nproc=os.cpu_count(),
+                      affinity=avail)
+
+    import torch
+
+    from paper_1704_04549_amd import kp
+    dev = torch.device("cuda", 0)
+    ctx = kp.Ctx(0)
+    stream = ctx.stream
+    qb = kp.QuadBatch(3, n, mu, q["tau"], *(torch.from_numpy(np.ascontiguousarray(q[k])).to(dev)
+                                            for k in ("c", "a", "nu", "g")))
+    pc, st = ctx.setup_quad(qb)
+    b = qb.batch()
+    r = torch.from_numpy(np.random.default_rng(2006).standard_normal((E, n ** 3))).to(dev)
+    z32 = torch.empty(r.shape, dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        ctx.setup_quad(qb, pc, st)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ctx.setup_quad(qb, pc, st)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    t_setup = sum(a.elapsed_time(bb) for a, bb in ev) / args.steps
+    nonzero = int((st != 0).sum())
+    zd = torch.empty_like(r)
+
+    def apply():
+        if args.prec == "fp64":
+            ctx.apply(b, 2, pc, "fp64", r, zd)
+        else:
+            ctx.apply_z32(b, 2, pc, args.prec, r, z32)
+    apply()
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record(stream)
+    for _ in range(10):
+        apply()
+    a1.record(stream)
+    torch.cuda.synchronize()
+    t_apply = a0.elapsed_time(a1) / 10
+    # algorithmic bytes of the setup: the coefficients read (c, a_i, nu at
+    # mu^3 points, g on six faces at mu^2 points) and the factors written
+    coef_bytes = E * (5 * mu ** 3 + 6 * mu ** 2) * 8
+    fac_bytes = E * 5 * n * n * 8
+    gbs = (coef_bytes + fac_bytes) / (t_setup * 1e-3) / 1e9
+    line = {
+        "metric": "general-element (non-collocated quadrature) setup DOF/s, 3D p=15, mu=17",
+        "value": ndof / (sec if sec > 0 else 1.0),
+        "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp64", "data": "synthetic",
+        "config": {"workload": f"3D p={n - 1} (n={n}), mu={mu} Gauss-Legendre points per axis, {E} elements, "
+                               "per-point coefficients (curved-element fields), two-stage KSVD in the Gram form "
+                               "of the rearranged operator, apply tables",
+                   "elements": E, "dof": ndof, "status_nonzero": nonzero},
+        "setup_ms": t_setup,
+        "apply_ms": t_apply,
+        "apply_prec": args.prec,
+        "roofline": {"kernel": "setup (k_setup_quad, then the table kernels)", "bound": "hbm",
+                     "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                     "algorithmic_bytes": int(coef_bytes + fac_bytes),
+                     "note": "bytes of the coefficients read and the factors written; the setup is a chain "
+                             "of dependent Lanczos steps per element, not bound by HBM"},
+    }
+    if sample is not None:
+        done = sample["done"]
+        k = len(done)
+        t_el = sum(d[1] for d in done) / k
+        line["cpu_baseline"] = dict(
+            value=n ** 3 / t_el * sample["workers"], unit="DOF/s", cores=sample["workers"], kind="oracle",
+            sample=f"{k} elements evenly spread over the batch, {sample['workers']} worker processes with one "
+                   f"BLAS thread each for {sample['wall']:.1f} s: per element R(A) (256 x 65536) row by row from "
+                   f"the shuffled transpose products and the two full SVDs (mean {t_el:.1f} s)",
+            host=dict(nproc=sample["nproc"], affinity_cpus=sample["affinity"]))
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def bench_mixed(args):
     """The mixed batch: 50000 2D elements (p 3..30) and 2000 3D elements
     (p 3..15), block-diagonal, one persistent launch per stage, autotuned
@@ -482,6 +608,9 @@ def main():
         sys.exit(2)
     if args.workload == "c5_mixed":
         bench_mixed(args)
+        return
+    if args.workload == "quad_3d_p15":
+        bench_quad(args)
         return
     if args.workload.startswith("sys_"):
         if args.prec not in ("fp32", "fp64"):
