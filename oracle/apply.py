@@ -29,8 +29,9 @@ the alternative the paper mentions in Sec. 4.2; used only as a pin on
 small n.
 
 Pinned by tests/test_oracle_apply.py (P z = r residual, Schur = dense,
-FDM = dense on n <= 6, hand-written Sylvester = scipy.linalg.solve_sylvester,
-operation counts against 14 n^3 / 16 n^4 and their growth rates in n).
+FDM = dense on n <= 6, hand-written Sylvester = scipy.linalg.solve_sylvester)
+and tests/test_oracle_shuffled.py (operation counts against 14 n^3 / 16 n^4
+and their growth rates in n).
 """
 from __future__ import annotations
 

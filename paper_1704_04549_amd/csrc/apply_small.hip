@@ -24,6 +24,19 @@
 namespace kp {
 
 constexpr int kS3 = 8;  // largest n of this kernel
+// third word of a raw buffer descriptor on gfx9 (32-bit data format); raw
+// buffer loads past the descriptor's byte count return zero
+constexpr int kBufWord3 = 0x00020000;
+
+// type of the tables' LDS copy: BF16 entries are held as FP32
+template <typename TT>
+struct SmallLdsTab {
+    typedef TT type;
+};
+template <>
+struct SmallLdsTab<uint16_t> {
+    typedef float type;
+};
 
 __host__ __device__ inline size_t small3_wave_bytes(int n, size_t tsz, size_t tabsz) {
     const size_t tabs = ((size_t)(7 + n) * n * n * tabsz + 15) / 16 * 16;
@@ -33,31 +46,39 @@ __host__ __device__ inline size_t small3_wave_bytes(int n, size_t tsz, size_t ta
     return (tabs + (buf > ex ? buf : ex) * tsz + 15) / 16 * 16;
 }
 
-template <typename T, typename TT, class Rnd, class Z, bool AX>
-__global__ void __launch_bounds__(256) k_apply_small3(int64_t E, int n, int nrhs, const TT* tabs, int64_t tab_stride,
-                                                      const int8_t* kinds, const double* r, Z* z, Rnd rnd,
-                                                      const int8_t* axes) {
+// NT: n fixed at compile time (0: n_arg), so that every fibre loop and
+// table index folds to constants
+template <typename T, typename TT, class Rnd, class Z, bool AX, int NT>
+__global__ void __launch_bounds__(256) k_apply_small3(int64_t E, int n_arg, int nrhs, const TT* tabs,
+                                                      int64_t tab_stride, const int8_t* kinds, const double* r, Z* z,
+                                                      Rnd rnd, const int8_t* axes) {
+    const int n = NT > 0 ? NT : n_arg;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int wv = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
+    // the wave index as a scalar, so that the item index and every per-item
+    // address below are scalars
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), l = (int)(threadIdx.x & 63);
     const int nn = n * n, nd = nn * n, n1 = n + 1;
     const int ntab = (7 + n) * nn;
-    const size_t per = small3_wave_bytes(n, sizeof(T), sizeof(TT));
-    TT* tb = (TT*)(smem + wv * per);
-    T* buf = (T*)((unsigned char*)tb + ((size_t)ntab * sizeof(TT) + 15) / 16 * 16);
+    // the wave's copy of the tables in LDS: BF16 tables are widened to FP32
+    // on the way in (exactly), so that no table read converts
+    typedef typename SmallLdsTab<TT>::type LT;
+    const size_t per = small3_wave_bytes(n, sizeof(T), sizeof(LT));
+    LT* tb = (LT*)(smem + wv * per);
+    T* buf = (T*)((unsigned char*)tb + ((size_t)ntab * sizeof(LT) + 15) / 16 * 16);
     T* ex = buf;            // six exchange blocks of kS3 x kS3 (slice, row), during the sweep
-    const TT* L0 = tb;
-    const TT* L1 = tb + nn;
-    const TT* L2 = tb + 2 * nn;
-    const TT* R0 = tb + 3 * nn;
-    const TT* R1 = tb + 4 * nn;
-    const TT* T1 = tb + 5 * nn;
-    const TT* T2 = tb + 6 * nn;
-    const TT* N = tb + 7 * nn;
+    const LT* L0 = tb;
+    const LT* L1 = tb + nn;
+    const LT* L2 = tb + 2 * nn;
+    const LT* R0 = tb + 3 * nn;
+    const LT* R1 = tb + 4 * nn;
+    const LT* T1 = tb + 5 * nn;
+    const LT* T2 = tb + 6 * nn;
+    const LT* N = tb + 7 * nn;
     const bool act = l < nn;
     const int p = act ? l / n : 0, q = act ? l % n : 0;
     WaveTeam wt;
     // x <- M x along the fibre (M n x n row-major in LDS)
-    auto inl = [&](const TT* M, T (&x)[kS3]) {
+    auto inl = [&](const LT* M, T (&x)[kS3]) {
         T xr[kS3], y[kS3];
 #pragma unroll
         for (int k = 0; k < kS3; ++k) xr[k] = rnd(x[k]);
@@ -94,21 +115,62 @@ __global__ void __launch_bounds__(256) k_apply_small3(int64_t E, int n, int nrhs
                 }
         wt.sync();
     };
+    // the tables are copied as 4-byte words: (7 + n) n^2 is even for every n,
+    // so an element's tables start and end on a word boundary (the launcher
+    // checks the stride)
+    constexpr int kTabWords = ((7 + kS3) * kS3 * kS3 * (int)sizeof(TT) + 3) / 4;
+    constexpr int kTabPer = (kTabWords + 63) / 64;
+    const int nwords = ntab * (int)sizeof(TT) / 4;
+    // buf, in units of one word's worth of LDS entries (a word, or two FP32
+    // values for BF16 tables) from tb
+    const int buf_unit = (int)(((size_t)ntab * sizeof(LT) + 15) / 16 * 16 / (4 * sizeof(LT) / sizeof(TT)));
     const int64_t work = E * nrhs;
     for (int64_t w = (int64_t)blockIdx.x * 4 + wv; w < work; w += (int64_t)gridDim.x * 4) {
         const int64_t e = w / nrhs;
-        const TT* tab = tabs + e * tab_stride;
-        for (int t = l; t < ntab; t += 64) tb[t] = tab[t];
+        const TT* tabw = tabs + e * tab_stride;
         int sa = nn, sb = n, sc = 1;
         if (AX) {
             const int ax = axes[e];
             if (ax == 1) { sa = n; sb = nn; sc = 1; }
             else if (ax == 2) { sa = 1; sb = nn; sc = n; }
         }
-        T x[kS3];
-        const double* rw = r + w * nd;
+        // every load of the item is issued before the first wait: the table
+        // words, the r fibre and the block kinds of T2.  The tables and r are
+        // read through buffer descriptors sized to the item, so a word past
+        // the element's tables or a lane outside the element (its offset set
+        // past the end) reads zero without touching memory.
+        const __amdgpu_buffer_rsrc_t rt =
+            __builtin_amdgcn_make_buffer_rsrc((void*)tabw, (short)0, nwords * 4, kBufWord3);
+        uint32_t tv[kTabPer];
 #pragma unroll
-        for (int f = 0; f < kS3; ++f) x[f] = (act && f < n) ? (T)rw[f * sa + p * sb + q * sc] : (T)0;
+        for (int k = 0; k < kTabPer; ++k) tv[k] = __builtin_amdgcn_raw_buffer_load_b32(rt, 4 * l + 256 * k, 0, 0);
+        const __amdgpu_buffer_rsrc_t rr =
+            __builtin_amdgcn_make_buffer_rsrc((void*)(r + w * nd), (short)0, nd * 8, kBufWord3);
+        const int lane_off = act ? 8 * (p * sb + q * sc) : (int)0x80000000;
+        double rv[kS3];
+#pragma unroll
+        for (int f = 0; f < kS3; ++f)
+            rv[f] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rr, lane_off + 8 * f * sa, 0, 0));
+        // kinds of columns 0..7 (the section is 256-byte aligned, 32 bytes per element)
+        const uint2 kdw = *(const uint2*)__builtin_assume_aligned(kinds + e * kMaxN, 8);
+        // words past the tables go to the first word of the relayout buffer,
+        // which is written before it is read (no branch, so that no load is
+        // moved behind one)
+#pragma unroll
+        for (int k = 0; k < kTabPer; ++k) {
+            const int id = l + 64 * k;
+            const int dst = id < nwords ? id : buf_unit;
+            if constexpr (sizeof(TT) == 2) {
+                // the word's two BF16 entries, low half first
+                const float2 v = {bf16_to_f32((uint16_t)(tv[k] & 0xffffu)), bf16_to_f32((uint16_t)(tv[k] >> 16))};
+                ((float2*)tb)[dst] = v;
+            } else {
+                ((uint32_t*)tb)[dst] = tv[k];
+            }
+        }
+        T x[kS3];
+#pragma unroll
+        for (int f = 0; f < kS3; ++f) x[f] = f < n ? (T)rv[f] : (T)0;
         wt.sync();
         // forward contractions: L0 on a (layout A), L1 on b (B), L2 on c (C)
         inl(L0, x);
@@ -130,9 +192,9 @@ __global__ void __launch_bounds__(256) k_apply_small3(int64_t E, int n, int nrhs
         const int i = q;              // the row this lane forms
         int j = n - 1;
         while (j >= 0) {
-            const int kd = kinds[e * kMaxN + j];
+            const int kd = (int)(((j < 4 ? kdw.x : kdw.y) >> (8 * (j & 3))) & 0xffu);
             if (kd != 2) {
-                const TT* Nj = N + j * nn;
+                const LT* Nj = N + j * nn;
                 if (act && q == j)
 #pragma unroll
                     for (int k = 0; k < kS3; ++k)
@@ -161,7 +223,7 @@ __global__ void __launch_bounds__(256) k_apply_small3(int64_t E, int n, int nrhs
             } else {
                 const int j1 = j - 1;
                 const T pp = (T)ldt(T2, j * n + j), qq = (T)ldt(T2, j1 * n + j), sv = (T)ldt(T2, j * n + j1);
-                const TT* Nj = N + j * nn;
+                const LT* Nj = N + j * nn;
                 if (act && (q == j1 || q == j)) {
                     T* dst = q == j1 ? xa : xb;
 #pragma unroll
@@ -231,15 +293,22 @@ __global__ void __launch_bounds__(256) k_apply_small3(int64_t E, int n, int nrhs
 template <typename T, typename TT, class Rnd, class Z>
 static hipError_t small3(hipStream_t s, int64_t E, int n, int nrhs, const void* tabs, int64_t tab_stride,
                          const int8_t* kinds, const double* r, Z* z, Rnd rnd, const int8_t* axes) {
+    // word copies of the tables need word-aligned element strides, and the
+    // kinds are read eight at a time
+    if ((tab_stride * (int64_t)sizeof(TT)) % 4 != 0 || ((uintptr_t)tabs & 3) != 0 || ((uintptr_t)kinds & 7) != 0)
+        return hipErrorInvalidValue;
     const int64_t work = E * nrhs;
     const int64_t wg = (work + 3) / 4;
     const int grid = (int)(wg < 65536 ? wg : 65536);
-    const size_t lds = 4 * small3_wave_bytes(n, sizeof(T), sizeof(TT));
+    const size_t lds = 4 * small3_wave_bytes(n, sizeof(T), sizeof(typename SmallLdsTab<TT>::type));
     if (axes)
-        hipLaunchKernelGGL((k_apply_small3<T, TT, Rnd, Z, true>), dim3(grid), dim3(256), lds, s, E, n, nrhs,
+        hipLaunchKernelGGL((k_apply_small3<T, TT, Rnd, Z, true, 0>), dim3(grid), dim3(256), lds, s, E, n, nrhs,
+                           (const TT*)tabs, tab_stride, kinds, r, z, rnd, axes);
+    else if (n == kS3)
+        hipLaunchKernelGGL((k_apply_small3<T, TT, Rnd, Z, false, kS3>), dim3(grid), dim3(256), lds, s, E, n, nrhs,
                            (const TT*)tabs, tab_stride, kinds, r, z, rnd, axes);
     else
-        hipLaunchKernelGGL((k_apply_small3<T, TT, Rnd, Z, false>), dim3(grid), dim3(256), lds, s, E, n, nrhs,
+        hipLaunchKernelGGL((k_apply_small3<T, TT, Rnd, Z, false, 0>), dim3(grid), dim3(256), lds, s, E, n, nrhs,
                            (const TT*)tabs, tab_stride, kinds, r, z, rnd, axes);
     return hipGetLastError();
 }

@@ -308,14 +308,21 @@ struct WaveTeam {
 };
 #endif
 
-// bf16 <-> f32 (round to nearest even), host and device
+// bf16 <-> f32 (round to nearest even), host and device.  The device form is
+// the hardware converter (v_cvt_pk_bf16_f32, round to nearest even); the host
+// form rounds the bit pattern.  They agree on every finite value (NaN
+// payloads may differ).
 KP_INLINE uint16_t f32_to_bf16(float f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
+#else
     union { float f; uint32_t u; } c;
     c.f = f;
     uint32_t u = c.u;
     if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
+#endif
 }
 KP_INLINE float bf16_to_f32(uint16_t h) {
     union { float f; uint32_t u; } c;
