@@ -41,6 +41,33 @@ constexpr int kTensor = 16 * kSA;
 
 __device__ __forceinline__ int xidx(int a, int b, int c) { return a * kSA + b * kSB + c; }
 
+// The right-hand sides s0 .. s0 + 15 of a 2D element (256 entries each,
+// contiguous from rs0): thread tid loads the entry pairs t = 2 (tid + 256 i),
+// i < 8, as 16-byte loads through a buffer descriptor that ends at the
+// element's last right-hand side, so the rows past it read zero with no
+// condition and every load is in flight before the first wait.
+constexpr int kBufWord3 = 0x00020000;  // raw buffer descriptor, word 3 (gfx9, 32-bit format)
+struct Rhs16 {
+    double2 v[8];
+};
+__device__ __forceinline__ Rhs16 load_rhs16(const double* rs0, int ns, int tid) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)rs0, (short)0, ns * 2048, kBufWord3);
+    Rhs16 x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        x.v[i] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * (tid + 256 * i), 0, 0));
+    return x;
+}
+template <class T>
+__device__ __forceinline__ void store_rhs16(const Rhs16& x, T* X, int tid) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int t = 2 * (tid + 256 * i);
+        X[xidx(t >> 8, (t >> 4) & 15, t & 15)] = (T)x.v[i].x;
+        X[xidx(t >> 8, (t >> 4) & 15, (t & 15) + 1)] = (T)x.v[i].y;
+    }
+}
+
 // f32 -> bf16, round to nearest even, on the hardware converter (gfx950
 // v_cvt_pk_bf16_f32); two at a time where the values come in pairs
 typedef float floatx2 __attribute__((ext_vector_type(2)));
@@ -435,10 +462,14 @@ __global__ void __launch_bounds__(256) k_apply16(int64_t E, int nrhs, const type
             for (int i = 0; i < n16 / 256; ++i) nbuf[i] = src[tid + 256 * i];
         }
         double2 rbuf[8];
+        Rhs16 rh;
         if (DIM == 3) {
             const double2* rw = (const double2*)(r + w * 4096);
 #pragma unroll
             for (int i = 0; i < 8; ++i) rbuf[i] = rw[tid + 256 * i];
+        } else {
+            const int s0 = grp * 16;
+            rh = load_rhs16(r + (e * nrhs + s0) * 256, nrhs - s0 < 16 ? nrhs - s0 : 16, tid);
         }
         const T t2v = (T)P::tab(tab + 6 * 256, tid);
         int kd[16];
@@ -458,12 +489,7 @@ __global__ void __launch_bounds__(256) k_apply16(int64_t E, int nrhs, const type
                 X[xidx(t >> 8, (t >> 4) & 15, (t & 15) + 1)] = (T)rbuf[i].y;
             }
         } else {
-            const int s0 = grp * 16;
-            for (int t = tid; t < 4096; t += 256) {
-                const int a = t >> 8, s = s0 + a;
-                X[xidx(a, (t >> 4) & 15, t & 15)] =
-                    s < nrhs ? (T)r[(e * nrhs + s) * 256 + (t & 255)] : (T)0;
-            }
+            store_rhs16(rh, X, tid);
         }
         __syncthreads();
         if (DIM == 3) {
@@ -561,6 +587,7 @@ __global__ void __launch_bounds__(256) k_apply16_rank3(int64_t E, int nrhs, cons
         int kd[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) kd[j] = kinds[e * kMaxN + j];
+        const Rhs16 rh = load_rhs16(r + (e * nrhs + s0) * 256, ns, tid);
         {
             uint4* dst = (uint4*)Nf;
 #pragma unroll
@@ -569,11 +596,9 @@ __global__ void __launch_bounds__(256) k_apply16_rank3(int64_t E, int nrhs, cons
         T2s[tid] = t2v;
         M3[tid] = stage_tab<P>(-a3);
         M3[256 + tid] = stage_tab<P>(b3);
-        for (int t = tid; t < 4096; t += 256) {
-            const int a = t >> 8, sl = s0 + a;
-            X[xidx(a, (t >> 4) & 15, t & 15)] = a < ns ? (T)r[(e * nrhs + sl) * 256 + (t & 255)] : (T)0;
-            Zs[t] = (T)0;
-        }
+        store_rhs16(rh, X, tid);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Zs[tid + 256 * i] = (T)0;
         __syncthreads();
         const typename P::Frag fA3 = P::load(M3, g, c);
         const typename P::Frag fB3 = P::load(M3 + 256, g, c);
