@@ -672,7 +672,14 @@ KP_HD int lanczos_top(const Team& tm, const Op& op, int m, int r, int kmax, doub
 #pragma unroll
                     for (int u = 0; u < 8; ++u) s -= L.h[j + u] * qv[u];
                 }
-                for (; j <= k; ++j) s -= L.h[j] * Q[(long)j * m + i];
+                if (j <= k) {  // the last k + 1 - j < 8 vectors: loads in flight together (clamped rows unused)
+                    double qv[7];
+#pragma unroll
+                    for (int u = 0; u < 7; ++u) qv[u] = Q[(long)(j + u <= k ? j + u : k) * m + i];
+#pragma unroll
+                    for (int u = 0; u < 7; ++u)
+                        if (j + u <= k) s -= L.h[j + u] * qv[u];
+                }
                 L.w[i] = s;
             }
             aco += L.h[k];
@@ -747,11 +754,18 @@ KP_HD int lanczos_top(const Team& tm, const Op& op, int m, int r, int kmax, doub
         }
         tm.sync();
     }
-    // Ritz vectors u_j = Q sel_j
+    // Ritz vectors u_j = Q sel_j (basis loads eight at a time, the same order)
     for (long t = tm.tid(); t < (long)r * m; t += tm.size()) {
         const int j = (int)(t / m), i = (int)(t % m);
         double s = 0.0;
-        for (int q = 0; q < steps; ++q) s += L.sel[j * kmax + q] * Q[(long)q * m + i];
+        for (int q0 = 0; q0 < steps; q0 += 8) {
+            double qv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) qv[u] = Q[(long)(q0 + u < steps ? q0 + u : steps - 1) * m + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q0 + u < steps) s += L.sel[j * kmax + q0 + u] * qv[u];
+        }
         U[t] = s;
     }
     tm.sync();

@@ -156,9 +156,13 @@ struct BlockTeam {
             for (int u = 0; u < 8; ++u) s[u] = 0.0;
             for (int i = lane; i < len; i += 64) {
                 const double vi = v[i];
+                // rows past k - 1 read row k - 1 (their sums are not stored):
+                // the eight loads carry no condition, so none waits for another
+                double qv[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (j0 + u * nw < k) s[u] += Q[(j0 + u * nw) * ldq + i] * vi;
+                for (int u = 0; u < 8; ++u) qv[u] = Q[(long)min(j0 + u * nw, k - 1) * ldq + i];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s[u] += qv[u] * vi;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) s[u] = wave_sum(s[u]);
@@ -267,9 +271,13 @@ struct WaveTeam {
             for (int u = 0; u < 8; ++u) s[u] = 0.0;
             for (int i = lane; i < len; i += 64) {
                 const double vi = v[i];
+                // rows past k - 1 read row k - 1 (their sums are not stored):
+                // the eight loads carry no condition, so none waits for another
+                double qv[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (j0 + u < k) s[u] += Q[(j0 + u) * ldq + i] * vi;
+                for (int u = 0; u < 8; ++u) qv[u] = Q[(long)min(j0 + u, k - 1) * ldq + i];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s[u] += qv[u] * vi;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) s[u] = wave_sum(s[u]);

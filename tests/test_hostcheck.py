@@ -112,7 +112,7 @@ def test_real_schur(lib, n):
         assert np.max(np.abs(np.sort_complex(np.linalg.eigvals(T)) - ev)) <= 1e-10 * np.max(np.abs(ev))
 
 
-@pytest.mark.parametrize("dim,n", [(2, 8), (2, 16), (3, 8)])
+@pytest.mark.parametrize("dim,n", [(2, 2), (2, 5), (2, 8), (2, 16), (2, 31), (3, 8)])
 def test_apply_all_precisions(lib, dim, n):
     params, _ = synth.mesh_params(2, dim, 33)
     rng = np.random.default_rng(1)
