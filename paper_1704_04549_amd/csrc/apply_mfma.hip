@@ -612,28 +612,22 @@ __global__ void __launch_bounds__(256) k_apply16_rank3(int64_t E, int nrhs, cons
             contract<P, 2>(fL[4], X, g, c, wv);
             // sum += d; per slice ||d||^2 and ||sum||^2 (thread tid holds entry
             // tid of every slice a = i)
-            double pd[16], pz[16];
+            // one slice at a time, so that two partial sums are live, not 32
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int t = tid + 256 * i;
                 const T dv = X[xidx(i, (t >> 4) & 15, t & 15)];
                 const T zv = Zs[t] + dv;
                 Zs[t] = zv;
-                pd[i] = (double)dv * (double)dv;
-                pz[i] = (double)zv * (double)zv;
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
+                double pd = (double)dv * (double)dv;
+                double pz = (double)zv * (double)zv;
                 for (int off = 32; off > 0; off >>= 1) {
-                    pd[i] += __shfl_xor(pd[i], off, 64);
-                    pz[i] += __shfl_xor(pz[i], off, 64);
+                    pd += __shfl_xor(pd, off, 64);
+                    pz += __shfl_xor(pz, off, 64);
                 }
-            }
-            if (l == 0) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    part[wv * 32 + i] = pd[i];
-                    part[wv * 32 + 16 + i] = pz[i];
+                if (l == 0) {
+                    part[wv * 32 + i] = pd;
+                    part[wv * 32 + 16 + i] = pz;
                 }
             }
             __syncthreads();
