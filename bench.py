@@ -174,16 +174,16 @@ def kernel_source_hash(names=("apply_mfma.hip", "kp_common.h")):
 # kernel source they were taken on (profiles/ holds the counter summaries and
 # the commands).
 MEASURED_TRAFFIC = {
-    "source_sha256": "db3efe704c2bfdef0196d9c36be7ad9ec1fb5fd14151aed40d368ea547ca52c5",
-    "bytes": {"fp32": 308557063, "fp64": 462471740},
-    "mfma_busy_frac": {"fp32": 0.2840, "fp64": 0.2908},
+    "source_sha256": "ad22b51e0a8a62d124300e12ffc4d689b11390f06dd9acb84df41b08b0da739e",
+    "bytes": {"fp32": 308408956, "fp64": 462483433},
+    "mfma_busy_frac": {"fp32": 0.2873, "fp64": 0.2907},
     "mfma_counted_flops": {"fp32": 3459661824, "fp64": 3459661824},
 }
 # HBM bytes of one 3D p = 15 setup (4096 elements, every setup kernel) from
 # the same counter runs, valid for the setup sources they were taken on
 MEASURED_SETUP_TRAFFIC = {
-    "source_sha256": "61702a359fe8f0dc67141d46d31f8d351af278a661183a5707956b4648560288",
-    "bytes": 1848070834,
+    "source_sha256": "f2f97560f8cc614c71065ea45de1b5d44bfb2d7ad1e6de65f7f272aae0067c98",
+    "bytes": 1848380363,
 }
 
 
