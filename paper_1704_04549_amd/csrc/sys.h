@@ -535,6 +535,30 @@ __device__ inline int sys_angle_search_grp(const BlockTeam& tm, int m, int n, co
 // index if already chosen (sys_angle_search_grp), else -1 (searched here).
 // Returns the element status bits (2 singular factor, 4 Schur not
 // converged, 8 non-finite tables).
+// Real Schur form of an s x s matrix (s <= 32) for the tables.  Its
+// reflector loops span at most s lanes, so on a workgroup team the first wave
+// runs the QR alone, with wave barriers in place of the workgroup barriers of
+// its thousands of dependent steps, and the other waves wait at one barrier.
+// flag: one shared double.
+template <class Team>
+KP_HD bool sys_schur(const Team& tm, int s, double* H, double* Q, double* sh, double* flag) {
+    (void)flag;
+    return real_schur(tm, s, H, Q, sh);
+}
+#if defined(__HIPCC__)
+__device__ inline bool sys_schur(const BlockTeam& tm, int s, double* H, double* Q, double* sh, double* flag) {
+    if (tm.group() == 0) {
+        WaveTeam wt;
+        const bool ok = real_schur(wt, s, H, Q, sh);
+        if (wt.leader()) *flag = ok ? 1.0 : 0.0;
+    }
+    tm.sync();
+    const bool ok = *flag != 0.0;
+    tm.sync();
+    return ok;
+}
+#endif
+
 template <class Team>
 KP_HD int tables_sys(const Team& tm, int m, int n, const double* F, double* tab, int8_t* kinds, double* work,
                      double* sh, int rot_k = -1) {
@@ -601,7 +625,7 @@ KP_HD int tables_sys(const Team& tm, int m, int n, const double* F, double* tab,
         tm.sync();
         if (!invert(tm, s, W0, W1, nullptr, mult)) status |= 2;
         mm(tm, s, W1, Foth, W2);                              // C = Finv^-1 Foth
-        if (!real_schur(tm, s, W2, W3, sh)) status |= 4;      // W2 <- T, W3 <- Q
+        if (!sys_schur(tm, s, W2, W3, sh, mult)) status |= 4;  // W2 <- T, W3 <- Q
         mtm(tm, s, W3, W1, W4);                               // L = Q^T Finv^-1
         double* L = tab + (side == 0 ? o.LA : o.LB);
         double* Q = tab + (side == 0 ? o.QA : o.QB);
