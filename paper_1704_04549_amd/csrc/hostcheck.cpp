@@ -159,7 +159,7 @@ int kph_setup_quad(int dim, int n, int mu, double tau, const double* c, const do
     static QuadTables Q;
     if (!make_quad_tables(n, mu, &Q)) return -1;
     HostTeam tm;
-    std::vector<double> work(quad_setup_doubles(n));
+    std::vector<double> work(quad_setup_doubles(dim, n, mu));
     QuadScratch qs;
     SetupWork W = carve_quad_setup(work.data(), n, &qs);
     QuadElem el{dim, n, mu, tau, c, a, nu, g};

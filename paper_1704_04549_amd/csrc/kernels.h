@@ -101,7 +101,7 @@ hipError_t launch_choose_axis(hipStream_t s, int64_t E, int64_t nfnn, const doub
 hipError_t launch_fill_i8(hipStream_t s, int64_t count, int8_t* p, int8_t v);
 
 // setup of general elements (quad.h, quad.hip): one workgroup per element,
-// grid workspace slots of ws_stride = quad_setup_doubles(n) doubles
+// grid workspace slots of ws_stride = quad_setup_doubles(dim, n, mu) doubles
 struct QuadTables;
 hipError_t launch_setup_quad(hipStream_t s, int grid, int64_t E, int dim, int n, int mu, double tau,
                              const QuadTables* qt, const double* c, const double* a, const double* nu,

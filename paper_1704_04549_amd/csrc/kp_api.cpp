@@ -361,7 +361,7 @@ kp_status kp_setup_quad(kp_ctx c, const kp_quad_batch* q, void* precond, int32_t
         }
         c->d_quad[q->n][q->mu] = d;
     }
-    const int64_t wsd = (quad_setup_doubles(q->n) + 31) / 32 * 32;
+    const int64_t wsd = (quad_setup_doubles(q->dim, q->n, q->mu) + 31) / 32 * 32;
     const int grid = (int)(E < 2048 ? E : 2048);
     kp_status st;
     if ((st = ensure_ws(c, (size_t)wsd * grid * sizeof(double), &c->ws, &c->ws_bytes)) != KP_OK) return st;

@@ -127,6 +127,40 @@ KP_INLINE double coef3(const QuadElem& el, const QuadTables& Q, int t, int al, i
     }
 }
 
+// Term t's weighted coefficients in C (quad_coef_doubles layout) at (al, be, ga):
+// the value coef3 returns, read with one load.  The face terms depend on two of
+// the three indices (the third is the face's single point).
+KP_INLINE const double* coef3_base(const double* C, int mu, int t) {
+    const long m3 = (long)mu * mu * mu, m2 = (long)mu * mu;
+    return t == 0 ? C : t <= 3 ? C + t * m3 : t <= 6 ? C + 4 * m3 : C + 5 * m3 + (t - 7) * m2;
+}
+KP_INLINE double coef3w(const double* Ct, int mu, int t, int al, int be, int ga) {
+    return t <= 6 ? Ct[((long)al * mu + be) * mu + ga]
+           : t <= 8 ? Ct[be * mu + ga]
+           : t <= 10 ? Ct[al * mu + ga]
+                     : Ct[al * mu + be];
+}
+// C <- the weighted coefficients of the element (the products coef3 forms, in
+// its order)
+template <class Team>
+KP_HD void coef3_weights(const Team& tm, const QuadElem& el, const QuadTables& Q, double* C) {
+    const int mu = el.mu;
+    const long m3 = (long)mu * mu * mu, m2 = (long)mu * mu;
+    for (long p3 = tm.tid(); p3 < m3; p3 += tm.size()) {
+        const int al = (int)(p3 / m2), be = (int)((p3 / mu) % mu), ga = (int)(p3 % mu);
+        C[p3] = coef3(el, Q, 0, al, be, ga);
+        for (int d = 0; d < 3; ++d) C[(1 + d) * m3 + p3] = coef3(el, Q, 1 + d, al, be, ga);
+        C[4 * m3 + p3] = coef3(el, Q, 4, al, be, ga);
+    }
+    for (long idx = tm.tid(); idx < 6 * m2; idx += tm.size()) {
+        const int f = (int)(idx / m2), i = (int)((idx / mu) % mu), j = (int)(idx % mu);
+        const int t = 7 + f;
+        // (be, ga) for t = 7, 8; (al, ga) for 9, 10; (al, be) for 11, 12
+        C[5 * m3 + idx] = t <= 8 ? coef3(el, Q, t, 0, i, j) : t <= 10 ? coef3(el, Q, t, i, 0, j) : coef3(el, Q, t, i, j, 0);
+    }
+    tm.sync();
+}
+
 // ----------------------------------------------------------------- 2D terms
 struct Term2 {
     int tx, ty;
@@ -167,15 +201,24 @@ KP_HD void terms2_of_element(const Team& tm, const QuadElem& el, const QuadTable
     tm.sync();
 }
 
+// The 3D element's weighted term coefficients (coef3 of every term, read once
+// per Lanczos product instead of four loads): the mass, the three advection
+// components and the diffusion (the three diffusion terms share it) as mu^3
+// tensors, then the six face terms as mu^2 matrices.
+KP_INLINE long quad_coef_doubles(int dim, int mu) {
+    return dim == 3 ? 5L * mu * mu * mu + 6L * mu * mu : 0;
+}
+
 // Scratch of the general-element operators (team-shared): doubles needed
-KP_INLINE long quad_work_doubles(int n) {
+KP_INLINE long quad_work_doubles(int dim, int n, int mu) {
     const long M2 = (long)kQuadMaxMu * kQuadMaxMu;
     return 9 * M2 /*S*/ + 9 * M2 /*W*/ + 45 * M2 /*M*/ + 9 * M2 /*F2 or Sd*/ + 2 * kQuadMaxMu * kMaxN /*T*/ +
-           2 * kQuadTypes * kQuadMaxMu /*q, Qp*/ + 5 * M2 /*R*/ + 64 + 0 * n;
+           2 * kQuadTypes * kQuadMaxMu /*q, Qp*/ + 5 * M2 /*R*/ + quad_coef_doubles(dim, mu) + 64 + 0 * n;
 }
 
 struct QuadScratch {
     double *S, *W, *M, *F, *T, *q, *Qp, *R;
+    double* C;  // 3D: the element's weighted term coefficients (quad_coef_doubles)
 };
 KP_INLINE QuadScratch carve_quad(double* p) {
     const long M2 = (long)kQuadMaxMu * kQuadMaxMu;
@@ -187,7 +230,8 @@ KP_INLINE QuadScratch carve_quad(double* p) {
     s.T = p; p += 2 * kQuadMaxMu * kMaxN;
     s.q = p; p += kQuadTypes * kQuadMaxMu;
     s.Qp = p; p += kQuadTypes * kQuadMaxMu;
-    s.R = p;
+    s.R = p; p += 5 * M2;
+    s.C = p;
     return s;
 }
 
@@ -200,6 +244,7 @@ KP_HD void quad_left(const Team& tm, const QuadTables& Q, const double* x, doubl
         const int d = idx / (mu * n), al = (idx / n) % mu, c = idx % n;
         const double* L = d ? Q.dPhi : Q.Phi;
         double s = 0.0;
+#pragma unroll 8
         for (int a = 0; a < n; ++a) s += L[al * n + a] * x[a * n + c];
         T[idx] = s;
     }
@@ -216,6 +261,7 @@ KP_HD void quad_left(const Team& tm, const QuadTables& Q, const double* x, doubl
         const double* Tx = T + (p == 0 ? 0 : mu * n) + al * n;  // Phi x for PP, dPhi x for dP, dd
         const double* Rr = (p == 2 ? Q.dPhi : Q.Phi) + al * n;
         double s = 0.0;
+#pragma unroll 8
         for (int c = 0; c < n; ++c) s += Tx[c] * Rr[c];
         q[p * kQuadMaxMu + al] = s;
     }
@@ -233,6 +279,7 @@ KP_HD void quad_right_left(const Team& tm, const QuadTables& Q, const double* Qp
     for (int t = tm.tid(); t < n * n; t += tm.size()) {
         const int a = t / n, c = t % n;
         double s = 0.0;
+#pragma unroll 8
         for (int al = 0; al < mu; ++al)
             s += Q.Phi[al * n + a] * Qp[al] * Q.Phi[al * n + c] +
                  Q.dPhi[al * n + a] * (Qp[kQuadMaxMu + al] * Q.Phi[al * n + c] +
@@ -261,6 +308,7 @@ struct OpQuad2 {
                 for (int t = 0; t < nt; ++t) {
                     if (T[t].ty != y) continue;
                     const int mx = qmu(*Q, T[t].tx);
+#pragma unroll 8
                     for (int al = 0; al < mx; ++al)
                         v += T[t].F[(long)al * T[t].ld + be] * q[T[t].tx * kQuadMaxMu + al];
                 }
@@ -280,8 +328,11 @@ struct OpQuad2 {
             const int yp = idx / mu, bp = idx % mu;
             double v = 0.0;
             if (bp < qmu(*Q, yp))
-                for (int yy = 0; yy < kQuadTypes; ++yy)
-                    for (int be = 0; be < qmu(*Q, yy); ++be) v += qK(*Q, yy, yp, be, bp) * s.S[yy * kQuadMaxMu + be];
+                for (int yy = 0; yy < kQuadTypes; ++yy) {
+                    const int my = qmu(*Q, yy);
+#pragma unroll 8
+                    for (int be = 0; be < my; ++be) v += qK(*Q, yy, yp, be, bp) * s.S[yy * kQuadMaxMu + be];
+                }
             s.W[yp * kQuadMaxMu + bp] = v;
         }
         tm.sync();
@@ -293,6 +344,7 @@ struct OpQuad2 {
                 for (int t = 0; t < nt; ++t) {
                     if (T[t].tx != p) continue;
                     const int my = qmu(*Q, T[t].ty);
+#pragma unroll 8
                     for (int be = 0; be < my; ++be)
                         v += T[t].F[(long)al * T[t].ld + be] * s.W[T[t].ty * kQuadMaxMu + be];
                 }
@@ -345,7 +397,9 @@ struct OpQuad3 {
                     term3(t, &tx, &ty, &tz, &tg);
                     if (tg != g) continue;
                     const int mx = qmu(*Q, tx);
-                    for (int al = 0; al < mx; ++al) v += coef3(el, *Q, t, al, be, ga) * q[tx * kQuadMaxMu + al];
+                    const double* Ct = coef3_base(s.C, mu, t);
+#pragma unroll 8
+                    for (int al = 0; al < mx; ++al) v += coef3w(Ct, mu, t, al, be, ga) * q[tx * kQuadMaxMu + al];
                 }
             S[g * M2 + (long)be * kQuadMaxMu + ga] = sc * v;
         }
@@ -366,8 +420,11 @@ struct OpQuad3 {
             int gy, gz;
             group3(g, &gy, &gz);
             double v = 0.0;
-            if (be < qmu(*Q, gy) && gp < qmu(*Q, zt))
-                for (int ga = 0; ga < qmu(*Q, gz); ++ga) v += s.S[g * M2 + (long)be * kQuadMaxMu + ga] * qK(*Q, gz, zt, ga, gp);
+            if (be < qmu(*Q, gy) && gp < qmu(*Q, zt)) {
+                const int mz = qmu(*Q, gz);
+#pragma unroll 8
+                for (int ga = 0; ga < mz; ++ga) v += s.S[g * M2 + (long)be * kQuadMaxMu + ga] * qK(*Q, gz, zt, ga, gp);
+            }
             s.M[(g * kQuadTypes + zt) * M2 + (long)be * kQuadMaxMu + gp] = v;
         }
         tm.sync();
@@ -382,8 +439,9 @@ struct OpQuad3 {
                     int gy, gz;
                     group3(g, &gy, &gz);
                     const double* Mg = s.M + (g * kQuadTypes + hz) * M2;
-                    for (int be = 0; be < qmu(*Q, gy); ++be)
-                        v += qK(*Q, gy, hy, be, bp) * Mg[(long)be * kQuadMaxMu + gp];
+                    const int my = qmu(*Q, gy);
+#pragma unroll 8
+                    for (int be = 0; be < my; ++be) v += qK(*Q, gy, hy, be, bp) * Mg[(long)be * kQuadMaxMu + gp];
                 }
             s.W[h * M2 + (long)bp * kQuadMaxMu + gp] = v;
         }
@@ -398,7 +456,10 @@ struct OpQuad3 {
                     term3(t, &tx, &ty, &tz, &tg);
                     if (tx != p || be >= qmu(*Q, ty)) continue;
                     const double* Wg = s.W + tg * M2 + (long)be * kQuadMaxMu;
-                    for (int ga = 0; ga < qmu(*Q, tz); ++ga) v += coef3(el, *Q, t, al, be, ga) * Wg[ga];
+                    const double* Ct = coef3_base(s.C, mu, t);
+                    const int mz = qmu(*Q, tz);
+#pragma unroll 8
+                    for (int ga = 0; ga < mz; ++ga) v += coef3w(Ct, mu, t, al, be, ga) * Wg[ga];
                 }
             s.R[(p * kQuadMaxMu + al) * kQuadMaxMu + be] = v;
         }
@@ -437,10 +498,10 @@ KP_INLINE int quad_kmax(int n) {
 
 // Per-slot work of the general-element setup: the Lanczos work for m = n^2
 // and kmax = quad_kmax(n), the three Ritz vectors, then the quad scratch
-KP_INLINE long quad_setup_doubles(int n) {
+KP_INLINE long quad_setup_doubles(int dim, int n, int mu) {
     const long m = (long)n * n, k = quad_kmax(n);
     return (k + 1) * m + m + (k + 2) + 2 * (k + 1) + 2 * k + k * k + 3 * k + 3 + 8 + 2 * k + 4 + 3 * m +
-           quad_work_doubles(n) + 64;
+           quad_work_doubles(dim, n, mu) + 64;
 }
 KP_INLINE SetupWork carve_quad_setup(double* p, int n, QuadScratch* qs) {
     const long m = (long)n * n, k = quad_kmax(n);
@@ -484,6 +545,7 @@ KP_HD int setup_quad_element(const Team& tm, const QuadElem& el, const QuadTable
                                     n, sigma);
         return status;
     }
+    coef3_weights(tm, el, Q, qs.C);
     OpQuad3 op{&Q, el, qs};
     lanczos_start(tm, W.L.Q, nn, nullptr);
     const int conv = lanczos_top(tm, op, nn, 1, kmax, 1e-14, W.L, W.U);

@@ -105,16 +105,16 @@ int main() {
         }
         for (long t = 0; t < dim * md; ++t) a[t] = nd01(rng);
         for (long t = 0; t < 2 * dim * mf; ++t) g[t] = u01(rng);
-        std::vector<double> ws(quad_setup_doubles(n));
+        double* ws = exact<double>(quad_setup_doubles(dim, n, mu));
         QuadScratch qs;
-        SetupWork W = carve_quad_setup(ws.data(), n, &qs);
+        SetupWork W = carve_quad_setup(ws, n, &qs);
         const long nn = (long)n * n;
         double* F = exact<double>((dim == 2 ? 4 : 5) * nn);
         double* sig = exact<double>(4);
         QuadElem el{dim, n, mu, 0.1, c, a, nu, g};
         Term2 T2[kQuadGroups3];
         setup_quad_element(tm, el, Q, F, sig, W, qs, T2);
-        free(c); free(a); free(nu); free(g); free(F); free(sig);
+        free(c); free(a); free(nu); free(g); free(F); free(sig); free(ws);
         ++checked;
     }
     // systems blocks: nc components, m = nc n first factors
