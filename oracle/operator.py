@@ -14,8 +14,10 @@ opposite face (l1 or l0).  Elements whose face flag is zero have no coupling.
 
 Two forms: ``apply`` (matrix-free, dense per-element blocks) and
 ``assemble`` (scipy.sparse, small meshes).  Pinned by
-tests/test_oracle_operator.py (the two forms agree; discrete conservation
-1^T (G - mass) = 0 for a uniform velocity).
+tests/test_oracle_operator_krylov.py (the two forms agree; discrete
+conservation 1^T (G - mass) = 0 for a uniform velocity; every coupling block
+equals the upwind face integral of the weak form on polynomials, which fixes
+its sign, face pairing and neighbour side).
 """
 from __future__ import annotations
 

@@ -35,6 +35,46 @@ def test_discrete_conservation_uniform_velocity(dim, n, mesh):
     assert np.max(np.abs(np.ones(G.shape[0]) @ (G - mass))) < 1e-14 * np.abs(G).max() * n ** 2
 
 
+@pytest.mark.parametrize("dim,n", [(2, 4), (2, 6), (3, 3)])
+def test_coupling_blocks_match_the_upwind_face_integral(dim, n):
+    """Every off-diagonal block of the assembled operator against the upwind
+    face term written out from the weak form (Sec. 3.4.1, the face part of eq.
+    jac-entries), integrated exactly on polynomials: for a trial function u on
+    the neighbour f across face (axis, side) of element e and a test function v
+    on e, v^T G_ef u = tau u_face int v(x_axis = side) u_f(x_axis = 1 - side)
+    over the face when the face is an inflow face of e (u_face < 0), else 0.
+    This fixes the sign, the face pairing (the neighbour's opposite face) and
+    the neighbour table independently of the oracle's coupling code."""
+    from tests.test_oracle_blocks import integral, poly_eval, restrict
+    from scipy import signal
+    mesh = 3
+    params, nbr = synth.mesh_params(mesh, dim, seed=40 + n)
+    G = operator.assemble(params, nbr, n, dim).toarray()
+    T = tables(n)
+    N = n ** dim
+    rng = np.random.default_rng(n)
+    checked = inflow = 0
+    for e in range(mesh ** dim):
+        for ax in range(dim):
+            for side in (0, 1):
+                f = int(nbr[e, 2 * ax + side])
+                B = G[e * N:(e + 1) * N, f * N:(f + 1) * N]
+                cu = rng.standard_normal((n,) * dim)
+                cv = rng.standard_normal((n,) * dim)
+                u = poly_eval(cu, T["x"])
+                v = poly_eval(cv, T["x"])
+                uf = params[e, 8 + 2 * ax + side]
+                want = 0.0
+                if uf < 0.0:
+                    face = signal.convolve(restrict(cv, ax, float(side)), restrict(cu, ax, float(1 - side)))
+                    want = params[e, 6] * uf * (integral(face) if dim > 1 else face)
+                    inflow += 1
+                got = v @ B @ u
+                assert abs(got - want) <= 1e-12 * (1.0 + abs(want)) * n, (e, ax, side, got, want)
+                checked += 1
+    assert checked == (mesh ** dim) * 2 * dim and 0 < inflow < checked
+
+
 def test_fgmres_one_step_with_exact_inverse():
     n, E = 6, 5
     params = synth.draw_params(E, 2, seed=2)
