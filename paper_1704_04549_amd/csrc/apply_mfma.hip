@@ -322,14 +322,18 @@ struct PolBF16X3 {
 // ----------------------------------------------------------- building blocks
 // X <- M (x)_axis X in place, axis in {0, 1, 2} of X[a][b][c].  Wave wv owns
 // the column tiles t = wv, wv+4, wv+8, wv+12; all reads finish (barrier)
-// before any write.
-template <class P, int AXIS>
+// before any write.  SKIP: tiles t >= nt are all zero and stay so (2D: the
+// slices past the work item's last right-hand side) and are skipped (the
+// rank-3 series; the rank-2 2D apply keeps all sixteen, which measured faster:
+// skipping raised its FP32 registers 111 -> 152 and cost a wave per SIMD).
+template <class P, int AXIS, bool SKIP = false>
 __device__ __forceinline__ void contract(const typename P::Frag& f, typename P::T* X, int g, int c,
-                                         int wv) {
+                                         int wv, int nt = 16) {
     typename P::Acc acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int t = wv + 4 * i;
+        if (SKIP && t >= nt) continue;
         if (AXIS == 0)
             acc[i] = P::mma(f, [&](int k, int j) { return X[xidx(k, t, j)]; }, g, c);
         else if (AXIS == 1)
@@ -341,6 +345,7 @@ __device__ __forceinline__ void contract(const typename P::Frag& f, typename P::
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int t = wv + 4 * i;
+        if (SKIP && t >= nt) continue;
         for (int v = 0; v < 4; ++v) {
             if (AXIS == 0)
                 X[xidx(P::orow(g, v), t, c)] = acc[i][v];
@@ -605,11 +610,11 @@ __global__ void __launch_bounds__(256) k_apply16_rank3(int64_t E, int nrhs, cons
         bool done = false, ok = false;
         for (int it = 0; it < maxit && !done; ++it) {
             // d = P2^{-1} X
-            contract<P, 1>(fL[0], X, g, c, wv);
-            contract<P, 2>(fL[1], X, g, c, wv);
+            contract<P, 1, true>(fL[0], X, g, c, wv, ns);
+            contract<P, 2, true>(fL[1], X, g, c, wv, ns);
             sylvester<P>(Nf, fT1, kd, T2s, X, g, c, l, wv);
-            contract<P, 1>(fL[3], X, g, c, wv);
-            contract<P, 2>(fL[4], X, g, c, wv);
+            contract<P, 1, true>(fL[3], X, g, c, wv, ns);
+            contract<P, 2, true>(fL[4], X, g, c, wv, ns);
             // sum += d; per slice ||d||^2 and ||sum||^2 (thread tid holds entry
             // tid of every slice a = i)
             // one slice at a time, so that two partial sums are live, not 32
@@ -645,8 +650,8 @@ __global__ void __launch_bounds__(256) k_apply16_rank3(int64_t E, int nrhs, cons
                 break;
             }
             // X = -(A3 (x) B3) d
-            contract<P, 1>(fA3, X, g, c, wv);
-            contract<P, 2>(fB3, X, g, c, wv);
+            contract<P, 1, true>(fA3, X, g, c, wv, ns);
+            contract<P, 2, true>(fB3, X, g, c, wv, ns);
         }
         for (int t = tid; t < 4096; t += 256) {
             const int a = t >> 8, sl = s0 + a;
