@@ -367,32 +367,39 @@ struct OpGram {
 struct OpStream {
     int n, s;
     const double* A;
-    double* yk;   // [s] scratch
+    double* yk;   // [s^2] scratch (apply only)
+    // y = R(A) R(A)^T x in two passes over the block: z = R(A)^T x (s^2
+    // entries, one per thread at a time), then y = R(A) z (one per thread);
+    // each sum's terms eight at a time so that their loads are in flight
+    // together
     template <class Team>
     KP_HD void apply(const Team& tm, const double* x, double* y) const {
         const int m = n * n;
         const long N = (long)n * s;
-        for (int t = tm.tid(); t < m; t += tm.size()) y[t] = 0.0;
-        for (int K = 0; K < s; ++K) {
-            // yk[K'] = sum_{a,a'} x[a n + a'] A[(a s + K) N + a' s + K']
-            for (int K2 = tm.tid(); K2 < s; K2 += tm.size()) {
-                double acc = 0.0;
-                for (int t = 0; t < m; ++t) {
-                    const int a = t / n, a2 = t % n;
-                    acc += x[t] * A[((long)a * s + K) * N + (long)a2 * s + K2];
-                }
-                yk[K2] = acc;
-            }
-            tm.sync();
-            for (int t = tm.tid(); t < m; t += tm.size()) {
+        const long ss = (long)s * s;
+        for (long q = tm.tid(); q < ss; q += tm.size()) {
+            const int K = (int)(q / s), K2 = (int)(q % s);
+            // yk[K s + K'] = sum_{a,a'} x[a n + a'] A[(a s + K) N + a' s + K']
+            double acc = 0.0;
+#pragma unroll 8
+            for (int t = 0; t < m; ++t) {
                 const int a = t / n, a2 = t % n;
-                const double* row = A + ((long)a * s + K) * N + (long)a2 * s;
-                double acc = 0.0;
-                for (int K2 = 0; K2 < s; ++K2) acc += row[K2] * yk[K2];
-                y[t] += acc;
+                acc += x[t] * A[((long)a * s + K) * N + (long)a2 * s + K2];
             }
-            tm.sync();
+            yk[q] = acc;
         }
+        tm.sync();
+        for (int t = tm.tid(); t < m; t += tm.size()) {
+            const int a = t / n, a2 = t % n;
+            double acc = 0.0;
+            for (int K = 0; K < s; ++K) {
+                const double* row = A + ((long)a * s + K) * N + (long)a2 * s;
+#pragma unroll 8
+                for (int K2 = 0; K2 < s; ++K2) acc += row[K2] * yk[(long)K * s + K2];
+            }
+            y[t] = acc;
+        }
+        tm.sync();
     }
     // y = R(A) v for a right vector v (s x s): y[a n + a2] = sum_{K,K2} A[a s + K, a2 s + K2] v[K s + K2]
     template <class Team>
@@ -404,6 +411,7 @@ struct OpStream {
             double acc = 0.0;
             for (int K = 0; K < s; ++K) {
                 const double* row = A + ((long)a * s + K) * N + (long)a2 * s;
+#pragma unroll 8
                 for (int K2 = 0; K2 < s; ++K2) acc += row[K2] * v[(long)K * s + K2];
             }
             y[t] = acc;
@@ -419,6 +427,7 @@ struct OpStream {
         for (long q = tm.tid(); q < (long)s * s; q += tm.size()) {
             const int K = (int)(q / s), K2 = (int)(q % s);
             double acc = 0.0;
+#pragma unroll 8
             for (int t = 0; t < m; ++t) {
                 const int a = t / n, a2 = t % n;
                 acc += x[t] * A[((long)a * s + K) * N + (long)a2 * s + K2];
