@@ -353,6 +353,7 @@ struct OpGram {
     KP_HD void apply(const Team& tm, const double* x, double* y) const {
         for (int i = tm.tid(); i < msz; i += tm.size()) {
             double s = 0.0;
+#pragma unroll 8
             for (int j = 0; j < msz; ++j) s += G[(long)i * msz + j] * x[j];
             y[i] = s;
         }
@@ -451,6 +452,7 @@ KP_HD void explicit_gram(const Team& tm, int n, int s, const double* A, double* 
         for (int K = 0; K < s; ++K) {
             const double* ra = A + ((long)a * s + K) * N + (long)a2 * s;
             const double* rb = A + ((long)b * s + K) * N + (long)b2 * s;
+#pragma unroll 8
             for (int K2 = 0; K2 < s; ++K2) acc += ra[K2] * rb[K2];
         }
         G[(long)p * m + q] = acc;
@@ -1556,6 +1558,7 @@ struct SetupWork {
                     // row kmax + 10)
     double* Vr;     // kmax x kmax (rank >= 3: accumulated Jacobi rotations)
     LanczosWork L;
+    const double* Gpre = nullptr;  // explicit blocks: the element's stage-1 Gram, formed beforehand, or null
 };
 constexpr int kGramMax = 64;  // explicit Gram kept when the left size n^2 <= this
 
@@ -1981,8 +1984,12 @@ KP_HD int setup_element(const Team& tm, int dim, int n, int rank, const Tables1D
             OpStream st{n, n, block, W.d};
             RightStream rs{&st};
             if (nn <= kGramMax) {
-                explicit_gram(tm, n, n, block, W.G);
-                OpGram og{nn, W.G};
+                const double* G1 = W.Gpre;
+                if (!G1) {
+                    explicit_gram(tm, n, n, block, W.G);
+                    G1 = W.G;
+                }
+                OpGram og{nn, G1};
                 status |= ksvd_stage<kRefine>(tm, og, rs, n, rank, kmax, guess, W, factors, 2L * nn,
                                      factors + nn, 2L * nn, n, sigma);
             } else {
@@ -2002,8 +2009,12 @@ KP_HD int setup_element(const Team& tm, int dim, int n, int rank, const Tables1D
     double sig1[4];
     if (expl) {
         if (nn > kGramMax) return 64;  // unsupported size for explicit 3D
-        explicit_gram(tm, n, nn, block, W.G);
-        OpGram og{nn, W.G};
+        const double* G1 = W.Gpre;
+        if (!G1) {
+            explicit_gram(tm, n, nn, block, W.G);
+            G1 = W.G;
+        }
+        OpGram og{nn, G1};
         lanczos_start(tm, W.L.Q, nn, guess);
         const int conv = lanczos_top(tm, og, nn, 1, kmax, 1e-14, W.L, W.U);
         status |= conv ? 0 : 1;

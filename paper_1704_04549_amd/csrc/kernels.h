@@ -22,7 +22,10 @@ hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int 
                         const Tables1D* tab, const double* params, const double* blocks,
                         const double* guess, double* factors, double* sigma, int32_t* status,
                         double* ws, int64_t ws_stride, const int32_t* skip = nullptr,
-                        int32_t status_or = 0);
+                        int32_t status_or = 0, const double* grams = nullptr);
+// stage-1 Gram matrices R(A) R(A)^T of explicit blocks with n^2 <= 64, grams
+// [E][n^2][n^2] (for launch_setup's grams)
+hipError_t launch_explicit_gram(hipStream_t s, int64_t E, int dim, int n, const double* blocks, double* grams);
 // learned setup: the judge of predicted factors `pred` against the SVD's
 // (`factors` with their FP64 tables, learned.h); out [E][4] and accept [E]
 // optional; use_pred: accepted predictions replace the factors (status 0),

@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int ra
                                                const double* blocks, const double* guess,
                                                double* factors, double* sigma, int32_t* status,
                                                double* ws, int64_t ws_stride, const int32_t* skip,
-                                               int32_t status_or) {
+                                               int32_t status_or, const double* grams) {
     __shared__ double red[4 * kMaxReduce];
     __shared__ Tables1D T;
     extern __shared__ double small[];
@@ -65,6 +65,7 @@ __global__ void __launch_bounds__(256) k_setup(int64_t E, int dim, int n, int ra
         const long gs = dim == 3 ? 2 : 1;
         const double* g = guess ? guess + e * gs * nn : nullptr;
         const double* g2 = (guess && dim == 3) ? g + nn : nullptr;
+        W.Gpre = grams ? grams + e * nn * nn : nullptr;
         int st = setup_element<kRefine>(tm, dim, n, rank, T, params + e * kRecLen, blk, g,
                                factors + e * nf * nn, sigma + e * 4, W, g2);
         if (threadIdx.x == 0) status[e] = st | status_or;
@@ -84,7 +85,8 @@ __global__ void __launch_bounds__(256) k_setup_waves(int64_t E, int dim_rt, int 
                                                      const double* blocks, const double* guess,
                                                      double* factors, double* sigma, int32_t* status,
                                                      double* ws, int64_t ws_stride, const int32_t* skip,
-                                                     int32_t status_or, int64_t small_stride) {
+                                                     int32_t status_or, int64_t small_stride,
+                                                     const double* grams) {
     __shared__ Tables1D T;
     extern __shared__ double small[];
     {
@@ -111,6 +113,7 @@ __global__ void __launch_bounds__(256) k_setup_waves(int64_t E, int dim_rt, int 
         const double* blk = expl ? blocks + e * nd * nd : nullptr;
         const double* g = guess ? guess + e * gs * nn : nullptr;
         const double* g2 = (guess && dim == 3) ? g + nn : nullptr;
+        W.Gpre = grams ? grams + e * nn * nn : nullptr;
         int st = setup_element<kRefine>(tm, DIM, n, rank, T, params + e * kRecLen, blk, g,
                                         factors + e * nf * nn, sigma + e * 4, W, g2);
         if ((threadIdx.x & 63) == 0) status[e] = st | status_or;
@@ -694,18 +697,100 @@ hipError_t launch_build_blocks(hipStream_t s, int64_t E, int dim, int n, const T
     return hipGetLastError();
 }
 
+// Stage-1 Gram matrices of explicit blocks, G_e = R(A_e) R(A_e)^T (m = n^2 <=
+// 64 rows, s^2 columns, s = n in 2D and n^2 in 3D), one wave per element on
+// the FP64 matrix cores: 16 x 16 output tiles (P, Q), Q >= P, of 16 x 16 x 4
+// products over the columns; the lane (g, c) loads R[16 P + c][k0 + g] of
+// each row tile once and feeds it to every tile of that row or column tile.
+// Rows past m and columns past s^2 read a valid entry and feed zero.  Each
+// block entry is read once (the rearrangement is applied in the addressing).
+__global__ void __launch_bounds__(256) k_explicit_gram(int64_t E, int n, int s, const double* blocks, double* grams) {
+    typedef double dx4 __attribute__((ext_vector_type(4)));
+    const int m = n * n;
+    const long N = (long)n * s, len = (long)s * s, nd2 = N * N;
+    const int lane = (int)(threadIdx.x & 63), g = lane >> 4, c = lane & 15;
+    const int mt = (m + 15) / 16;
+    long roff[4];
+    bool rok[4];
+#pragma unroll
+    for (int P = 0; P < 4; ++P) {
+        const int p = 16 * P + c;
+        rok[P] = p < m;
+        const int pp = rok[P] ? p : 0;
+        roff[P] = ((long)(pp / n) * s) * N + (long)(pp % n) * s;
+    }
+    for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < E; e += (int64_t)gridDim.x * 4) {
+        const double* A = blocks + e * nd2;
+        dx4 acc[10];
+#pragma unroll
+        for (int t = 0; t < 10; ++t) acc[t] = dx4{0.0, 0.0, 0.0, 0.0};
+        for (long k0 = 0; k0 < len; k0 += 8) {
+            double r[2][4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const long k = k0 + 4 * u + g;
+                const bool kok = k < len;
+                const long kk = kok ? k : len - 1;
+                const long col = (kk / s) * N + kk % s;
+#pragma unroll
+                for (int P = 0; P < 4; ++P) {
+                    const double v = A[roff[P] + col];
+                    r[u][P] = (kok && rok[P]) ? v : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                int t = 0;
+#pragma unroll
+                for (int P = 0; P < 4; ++P)
+#pragma unroll
+                    for (int Q = P; Q < 4; ++Q, ++t)
+                        if (Q < mt) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(r[u][P], r[u][Q], acc[t], 0, 0, 0);
+            }
+        }
+        // the lane holds D[g + 4 v][c] of each tile
+        double* G = grams + e * (long)m * m;
+        int t = 0;
+#pragma unroll
+        for (int P = 0; P < 4; ++P)
+#pragma unroll
+            for (int Q = P; Q < 4; ++Q, ++t)
+                if (Q < mt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 16 * P + g + 4 * v, j = 16 * Q + c;
+                        if (i < m && j < m) {
+                            G[(long)i * m + j] = acc[t][v];
+                            G[(long)j * m + i] = acc[t][v];
+                        }
+                    }
+    }
+}
+
+hipError_t launch_explicit_gram(hipStream_t s, int64_t E, int dim, int n, const double* blocks, double* grams) {
+    if (E <= 0) return hipSuccess;
+    if (n * n > 64) return hipErrorInvalidValue;
+    const int64_t wg = (E + 3) / 4;
+    const int grid = (int)(wg < 65536 ? wg : 65536);
+    hipLaunchKernelGGL(k_explicit_gram, dim3(grid), dim3(256), 0, s, E, n, dim == 3 ? n * n : n, blocks, grams);
+    return hipGetLastError();
+}
+
 hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int rank,
                         const Tables1D* tab, const double* params, const double* blocks,
                         const double* guess, double* factors, double* sigma, int32_t* status,
-                        double* ws, int64_t ws_stride, const int32_t* skip, int32_t status_or) {
+                        double* ws, int64_t ws_stride, const int32_t* skip, int32_t status_or,
+                        const double* grams) {
     const size_t small = setup_small_doubles(n, blocks != nullptr);
     if (rank >= 3) {
         hipLaunchKernelGGL(k_setup<true>, dim3(grid), dim3(256), small * sizeof(double), s, E, dim, n, rank,
-                           tab, params, blocks, guess, factors, sigma, status, ws, ws_stride, skip, status_or);
+                           tab, params, blocks, guess, factors, sigma, status, ws, ws_stride, skip, status_or,
+                           grams);
     } else if (4 * ((small + 31) / 32 * 32) * sizeof(double) + sizeof(Tables1D) > kSetupWavesLdsMax) {
         // the four waves' small arrays do not fit: one workgroup per element
         hipLaunchKernelGGL(k_setup<false>, dim3(grid), dim3(256), small * sizeof(double), s, E, dim, n, rank,
-                           tab, params, blocks, guess, factors, sigma, status, ws, ws_stride, skip, status_or);
+                           tab, params, blocks, guess, factors, sigma, status, ws, ws_stride, skip, status_or,
+                           grams);
     } else {
         // one wave per element: the grid's workspace slots (a multiple of 4,
         // see setup_slots) serve grid / 4 workgroups
@@ -715,7 +800,7 @@ hipError_t launch_setup(hipStream_t s, int grid, int64_t E, int dim, int n, int 
                              : (blocks ? k_setup_waves<false, 2, true> : k_setup_waves<false, 2, false>);
         hipLaunchKernelGGL(kern, dim3(g4), dim3(256), 4 * small_stride * sizeof(double), s, E, dim, n, rank,
                            tab, params, blocks, guess, factors, sigma, status, ws, ws_stride, skip, status_or,
-                           small_stride);
+                           small_stride, grams);
     }
     return hipGetLastError();
 }

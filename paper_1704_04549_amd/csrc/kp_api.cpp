@@ -237,8 +237,17 @@ kp_status kp_setup(kp_ctx c, const kp_batch* b, int32_t rank, int32_t mode, void
                                 nullptr, fac + k * E * nfnn, sig + k * E * 4, st2 + k * E, (double*)c->ws, wsd));
         KP_HIP(launch_choose_axis(c->stream, E, nfnn, fac, sig, st2, factors, sigma, status, axis));
     } else if (mode == KP_SETUP_SVD) {
+        // explicit blocks with n^2 <= 64: their stage-1 Gram matrices first, on
+        // the matrix cores, each block read once
+        const double* grams = nullptr;
+        if (b->blocks && (long)b->n * b->n <= kGramMax) {
+            const size_t gbytes = (size_t)E * b->n * b->n * b->n * b->n * sizeof(double);
+            if ((st = ensure_ws(c, gbytes, &c->ks, &c->ks_bytes)) != KP_OK) return st;
+            KP_HIP(launch_explicit_gram(c->stream, E, b->dim, b->n, b->blocks, (double*)c->ks));
+            grams = (const double*)c->ks;
+        }
         KP_HIP(launch_setup(c->stream, grid, E, b->dim, b->n, rank, T, b->params, b->blocks, nullptr,
-                            factors, sigma, status, (double*)c->ws, wsd));
+                            factors, sigma, status, (double*)c->ws, wsd, nullptr, 0, grams));
     } else {
         // 1. predicted factors into the context's scratch
         const size_t nn = (size_t)b->n * b->n;
