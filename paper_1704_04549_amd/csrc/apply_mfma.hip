@@ -26,6 +26,8 @@
 // accumulation) and BF16X3 (split hi + lo operands, three bf16 products).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "elem_ops.h"
 #include "kernels.h"
 
@@ -928,6 +930,248 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8
     }
 }
 
+// ------------------------------------------------- 2D, register-resident
+// One workgroup of four waves per (element, group of up to 16 right-hand
+// sides): the route of the 3D kernel without its first axis, the group's
+// right-hand sides taking that axis's place in the lane slot.  Route: load
+// (c, a, b) -> L on c -> transpose (b, a, c) -> L on b -> Sylvester (T1 on b,
+// T2 on c) -> Q1 on b -> transpose (c, a, b) -> Q2 on c -> store, with a the
+// right-hand side, b the x and c the y index.  Lane (g, cl) holds right-hand
+// side cl; in tile t its four values are the y entries orow(g, v) of x row t,
+// read through a buffer descriptor that ends at the group's last right-hand
+// side (zero past it, so every load is issued with no condition).
+template <class P, int WPE, class Z = double>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) k_apply16r2(
+    int64_t E, int nrhs, const typename P::Tab* tabs, int64_t tab_stride, const int8_t* kinds, const double* r,
+    Z* z, int stagger, int nres) {
+    typedef typename P::T T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* M = (T*)smem;       // transpose buffer; the Sylvester buffers alias it
+    T* T2s = M + kR3Work;  // T2, row-major
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, g = l >> 4, c = l & 15;
+    if ((int)blockIdx.x < nres && 2 * (int)blockIdx.x >= nres)
+        for (int i = 0; i < stagger; ++i) __builtin_amdgcn_s_sleep(32);
+    const int groups = (nrhs + 15) / 16;
+    const int64_t work = E * groups;
+    for (int64_t it = blockIdx.x; it < work; it += gridDim.x) {
+        const int64_t e = it / groups;
+        const int s0 = (int)(it % groups) * 16;
+        const int ns = nrhs - s0 < 16 ? nrhs - s0 : 16;
+        const double* r0 = r + (e * nrhs + s0) * 256;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)r0, (short)0, ns * 2048, kBufWord3);
+        double rb[4][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int base = 8 * (c * 256 + tile_of(s, w) * 16);
+            if constexpr (std::is_same<P, PolF64>::value) {
+                // rows g + 4 v: four separate entries
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    rb[s][v] = __builtin_bit_cast(
+                        double, __builtin_amdgcn_raw_buffer_load_b64(rs, base + 8 * P::orow(g, v), 0, 0));
+            } else {
+                // rows 4 g .. 4 g + 3: 32 contiguous bytes
+                const double2 u = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, base + 32 * g, 0, 0));
+                const double2 q = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, base + 32 * g + 16, 0, 0));
+                rb[s][0] = u.x;
+                rb[s][1] = u.y;
+                rb[s][2] = q.x;
+                rb[s][3] = q.y;
+            }
+        }
+        const typename P::Tab* tab = tabs + e * tab_stride;
+        const typename P::Frag fLb = P::row_frag(tab, 0, g, c), fLc = P::row_frag(tab, 1, g, c);
+        const typename P::Frag fQ1 = P::row_frag(tab, 3, g, c), fQ2 = P::row_frag(tab, 4, g, c);
+        const typename P::Frag fT1 = P::row_frag(tab, 5, g, c);
+        typename P::Frag fN[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) fN[s] = P::row_frag(tab, 7 + tile_of(s, w), g, c);
+        const T t2v = (T)P::tab(tab + 6 * 256, tid);
+        int kd[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) kd[j] = kinds[e * kMaxN + j];
+        typename P::Vec R[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) R[s][v] = (T)rb[s][v];
+        T2s[tid] = t2v;  // read after the barriers of the first transpose
+
+        contract_reg<P, false>(fLc, R);  // L on c
+        transpose_tg<P>(R, M, g, c, w);  // (b, a, c)
+        contract_reg<P, false>(fLb, R);  // L on b
+        sylvester_col<P>(R, fN, fT1, kd, T2s, M, l, w);
+        contract_reg<P, false>(fQ1, R);  // Q1 on b
+        transpose_tg<P>(R, M, g, c, w);  // (c, a, b)
+        contract_reg<P, false>(fQ2, R);  // Q2 on c
+
+        // streaming stores, as in the 3D kernel; lanes past the group's last
+        // right-hand side store nothing
+        if (c < ns) {
+            Z* zw = z + (e * nrhs + s0 + c) * 256;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    __builtin_nontemporal_store((Z)R[s][v], &zw[tile_of(s, w) * 16 + P::orow(g, v)]);
+        }
+    }
+}
+
+// ------------------------------------------ 2D rank 3, register-resident
+// The Neumann series of k_apply16_rank3 with the tensor, the running sum and
+// the element's fragments in registers (FP32 and FP64).  Each later term
+// d_{k+1} = -P2^{-1} (A3 (x) B3) d_k runs the rank-2 route of k_apply16r2
+// with its first two products merged with the Kronecker factors: the L
+// factor on y times B3 and the L factor on x times -A3, formed once per
+// element on the matrix cores, so that a term costs one rank-2 apply and no
+// more.  d_0 = P2^{-1} r takes the L factors alone.  The stopping test and
+// the flags are those of k_apply16_rank3.
+
+// P2^{-1} on the register tensor, from layout (c, a, b) back to (c, a, b);
+// fc, fb: the first products on c and on b
+template <class P>
+__device__ __forceinline__ void p2inv_reg(typename P::Vec (&R)[4], const typename P::Frag& fc,
+                                          const typename P::Frag& fb, const typename P::Frag& fQ1,
+                                          const typename P::Frag& fQ2, const typename P::Frag (&fN)[4],
+                                          const typename P::Frag& fT1, const int* kd, const typename P::T* T2s,
+                                          typename P::T* M, int g, int c, int l, int w) {
+    contract_reg<P, false>(fc, R);   // on c
+    transpose_tg<P>(R, M, g, c, w);  // (b, a, c)
+    contract_reg<P, false>(fb, R);   // on b
+    sylvester_col<P>(R, fN, fT1, kd, T2s, M, l, w);
+    contract_reg<P, false>(fQ1, R);  // Q1 on b
+    transpose_tg<P>(R, M, g, c, w);  // (c, a, b)
+    contract_reg<P, false>(fQ2, R);  // Q2 on c
+}
+
+// the A-side fragment of X Y for the lane's row c: Gt = Y^T X^T on the
+// matrix cores, whose output lane (g, c) holds Gt[orow(g, v)][c] = (X Y)[c][orow(g, v)],
+// from the fragment of X (row c of X) and the lane's column of Y^T
+template <class P>
+__device__ __forceinline__ typename P::Frag frag_product(const typename P::Frag& fx, const typename P::T (&yt)[4]) {
+    typename P::Frag a;
+    typename P::Vec b;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        a.a[kk] = yt[kk];
+        b[kk] = fx.a[kk];
+    }
+    const typename P::Acc d = P::template mmr<false>(a, b);
+    typename P::Frag f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) f.a[v] = (typename P::T)d[v];
+    return f;
+}
+
+template <class P, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) k_apply16r2_rank3(
+    int64_t E, int nrhs, const typename P::Tab* tabs, int64_t tab_stride, const int8_t* kinds,
+    const double* factors, const double* r, double* z, int maxit, double tol, int8_t* flags) {
+    typedef typename P::T T;
+    typedef typename P::Frag Frag;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* M = (T*)smem;                      // transpose buffer; the Sylvester buffers alias it
+    T* T2s = M + kR3Work;                 // T2, row-major
+    T* Zs = T2s + 256;                    // the running sum: thread tid's value i at i * 256 + tid
+    double* part = (double*)(Zs + 4096);  // [wave][slice]: ||d||^2 (0..15), ||z||^2 (16..31)
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, g = l >> 4, c = l & 15;
+    const int groups = (nrhs + 15) / 16;
+    const int64_t work = E * groups;
+    for (int64_t it = blockIdx.x; it < work; it += gridDim.x) {
+        const int64_t e = it / groups;
+        const int s0 = (int)(it % groups) * 16;
+        const int ns = nrhs - s0 < 16 ? nrhs - s0 : 16;
+        const double* r0 = r + (e * nrhs + s0) * 256;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)r0, (short)0, ns * 2048, kBufWord3);
+        double rb[4][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int base = 8 * (c * 256 + tile_of(s, w) * 16);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                rb[s][v] = __builtin_bit_cast(double,
+                                              __builtin_amdgcn_raw_buffer_load_b64(rs, base + 8 * P::orow(g, v), 0, 0));
+        }
+        const typename P::Tab* tab = tabs + e * tab_stride;
+        const Frag fLb = P::row_frag(tab, 0, g, c), fLc = P::row_frag(tab, 1, g, c);
+        const Frag fQ1 = P::row_frag(tab, 3, g, c), fQ2 = P::row_frag(tab, 4, g, c);
+        const Frag fT1 = P::row_frag(tab, 5, g, c);
+        Frag fN[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) fN[s] = P::row_frag(tab, 7 + tile_of(s, w), g, c);
+        const T t2v = (T)P::tab(tab + 6 * 256, tid);
+        // columns of B3 and -A3: the lane's entries [orow(g, kk)][c]
+        const double* F3 = factors + e * 6 * 256;
+        T b3t[4], a3t[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            b3t[kk] = (T)F3[5 * 256 + P::orow(g, kk) * 16 + c];
+            a3t[kk] = (T)(-F3[4 * 256 + P::orow(g, kk) * 16 + c]);
+        }
+        int kd[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) kd[j] = kinds[e * kMaxN + j];
+        typename P::Vec R[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) R[s][v] = (T)rb[s][v];
+        T2s[tid] = t2v;  // read after the barriers of the first transpose
+        const Frag fGc = frag_product<P>(fLc, b3t);  // L_y B3
+        const Frag fGb = frag_product<P>(fLb, a3t);  // -L_x A3
+        p2inv_reg<P>(R, fLc, fLb, fQ1, fQ2, fN, fT1, kd, T2s, M, g, c, l, w);  // d_0
+        bool ok = false;
+        for (int k = 0; k < maxit; ++k) {
+            if (k > 0) p2inv_reg<P>(R, fGc, fGb, fQ1, fQ2, fN, fT1, kd, T2s, M, g, c, l, w);
+            // z += d (the thread's own entries of Zs); per right-hand side (the
+            // lane's c) ||d||^2 and ||z||^2
+            double pd = 0.0, pz = 0.0;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    T* zp = Zs + (4 * s + v) * 256 + tid;
+                    const T zv = k == 0 ? R[s][v] : *zp + R[s][v];
+                    *zp = zv;
+                    pd += (double)R[s][v] * (double)R[s][v];
+                    pz += (double)zv * (double)zv;
+                }
+            pd += __shfl_xor(pd, 16, 64);
+            pz += __shfl_xor(pz, 16, 64);
+            pd += __shfl_xor(pd, 32, 64);
+            pz += __shfl_xor(pz, 32, 64);
+            if (g == 0) {
+                part[w * 32 + c] = pd;
+                part[w * 32 + 16 + c] = pz;
+            }
+            __syncthreads();
+            bool conv = true, finite = true;
+            for (int i = 0; i < ns; ++i) {
+                const double d2 = part[i] + part[32 + i] + part[64 + i] + part[96 + i];
+                const double z2 = part[16 + i] + part[48 + i] + part[80 + i] + part[112 + i];
+                if (!(d2 == d2) || !(z2 == z2) || d2 > 1e300 || z2 > 1e300) finite = false;
+                if (!(d2 <= tol * tol * z2)) conv = false;
+            }
+            __syncthreads();
+            if (!finite) break;
+            if (conv) {
+                ok = true;
+                break;
+            }
+        }
+        if (c < ns) {
+            double* zw = z + (e * nrhs + s0 + c) * 256;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    zw[tile_of(s, w) * 16 + P::orow(g, v)] = (double)Zs[(4 * s + v) * 256 + tid];
+        }
+        if (tid == 0 && !ok) flags[e] = 1;
+    }
+}
+
 // WPE: waves per SIMD the register allocation is held to (FP32, BF16: 4 with
 // 128 registers; split BF16: 3; FP64: 2).  One workgroup per item: a
 // persistent grid that prefetches the next item into registers measured
@@ -966,6 +1210,20 @@ static hipError_t launch16r3(hipStream_t st, int64_t E, int nrhs, const void* ta
     return hipGetLastError();
 }
 
+// the 2D register-resident kernel; WPE and STAGGER as for the 3D kernel
+template <class P, int WPE, int STAGGER, class Z>
+static hipError_t launch16r2(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
+                             const int8_t* kinds, const double* r, Z* z) {
+    const int64_t work = E * ((nrhs + 15) / 16);
+    const int grid = (int)(work < kApply16Grid ? work : kApply16Grid);
+    const size_t lds = (kR3Work + 256) * sizeof(typename P::T);
+    const int nres = WPE * device_cus();
+    const int stagger = (STAGGER > 0 && nres > 0 && work >= 4 * (int64_t)nres) ? STAGGER : 0;
+    hipLaunchKernelGGL((k_apply16r2<P, WPE, Z>), dim3(grid), dim3(256), lds, st, E, nrhs,
+                       (const typename P::Tab*)tabs, tab_stride, kinds, r, z, stagger, nres);
+    return hipGetLastError();
+}
+
 template <class P, int DIM, class Z>
 static hipError_t launch16(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
                            const void* frags, const int8_t* kinds, const double* r, Z* z) {
@@ -995,9 +1253,26 @@ static hipError_t launch16_rank3(hipStream_t st, int64_t E, int nrhs, const void
     return hipGetLastError();
 }
 
+// the register-resident series (FP32, FP64)
+template <class P, int WPE>
+static hipError_t launch16r2_rank3(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
+                                   const int8_t* kinds, const double* factors, const double* r, double* z,
+                                   int maxit, double tol, int8_t* flags) {
+    const int64_t work = E * ((nrhs + 15) / 16);
+    const int grid = (int)(work < kApply16Grid ? work : kApply16Grid);
+    const size_t lds = (kR3Work + 256 + 4096) * sizeof(typename P::T) + 128 * sizeof(double);
+    hipLaunchKernelGGL((k_apply16r2_rank3<P, WPE>), dim3(grid), dim3(256), lds, st, E, nrhs,
+                       (const typename P::Tab*)tabs, tab_stride, kinds, factors, r, z, maxit, tol, flags);
+    return hipGetLastError();
+}
+
 hipError_t launch_apply16_rank3(hipStream_t s, int prec, int64_t E, int nrhs, const void* tabs,
                                 int64_t tab_stride, const void* frags, const int8_t* kinds,
-                                const double* factors, const double* r, double* z, int8_t* flags) {
+                                const double* factors, const double* r, double* z, int8_t* flags, bool lds2d) {
+    if (!lds2d && prec == 0)
+        return launch16r2_rank3<PolF64, 2>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 256, 1e-14, flags);
+    if (!lds2d && prec == 1)
+        return launch16r2_rank3<PolF32, 3>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 128, 2e-7, flags);
     switch (prec) {
         // term limits: a spectral radius up to about 0.88 still converges within them
         case 0: return launch16_rank3<PolF64>(s, E, nrhs, tabs, tab_stride, frags, kinds, factors, r, z, 256, 1e-14,
@@ -1013,13 +1288,21 @@ hipError_t launch_apply16_rank3(hipStream_t s, int prec, int64_t E, int nrhs, co
 
 hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
                           int64_t tab_stride, const void* frags, const int8_t* kinds,
-                          const double* r, double* z, const int8_t* axes) {
+                          const double* r, double* z, const int8_t* axes, bool lds2d) {
     if (dim == 3) {
         switch (prec) {
             case 0: return launch16r3<PolF64, 2, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
             case 1: return launch16r3<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
             case 2: return launch16r3<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
             default: return launch16r3<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
+        }
+    }
+    if (!lds2d) {
+        switch (prec) {
+            case 0: return launch16r2<PolF64, 2, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 1: return launch16r2<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 2: return launch16r2<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            default: return launch16r2<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
         }
     }
     switch (prec) {
@@ -1032,13 +1315,20 @@ hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs,
 
 hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
                           int64_t tab_stride, const void* frags, const int8_t* kinds,
-                          const double* r, float* z, const int8_t* axes) {
+                          const double* r, float* z, const int8_t* axes, bool lds2d) {
     if (prec == 0) return hipErrorInvalidValue;  // FP64 arithmetic: z stays FP64
     if (dim == 3) {
         switch (prec) {
             case 1: return launch16r3<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
             case 2: return launch16r3<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
             default: return launch16r3<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z, axes);
+        }
+    }
+    if (!lds2d) {
+        switch (prec) {
+            case 1: return launch16r2<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 2: return launch16r2<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            default: return launch16r2<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
         }
     }
     switch (prec) {

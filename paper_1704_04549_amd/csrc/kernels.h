@@ -66,10 +66,13 @@ hipError_t launch_apply_rank3(hipStream_t s, int prec, int64_t E, int n, int nrh
 // 2D rank 3 with n = 16 on the matrix cores (apply_mfma.hip): the Neumann
 // series of P2^{-1} (A3 (x) B3) over the rank-2 apply, 16 right-hand sides per
 // workgroup; flags[e] (int8, zeroed by the caller) is set for an element whose
-// series did not converge, for launch_apply_rank3 with only = flags
+// series did not converge, for launch_apply_rank3 with only = flags.  FP32 and
+// FP64 run the register-resident kernel unless lds2d is set; BF16 and split
+// BF16 always run the LDS-resident one.
 hipError_t launch_apply16_rank3(hipStream_t s, int prec, int64_t E, int nrhs, const void* tabs,
                                 int64_t tab_stride, const void* frags, const int8_t* kinds,
-                                const double* factors, const double* r, double* z, int8_t* flags);
+                                const double* factors, const double* r, double* z, int8_t* flags,
+                                bool lds2d = false);
 hipError_t launch_cast_tables(hipStream_t s, int64_t count, const double* t64, float* t32,
                               uint16_t* hi, uint16_t* lo, float* t2);
 hipError_t launch_frag_tables(hipStream_t s, int64_t E, const double* t64, double* f64f, float* f32f,
@@ -79,10 +82,11 @@ hipError_t launch_frag_tables(hipStream_t s, int64_t E, const double* t64, doubl
 // fragment-ordered copy of the same precision.
 constexpr int64_t kApply16Grid = 1 << 20;
 // axes: the 3D elements' split axes (kp_setup with KP_OPT_SPLIT_AXIS), or NULL
-// (every element split on x)
+// (every element split on x); lds2d: 2D runs the LDS-resident kernel (tensor
+// in LDS, fragment-ordered tables) instead of the register-resident one
 hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
                           int64_t tab_stride, const void* frags, const int8_t* kinds,
-                          const double* r, double* z, const int8_t* axes = nullptr);
+                          const double* r, double* z, const int8_t* axes = nullptr, bool lds2d = false);
 hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
                                 const void* tabs, int64_t tab_stride, const int8_t* kinds,
                                 const double* r, double* z, const int8_t* axes = nullptr);
@@ -90,7 +94,7 @@ hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int
 // results are FP32 numbers, stored exactly; prec FP64 is refused)
 hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
                           int64_t tab_stride, const void* frags, const int8_t* kinds,
-                          const double* r, float* z, const int8_t* axes = nullptr);
+                          const double* r, float* z, const int8_t* axes = nullptr, bool lds2d = false);
 hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
                                 const void* tabs, int64_t tab_stride, const int8_t* kinds,
                                 const double* r, float* z, const int8_t* axes = nullptr);

@@ -121,7 +121,11 @@ kp_status kp_set_option(kp_ctx c, int32_t option, int64_t value) {
     if (!c) return KP_ERR_ARG;
     switch (option) {
         case KP_OPT_FGMRES_GRAPHS: c->use_graphs = value != 0; return KP_OK;
-        case KP_OPT_APPLY_MFMA16: c->use_mfma16 = value != 0; return KP_OK;
+        case KP_OPT_APPLY_MFMA16:
+            if (value < 0 || value > 2) return KP_ERR_ARG;
+            c->use_mfma16 = value != 0;
+            c->apply16_lds2d = value == 2;
+            return KP_OK;
         case KP_OPT_FGMRES_Z32: c->fgmres_z32 = value != 0; return KP_OK;
         case KP_OPT_OPERATOR_COLS: c->op_cols = value != 0; return KP_OK;
         case KP_OPT_SPLIT_AXIS: c->split_axis = value != 0; return KP_OK;
@@ -479,7 +483,8 @@ static kp_status apply_impl(kp_ctx c, const kp_batch* b, int32_t rank, const voi
                                     : prec == KP_BF16 ? (const void*)(pc + L.fbf)
                                                       : (const void*)(pc + L.fbf3);
                 KP_HIP(launch_fill_i8(c->stream, E, flags, 0));
-                KP_HIP(launch_apply16_rank3(c->stream, prec, E, nrhs, tabs, L.ne, frags, kd, fac, r, z, flags));
+                KP_HIP(launch_apply16_rank3(c->stream, prec, E, nrhs, tabs, L.ne, frags, kd, fac, r, z, flags,
+                                                c->apply16_lds2d));
                 KP_HIP(launch_apply_rank3(c->stream, prec, E, b->n, nrhs, fac, tabs, L.ne, kd, r, z, flags));
             } else {
                 KP_HIP(launch_apply_rank3(c->stream, prec, E, b->n, nrhs, fac, tabs, L.ne, kd, r, z));
@@ -491,7 +496,7 @@ static kp_status apply_impl(kp_ctx c, const kp_batch* b, int32_t rank, const voi
                             : prec == KP_BF16 ? (const void*)(pc + L.fbf)
                                               : (const void*)(pc + L.fbf3);
         KP_HIP(launch_apply16(c->stream, prec, E, b->dim, nrhs, tabs, L.ne, frags,
-                              (const int8_t*)(pc + L.kinds), r, z, axes));
+                              (const int8_t*)(pc + L.kinds), r, z, axes, c->apply16_lds2d));
     } else if (b->dim == 3 && b->n <= 8 && c->use_small3) {
         KP_HIP(launch_apply_small3(c->stream, prec, E, b->n, nrhs, tabs, L.ne, (const int8_t*)(pc + L.kinds), r, z,
                                    axes));
