@@ -753,8 +753,8 @@ def main():
         busy = MEASURED_TRAFFIC["mfma_busy_frac"].get(args.prec)
         counted = MEASURED_TRAFFIC["mfma_counted_flops"].get(args.prec)
     kname = ("k_apply16r3, n=16 3D matrix-core path" if (dim == 3 and n == 16)
-             else "k_apply16_rank3, n=16 2D rank-3 Neumann series on the matrix cores" if (n == 16 and rank == 3)
-             else "k_apply16, n=16 2D matrix-core path" if n == 16
+             else "k_apply16r2_rank3, n=16 2D rank-3 Neumann series on the matrix cores, tensor in registers" if (n == 16 and rank == 3)
+             else "k_apply16r2, n=16 2D matrix-core path, tensor in registers" if n == 16
              else "k_apply_rank3" if rank == 3
              else "k_apply_small3, one wave per element and right-hand side" if (dim == 3 and n <= 8)
              else "k_apply_generic")

@@ -1019,8 +1019,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8
 }
 
 // ------------------------------------------ 2D rank 3, register-resident
-// The Neumann series of k_apply16_rank3 with the tensor, the running sum and
-// the element's fragments in registers (FP32 and FP64).  Each later term
+// The Neumann series of k_apply16_rank3 with the tensor and the element's
+// fragments in registers (the running sum in LDS, one slot per thread).  Each later term
 // d_{k+1} = -P2^{-1} (A3 (x) B3) d_k runs the rank-2 route of k_apply16r2
 // with its first two products merged with the Kronecker factors: the L
 // factor on y times B3 and the L factor on x times -A3, formed once per
@@ -1048,19 +1048,52 @@ __device__ __forceinline__ void p2inv_reg(typename P::Vec (&R)[4], const typenam
 // the A-side fragment of X Y for the lane's row c: Gt = Y^T X^T on the
 // matrix cores, whose output lane (g, c) holds Gt[orow(g, v)][c] = (X Y)[c][orow(g, v)],
 // from the fragment of X (row c of X) and the lane's column of Y^T
+// (the BF16 forms: the product of the fragment's values in FP32, rounded to
+// the fragment's form afterwards)
+__device__ __forceinline__ void frag_rows(const PolBF16::Frag& f, float (&x)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = bf16_to_f32((uint16_t)f.a[i]);
+}
+__device__ __forceinline__ void frag_rows(const PolBF16X3::Frag& f, float (&x)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = bf16_to_f32((uint16_t)f.hi[i]) + bf16_to_f32((uint16_t)f.lo[i]);
+}
+__device__ __forceinline__ void frag_set(PolBF16::Frag& f, const floatx4& d) { f.a = bf16x4s(d[0], d[1], d[2], d[3]); }
+__device__ __forceinline__ void frag_set(PolBF16X3::Frag& f, const floatx4& d) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        short h, lo;
+        PolBF16X3::split(d[i], &h, &lo);
+        f.hi[i] = h;
+        f.lo[i] = lo;
+    }
+}
 template <class P>
 __device__ __forceinline__ typename P::Frag frag_product(const typename P::Frag& fx, const typename P::T (&yt)[4]) {
-    typename P::Frag a;
-    typename P::Vec b;
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        a.a[kk] = yt[kk];
-        b[kk] = fx.a[kk];
-    }
-    const typename P::Acc d = P::template mmr<false>(a, b);
     typename P::Frag f;
+    if constexpr (std::is_same<P, PolF32>::value || std::is_same<P, PolF64>::value) {
+        typename P::Frag a;
+        typename P::Vec b;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) f.a[v] = (typename P::T)d[v];
+        for (int kk = 0; kk < 4; ++kk) {
+            a.a[kk] = yt[kk];
+            b[kk] = fx.a[kk];
+        }
+        const typename P::Acc d = P::template mmr<false>(a, b);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) f.a[v] = (typename P::T)d[v];
+    } else {
+        float x[4];
+        frag_rows(fx, x);
+        PolF32::Frag a;
+        PolF32::Vec b;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            a.a[kk] = yt[kk];
+            b[kk] = x[kk];
+        }
+        frag_set(f, PolF32::mmr<false>(a, b));
+    }
     return f;
 }
 
@@ -1210,7 +1243,8 @@ static hipError_t launch16r3(hipStream_t st, int64_t E, int nrhs, const void* ta
     return hipGetLastError();
 }
 
-// the 2D register-resident kernel; WPE and STAGGER as for the 3D kernel
+// the 2D register-resident kernel; WPE and STAGGER as for the 3D kernel (a
+// stagger of 0 to 14 units changed the 2D p = 15 FP32 apply by under 3%: 0)
 template <class P, int WPE, int STAGGER, class Z>
 static hipError_t launch16r2(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
                              const int8_t* kinds, const double* r, Z* z) {
@@ -1253,7 +1287,9 @@ static hipError_t launch16_rank3(hipStream_t st, int64_t E, int nrhs, const void
     return hipGetLastError();
 }
 
-// the register-resident series (FP32, FP64)
+// the register-resident series.  FP32 is held to four waves
+// per SIMD: 44 bytes per lane spill, outside the term loop (4.1 ms against
+// 4.5 ms at three waves and no spill, 2D p = 15)
 template <class P, int WPE>
 static hipError_t launch16r2_rank3(hipStream_t st, int64_t E, int nrhs, const void* tabs, int64_t tab_stride,
                                    const int8_t* kinds, const double* factors, const double* r, double* z,
@@ -1272,7 +1308,11 @@ hipError_t launch_apply16_rank3(hipStream_t s, int prec, int64_t E, int nrhs, co
     if (!lds2d && prec == 0)
         return launch16r2_rank3<PolF64, 2>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 256, 1e-14, flags);
     if (!lds2d && prec == 1)
-        return launch16r2_rank3<PolF32, 3>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 128, 2e-7, flags);
+        return launch16r2_rank3<PolF32, 4>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 128, 2e-7, flags);
+    if (!lds2d && prec == 2)
+        return launch16r2_rank3<PolBF16, 4>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 64, 2e-3, flags);
+    if (!lds2d && prec == 3)
+        return launch16r2_rank3<PolBF16X3, 3>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 96, 5e-6, flags);
     switch (prec) {
         // term limits: a spectral radius up to about 0.88 still converges within them
         case 0: return launch16_rank3<PolF64>(s, E, nrhs, tabs, tab_stride, frags, kinds, factors, r, z, 256, 1e-14,
@@ -1300,9 +1340,9 @@ hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs,
     if (!lds2d) {
         switch (prec) {
             case 0: return launch16r2<PolF64, 2, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            case 1: return launch16r2<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 1: return launch16r2<PolF32, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
             case 2: return launch16r2<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            default: return launch16r2<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            default: return launch16r2<PolBF16X3, 3, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
         }
     }
     switch (prec) {
@@ -1326,9 +1366,9 @@ hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs,
     }
     if (!lds2d) {
         switch (prec) {
-            case 1: return launch16r2<PolF32, 4, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            case 1: return launch16r2<PolF32, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
             case 2: return launch16r2<PolBF16, 4, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
-            default: return launch16r2<PolBF16X3, 3, 7>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
+            default: return launch16r2<PolBF16X3, 3, 0>(s, E, nrhs, tabs, tab_stride, kinds, r, z);
         }
     }
     switch (prec) {

@@ -66,9 +66,8 @@ hipError_t launch_apply_rank3(hipStream_t s, int prec, int64_t E, int n, int nrh
 // 2D rank 3 with n = 16 on the matrix cores (apply_mfma.hip): the Neumann
 // series of P2^{-1} (A3 (x) B3) over the rank-2 apply, 16 right-hand sides per
 // workgroup; flags[e] (int8, zeroed by the caller) is set for an element whose
-// series did not converge, for launch_apply_rank3 with only = flags.  FP32 and
-// FP64 run the register-resident kernel unless lds2d is set; BF16 and split
-// BF16 always run the LDS-resident one.
+// series did not converge, for launch_apply_rank3 with only = flags; lds2d:
+// the LDS-resident kernel instead of the register-resident one.
 hipError_t launch_apply16_rank3(hipStream_t s, int prec, int64_t E, int nrhs, const void* tabs,
                                 int64_t tab_stride, const void* frags, const int8_t* kinds,
                                 const double* factors, const double* r, double* z, int8_t* flags,
