@@ -174,16 +174,16 @@ def kernel_source_hash(names=("apply_mfma.hip", "kp_common.h")):
 # kernel source they were taken on (profiles/ holds the counter summaries and
 # the commands).
 MEASURED_TRAFFIC = {
-    "source_sha256": "45f44c58a89a48c1a5ad7d32d259c9c91137b22b7b7271b9d1098d8b66f5a50a",
-    "bytes": {"fp32": 308553002, "fp64": 462444511},
-    "mfma_busy_frac": {"fp32": 0.2796, "fp64": 0.2921},
+    "source_sha256": "4f652ef39dafb3395ac700365a531445579292db6b3134d169311962788cf4a7",
+    "bytes": {"fp32": 308531097, "fp64": 462462946},
+    "mfma_busy_frac": {"fp32": 0.2845, "fp64": 0.2918},
     "mfma_counted_flops": {"fp32": 3459661824, "fp64": 3459661824},
 }
 # HBM bytes of one 3D p = 15 setup (4096 elements, every setup kernel) from
 # the same counter runs, valid for the setup sources they were taken on
 MEASURED_SETUP_TRAFFIC = {
-    "source_sha256": "83fe027658b1bc14e4ab70814fc3feef6198c5296fc02f51f8c8b37d31b57d12",
-    "bytes": 1846898941,
+    "source_sha256": "7a3e2d8fff56ddedf17f6dcc3534d32761f88f9aa68f2ce9cb7004bd779cb8c2",
+    "bytes": 1846912967,
 }
 
 

@@ -123,11 +123,7 @@ kp_status kp_set_stream(kp_ctx ctx, void* stream);
  *     last cycle's steps after that column run without effect.  A cycle that
  *     cannot be captured runs without graphs.
  *   KP_OPT_APPLY_MFMA16 (default 1): the matrix-core apply for n = 16; 0
- *     selects the generic per-element kernel; 2 keeps the matrix cores but
- *     runs 2D batches on the LDS-resident kernel (tensor in LDS) instead of
- *     the register-resident one (the same operations, rounded in another
- *     order: the two L products are applied y first in the register kernel).
- *     Other values: KP_ERR_ARG.
+ *     selects the generic per-element kernel.
  *   KP_OPT_FGMRES_Z32 (default 1): kp_fgmres keeps the preconditioned basis
  *     Z in FP32 when the preconditioner is the rank-2 KSVD apply in FP32,
  *     BF16 or split BF16 (kp_apply_z32); its outputs are FP32 numbers, so

@@ -29,9 +29,6 @@ struct kp_ctx_s {
     // matrix-core apply for n = 16 (KP_APPLY_GENERIC=1 in the environment selects
     // the generic per-element kernel instead, for comparison)
     bool use_mfma16 = true;
-    // 2D n = 16: the LDS-resident kernel instead of the register-resident one
-    // (KP_OPT_APPLY_MFMA16 = 2)
-    bool apply16_lds2d = false;
     // learned setup: MLP workspace and the model attached with kp_set_model
     void* mw = nullptr;
     size_t mw_bytes = 0;

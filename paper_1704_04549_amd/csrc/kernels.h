@@ -66,34 +66,28 @@ hipError_t launch_apply_rank3(hipStream_t s, int prec, int64_t E, int n, int nrh
 // 2D rank 3 with n = 16 on the matrix cores (apply_mfma.hip): the Neumann
 // series of P2^{-1} (A3 (x) B3) over the rank-2 apply, 16 right-hand sides per
 // workgroup; flags[e] (int8, zeroed by the caller) is set for an element whose
-// series did not converge, for launch_apply_rank3 with only = flags; lds2d:
-// the LDS-resident kernel instead of the register-resident one.
+// series did not converge, for launch_apply_rank3 with only = flags.
 hipError_t launch_apply16_rank3(hipStream_t s, int prec, int64_t E, int nrhs, const void* tabs,
-                                int64_t tab_stride, const void* frags, const int8_t* kinds,
-                                const double* factors, const double* r, double* z, int8_t* flags,
-                                bool lds2d = false);
+                                int64_t tab_stride, const int8_t* kinds, const double* factors, const double* r,
+                                double* z, int8_t* flags);
 hipError_t launch_cast_tables(hipStream_t s, int64_t count, const double* t64, float* t32,
                               uint16_t* hi, uint16_t* lo, float* t2);
-hipError_t launch_frag_tables(hipStream_t s, int64_t E, const double* t64, double* f64f, float* f32f,
-                              uint16_t* fbf, uint16_t* fbf3);
 // n = 16 matrix-core apply (apply_mfma.hip); grid cap of its persistent loop.
-// tabs: row-major tables of the precision (T2 is read from them); frags: the
-// fragment-ordered copy of the same precision.
+// tabs: row-major tables of the precision.
 constexpr int64_t kApply16Grid = 1 << 20;
 // axes: the 3D elements' split axes (kp_setup with KP_OPT_SPLIT_AXIS), or NULL
-// (every element split on x); lds2d: 2D runs the LDS-resident kernel (tensor
-// in LDS, fragment-ordered tables) instead of the register-resident one
+// (every element split on x)
 hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
-                          int64_t tab_stride, const void* frags, const int8_t* kinds,
-                          const double* r, double* z, const int8_t* axes = nullptr, bool lds2d = false);
+                          int64_t tab_stride, const int8_t* kinds, const double* r, double* z,
+                          const int8_t* axes = nullptr);
 hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
                                 const void* tabs, int64_t tab_stride, const int8_t* kinds,
                                 const double* r, double* z, const int8_t* axes = nullptr);
 // the same two with z stored in FP32 (prec FP32, BF16, split BF16 only: their
 // results are FP32 numbers, stored exactly; prec FP64 is refused)
 hipError_t launch_apply16(hipStream_t s, int prec, int64_t E, int dim, int nrhs, const void* tabs,
-                          int64_t tab_stride, const void* frags, const int8_t* kinds,
-                          const double* r, float* z, const int8_t* axes = nullptr, bool lds2d = false);
+                          int64_t tab_stride, const int8_t* kinds, const double* r, float* z,
+                          const int8_t* axes = nullptr);
 hipError_t launch_apply_generic(hipStream_t s, int prec, int64_t E, int dim, int n, int nrhs,
                                 const void* tabs, int64_t tab_stride, const int8_t* kinds,
                                 const double* r, float* z, const int8_t* axes = nullptr);

@@ -859,43 +859,6 @@ hipError_t launch_form_tables_list(hipStream_t s, int64_t count, const int32_t* 
     return form_tables(s, count, dim, n, 2, factors, tab64, kinds, status, TabAddr{list, el, 0, 0});
 }
 
-// fragment-ordered copies of the n = 16 tables for the matrix-core apply:
-// one thread per (element, matrix, lane)
-__global__ void k_frag_tables(int64_t E, const double* t64, double* f64f, float* f32f, uint16_t* fbf,
-                              uint16_t* fbf3) {
-    const int64_t count = E * 23 * 64;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < count;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int l = (int)(q % 64);
-        const int64_t em = q / 64;  // element * 23 + matrix
-        const int g = l >> 4, c = l & 15;
-        const double* M = t64 + em * 256;
-        for (int k = 0; k < 4; ++k) {
-            const double v = M[c * 16 + 4 * k + g];
-            f64f[q * 4 + k] = v;
-            f32f[q * 4 + k] = (float)v;
-        }
-        const int64_t e = em / 23, m = em % 23;
-        for (int i = 0; i < 4; ++i) {
-            const float f = (float)M[c * 16 + 4 * g + i];
-            const uint16_t h = f32_to_bf16(f);
-            fbf[q * 4 + i] = h;
-            fbf3[((e * 23 + m) * 2 + 0) * 256 + l * 4 + i] = h;
-            fbf3[((e * 23 + m) * 2 + 1) * 256 + l * 4 + i] = f32_to_bf16(f - bf16_to_f32(h));
-        }
-    }
-}
-
-hipError_t launch_frag_tables(hipStream_t s, int64_t E, const double* t64, double* f64f, float* f32f,
-                              uint16_t* fbf, uint16_t* fbf3) {
-    const int64_t count = E * 23 * 64;
-    int grid = (int)((count + 255) / 256);
-    if (grid > 65536) grid = 65536;
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_frag_tables, dim3(grid), dim3(256), 0, s, E, t64, f64f, f32f, fbf, fbf3);
-    return hipGetLastError();
-}
-
 hipError_t launch_cast_tables(hipStream_t s, int64_t count, const double* t64, float* t32,
                               uint16_t* hi, uint16_t* lo, float* t2) {
     int grid = (int)((count + 255) / 256);

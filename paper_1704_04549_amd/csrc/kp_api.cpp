@@ -121,11 +121,7 @@ kp_status kp_set_option(kp_ctx c, int32_t option, int64_t value) {
     if (!c) return KP_ERR_ARG;
     switch (option) {
         case KP_OPT_FGMRES_GRAPHS: c->use_graphs = value != 0; return KP_OK;
-        case KP_OPT_APPLY_MFMA16:
-            if (value < 0 || value > 2) return KP_ERR_ARG;
-            c->use_mfma16 = value != 0;
-            c->apply16_lds2d = value == 2;
-            return KP_OK;
+        case KP_OPT_APPLY_MFMA16: c->use_mfma16 = value != 0; return KP_OK;
         case KP_OPT_FGMRES_Z32: c->fgmres_z32 = value != 0; return KP_OK;
         case KP_OPT_OPERATOR_COLS: c->op_cols = value != 0; return KP_OK;
         case KP_OPT_SPLIT_AXIS: c->split_axis = value != 0; return KP_OK;
@@ -170,10 +166,6 @@ static kp_status finish_tables(kp_ctx c, const kp_batch* b, int rank, char* pc, 
     KP_HIP(launch_cast_tables(c->stream, E * L.ne, (const double*)(pc + L.t64), (float*)(pc + L.t32),
                               (uint16_t*)(pc + L.thi), (uint16_t*)(pc + L.tlo),
                               (float*)(pc + L.t2)));
-    if (b->n == 16 && b->dim == 2)
-        KP_HIP(launch_frag_tables(c->stream, E, (const double*)(pc + L.t64), (double*)(pc + L.f64f),
-                                  (float*)(pc + L.f32f), (uint16_t*)(pc + L.fbf),
-                                  (uint16_t*)(pc + L.fbf3)));
     return KP_OK;
 }
 
@@ -478,25 +470,16 @@ static kp_status apply_impl(kp_ctx c, const kp_batch* b, int32_t rank, const voi
                 // GMRES for the elements it flags
                 if ((st = ensure_ws(c, (size_t)E, &c->ws, &c->ws_bytes)) != KP_OK) return st;
                 int8_t* flags = (int8_t*)c->ws;
-                const void* frags = prec == KP_FP64   ? (const void*)(pc + L.f64f)
-                                    : prec == KP_FP32 ? (const void*)(pc + L.f32f)
-                                    : prec == KP_BF16 ? (const void*)(pc + L.fbf)
-                                                      : (const void*)(pc + L.fbf3);
                 KP_HIP(launch_fill_i8(c->stream, E, flags, 0));
-                KP_HIP(launch_apply16_rank3(c->stream, prec, E, nrhs, tabs, L.ne, frags, kd, fac, r, z, flags,
-                                                c->apply16_lds2d));
+                KP_HIP(launch_apply16_rank3(c->stream, prec, E, nrhs, tabs, L.ne, kd, fac, r, z, flags));
                 KP_HIP(launch_apply_rank3(c->stream, prec, E, b->n, nrhs, fac, tabs, L.ne, kd, r, z, flags));
             } else {
                 KP_HIP(launch_apply_rank3(c->stream, prec, E, b->n, nrhs, fac, tabs, L.ne, kd, r, z));
             }
         }
     } else if (b->n == 16 && c->use_mfma16) {
-        const void* frags = prec == KP_FP64   ? (const void*)(pc + L.f64f)
-                            : prec == KP_FP32 ? (const void*)(pc + L.f32f)
-                            : prec == KP_BF16 ? (const void*)(pc + L.fbf)
-                                              : (const void*)(pc + L.fbf3);
-        KP_HIP(launch_apply16(c->stream, prec, E, b->dim, nrhs, tabs, L.ne, frags,
-                              (const int8_t*)(pc + L.kinds), r, z, axes, c->apply16_lds2d));
+        KP_HIP(launch_apply16(c->stream, prec, E, b->dim, nrhs, tabs, L.ne, (const int8_t*)(pc + L.kinds), r, z,
+                              axes));
     } else if (b->dim == 3 && b->n <= 8 && c->use_small3) {
         KP_HIP(launch_apply_small3(c->stream, prec, E, b->n, nrhs, tabs, L.ne, (const int8_t*)(pc + L.kinds), r, z,
                                    axes));

@@ -11,13 +11,6 @@
 //   thi     [E][ne]           bf16    high part of the split bf16 tables
 //   tlo     [E][ne]           bf16    low part
 //   t2      [E][ne]           float   thi + tlo as float
-//   2D with n = 16 only, the same 23 matrices in matrix-core fragment order
-//   (lane l = 16 g + c holds the four A-side entries it feeds to the MFMA;
-//   the 3D apply reads its fragments from the row-major tables):
-//   f64f    [E][23][64][4]    double  M[c][4k + g], k = 0..3
-//   f32f    [E][23][64][4]    float   M[c][4k + g]
-//   fbf     [E][23][64][4]    bf16    M[c][4g + i], i = 0..3   (bf16 of thi)
-//   fbf3    [E][23][2][64][4] bf16    hi and lo parts, same order as fbf
 #pragma once
 
 #include <stddef.h>
@@ -28,7 +21,7 @@
 namespace kp {
 
 struct PcLayout {
-    size_t sigma, factors, status, kinds, axis, t64, t32, thi, tlo, t2, f64f, f32f, fbf, fbf3, total;
+    size_t sigma, factors, status, kinds, axis, t64, t32, thi, tlo, t2, total;
     long nf, ne;
 };
 
@@ -58,11 +51,6 @@ inline bool pc_layout(int dim, int n, int rank, int64_t E, PcLayout* L) {
     L->thi = off; off = align256(off + E * L->ne * sizeof(uint16_t));
     L->tlo = off; off = align256(off + E * L->ne * sizeof(uint16_t));
     L->t2 = off; off = align256(off + E * L->ne * sizeof(float));
-    const size_t nfrag = (n == 16 && dim == 2) ? (size_t)E * L->ne : 0;  // 23 * 256 entries per element
-    L->f64f = off; off = align256(off + nfrag * sizeof(double));
-    L->f32f = off; off = align256(off + nfrag * sizeof(float));
-    L->fbf = off; off = align256(off + nfrag * sizeof(uint16_t));
-    L->fbf3 = off; off = align256(off + 2 * nfrag * sizeof(uint16_t));
     L->total = off;
     return true;
 }

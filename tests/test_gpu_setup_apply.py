@@ -168,7 +168,7 @@ def test_more_elements_than_setup_grid(ctx):
 def test_mfma16_apply_matches_generic_and_oracle(ctx, dim, nrhs, monkeypatch):
     """The n = 16 matrix-core apply against the generic kernel and the oracle, all precisions
     (2D with 20 right-hand sides exercises a ragged second group of slices, with one a group
-    of one).  2D also runs the LDS-resident kernel (KP_OPT_APPLY_MFMA16 = 2) to the same bars."""
+    of one)."""
     from paper_1704_04549_amd import kp
     from tests.gpu_util import batch, rel, to_dev
     n, E = 16, 12
@@ -186,16 +186,10 @@ def test_mfma16_apply_matches_generic_and_oracle(ctx, dim, nrhs, monkeypatch):
     for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5), ("bf16", 2e-2), ("bf16x3", 1e-4)):
         zm = ctx.apply(b, 2, pc, prec, rd)
         zg = gctx.apply(b, 2, pc, prec, rd)
-        el = 0.0
-        if dim == 2:
-            ctx.set_option(kp.KP_OPT_APPLY_MFMA16, 2)
-            zl = ctx.apply(b, 2, pc, prec, rd)
-            ctx.set_option(kp.KP_OPT_APPLY_MFMA16, 1)
-            el = rel(zl.cpu().numpy(), zref)
         torch.cuda.synchronize()
         em, eg = rel(zm.cpu().numpy(), zref), rel(zg.cpu().numpy(), zref)
-        print(f"  {prec}: mfma {em:.2e} generic {eg:.2e} lds {el:.2e}", flush=True)
-        assert em <= tol and eg <= tol and el <= tol
+        print(f"  {prec}: mfma {em:.2e} generic {eg:.2e}", flush=True)
+        assert em <= tol and eg <= tol
     gctx.close()
 
 
