@@ -813,10 +813,15 @@ static hipError_t launch16r2_rank3(hipStream_t st, int64_t E, int nrhs, const vo
 hipError_t launch_apply16_rank3(hipStream_t s, int prec, int64_t E, int nrhs, const void* tabs,
                                 int64_t tab_stride, const int8_t* kinds, const double* factors, const double* r,
                                 double* z, int8_t* flags) {
-    // term limits: a spectral radius up to about 0.88 still converges within them
+    // term limits: FP64 96 and FP32 48 terms converge for a spectral radius up
+    // to about 0.72 (slower elements go to the GMRES path); measured at 2D
+    // p = 15, 8 RHS, against the 256 and 128 terms that admit 0.88: FP64
+    // 17.6 -> 16.6 ms, FP32 4.10 -> 3.64 ms, since the few slow work items no
+    // longer hold the launch's tail (fewer terms cost more in the fallback:
+    // FP64 at 48 terms 17.9 ms, FP32 at 32 3.9 ms); the BF16 forms admit 0.9
     switch (prec) {
-        case 0: return launch16r2_rank3<PolF64, 2>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 256, 1e-14, flags);
-        case 1: return launch16r2_rank3<PolF32, 4>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 128, 2e-7, flags);
+        case 0: return launch16r2_rank3<PolF64, 2>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 96, 1e-14, flags);
+        case 1: return launch16r2_rank3<PolF32, 4>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 48, 2e-7, flags);
         case 2: return launch16r2_rank3<PolBF16, 4>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 64, 2e-3, flags);
         default:
             return launch16r2_rank3<PolBF16X3, 3>(s, E, nrhs, tabs, tab_stride, kinds, factors, r, z, 96, 5e-6, flags);
