@@ -74,20 +74,25 @@ def test_c2_full_rank3_sampled(ctx):
     pc, st = ctx.setup(b, 3)
     _, s_gpu = ctx.get_factors(b, 3, pc)
     rd = to_dev(w["rhs"])
-    z = ctx.apply(b, 3, pc, "fp64", rd)
+    zs = {p: ctx.apply(b, 3, pc, p, rd) for p in ("fp64", "fp32", "bf16", "bf16x3")}
     torch.cuda.synchronize()
     assert int((st != 0).sum()) == 0
     s_gpu = s_gpu.cpu().numpy()
-    z = z.cpu().numpy()
+    zs = {p: z.cpu().numpy() for p, z in zs.items()}
     T = tables(n)
     for e in (1, 9000, E - 2):
         fo = ksvd2d(element_block(w["params"][e], n, dim, T), n, 3)
         assert np.max(np.abs(s_gpu[e, :3] / fo["sigma"][:3] - 1)) <= 1e-12, e
         zref = dense_solve(fo, w["rhs"][e])
         kap = np.linalg.cond(precond_matrix(fo))
-        err = rel(z[e], zref)
+        err = rel(zs["fp64"][e], zref)
         print(f"  e={e}: {err:.2e} (kappa {kap:.1e})", flush=True)
         assert err <= max(1e-11, 100 * kap * EPS), e
+        # the reduced-precision series, to the rank-2 full-size bars
+        for p, tol in (("fp32", 1e-4), ("bf16", 5e-2), ("bf16x3", 1e-3)):
+            err = rel(zs[p][e], zref)
+            print(f"  e={e} {p}: {err:.2e}", flush=True)
+            assert err <= tol, (e, p, err)
 
 
 def test_c3_full_sampled_and_fgmres(ctx):
