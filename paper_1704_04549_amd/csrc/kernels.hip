@@ -246,35 +246,36 @@ __device__ bool invert4(int n, const double* Aq, double* Aiq, double* slot) {
     return invert_grp<16>(n, Aq, Aiq, slot);
 }
 
-// Inverse of an upper quasi-triangular n x n matrix X (n <= 16; a 2 x 2
+// Inverse of an upper quasi-triangular n x n matrix X (n <= G; a 2 x 2
 // diagonal block wherever the subdiagonal entry is nonzero) by back
-// substitution, one column per lane of the 16-lane group: lane c solves
+// substitution, one column per lane of the G-lane group: lane c solves
 // X y = e_c from the last row up (a 2 x 2 block by Cramer's rule) with y in
 // registers and X's rows read from LDS.  Xi (may alias X; every read of X
 // precedes the first write) receives the inverse.  Returns false when a
 // column is not finite (a singular diagonal block); null X: the group idles.
-__device__ __forceinline__ bool qtri_inverse16(int n, const double* X, double* Xi) {
-    const int c = (int)(threadIdx.x & 15);
+template <int G>
+__device__ __forceinline__ bool qtri_inverse(int n, const double* X, double* Xi) {
+    const int c = (int)(threadIdx.x % G);
     const bool act = X != nullptr && c < n;
-    double y[16];
+    double y[G];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) y[i] = 0.0;
+    for (int i = 0; i < G; ++i) y[i] = 0.0;
     bool below = false;  // row i + 1 closed a 2 x 2 block that solved row i too
 #pragma unroll
-    for (int i = 15; i >= 0; --i) {
+    for (int i = G - 1; i >= 0; --i) {
         if (act && i < n) {
             if (below) {
                 below = false;
             } else {
                 double r = i == c ? 1.0 : 0.0;
 #pragma unroll
-                for (int k = i + 1; k < 16; ++k)
+                for (int k = i + 1; k < G; ++k)
                     if (k < n) r -= X[i * n + k] * y[k];
                 const int i1 = i > 0 ? i - 1 : 0;  // the row above (i > 0 below)
                 if (i > 0 && X[i * n + i1] != 0.0) {
                     double r1 = i1 == c ? 1.0 : 0.0;
 #pragma unroll
-                    for (int k = i + 1; k < 16; ++k)
+                    for (int k = i + 1; k < G; ++k)
                         if (k < n) r1 -= X[i1 * n + k] * y[k];
                     const double a = X[i1 * n + i1], b = X[i1 * n + i];
                     const double d = X[i * n + i1], e = X[i * n + i];
@@ -290,15 +291,15 @@ __device__ __forceinline__ bool qtri_inverse16(int n, const double* X, double* X
     }
     double bad = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
+    for (int k = 0; k < G; ++k)
         if (!(fabs(y[k]) < 1e300)) bad = 1.0;
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) bad = fmax(bad, __shfl_xor(bad, off, 16));
+    for (int off = G / 2; off > 0; off >>= 1) bad = fmax(bad, __shfl_xor(bad, off, G));
     WaveTeam wt;
     wt.sync();  // every read of X precedes any write of Xi
     if (act)
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
+        for (int k = 0; k < G; ++k)
             if (k < n) Xi[k * n + c] = y[k];
     wt.sync();
     return bad == 0.0 || X == nullptr;
@@ -562,7 +563,7 @@ __global__ void __launch_bounds__(256) k_tables_finish4(int64_t E, int dim, int 
             const int q = lane >> 4, jq = wv + 4 * q;
             double* Xq = (jq < n && kd[jq] != 1) ? In + q * nn : nullptr;
             // upper quasi-triangular (T1's block structure): back substitution
-            if (!qtri_inverse16(n, Xq, Xq) && (lane & 15) == 0) fail[wv] = 1;
+            if (!qtri_inverse<16>(n, Xq, Xq) && (lane & 15) == 0) fail[wv] = 1;
             for (int qq = 0; qq < 4; ++qq) {
                 const int j = wv + 4 * qq;
                 if (j >= n || kd[j] == 1) continue;
@@ -595,7 +596,7 @@ __global__ void __launch_bounds__(256) k_tables_finish4(int64_t E, int dim, int 
             }
             const int q = lane >> 5, jq = wv + 8 * h + 4 * q;
             double* Xq = (jq < n && kd[jq] != 1) ? Wv + q * nn : nullptr;
-            if (!invert_grp<32>(n, Xq, Xq, gslot[wv]) && (lane & 31) == 0) fail[wv] = 1;
+            if (!qtri_inverse<32>(n, Xq, Xq) && (lane & 31) == 0) fail[wv] = 1;
             for (int qq = 0; qq < 2; ++qq) {
                 const int j = wv + 8 * h + 4 * qq;
                 if (j >= n || kd[j] == 1) continue;
