@@ -182,7 +182,7 @@ MEASURED_TRAFFIC = {
 # HBM bytes of one 3D p = 15 setup (4096 elements, every setup kernel) from
 # the same counter runs, valid for the setup sources they were taken on
 MEASURED_SETUP_TRAFFIC = {
-    "source_sha256": "4aef05ebf66cffe6bc22a0330507af5c432a2e38424bd817aae43527ad33b4d4",
+    "source_sha256": "4deefb91dc0c35166b8baef310b10a1731c9acc3307a6c69ecc7432a7b583a89",
     "bytes": 1852360880,
 }
 

@@ -321,10 +321,13 @@ __device__ double norm1_group(int n, const double* M) {
 // Four-wave variants of prepare and finish (256 threads per element): the
 // independent pieces of the work run on separate waves, each with its own
 // LDS scratch, with the arithmetic of the one-wave kernels (the angle search
-// compares the same scores with the same tie rule).  The inversions
-// run in registers, four at a time per wave for n <= 16 and two for n > 16
-// (invert_grp: the same operations per entry; its pivot order can differ from
-// invert()'s only on exact ties).
+// compares the same scores with the same tie rule), except for the column
+// inverses N_j.  The inversions run in registers, four at a time per wave
+// for n <= 16 and two for n > 16: the factor inverses by invert_grp (the same
+// operations per entry as invert(); its pivot order can differ only on exact
+// ties), the N_j, whose inputs are upper quasi-triangular, by qtri_inverse
+// (back substitution; equal to the one-wave kernel's Gauss-Jordan inverse
+// to rounding).
 //   prepare: wave w scores the rotation angles k = w and w + 4; the inverses
 //            are formed by wave 0 (n <= 16) or waves 0..2; waves 0, 1 form
 //            C1, C2.
